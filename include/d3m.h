@@ -1,0 +1,214 @@
+/* d3m.h -- C ABI of the D3M dual factorization and solution library for
+ * AMD MI355X (gfx950).
+ *
+ * What it computes (Sec. II of Moshfegh, Makris, Vouvakis, "Parallel Direct
+ * Domain Decomposition Methods (D3M) for Finite Elements", 2019): the
+ * reduced matrix K of D3M is block-wise sparse; its dense blocks couple the
+ * interfaces between domains (Fig. 1(b)).  The dual step factors K with a
+ * block LDL^T -- per nonzero block a dense factorization, dense triangular
+ * solves and dense updates, arranged as a task DAG built by simulating the
+ * sequential algorithm (Sec. II, Fig. 1(c)) -- and then solves with the
+ * factors.  Here K is complex symmetric (K = K^T, transposes are never
+ * conjugated), factored without pivoting as P K P^T = L D L^T with L unit
+ * lower triangular and D diagonal, P the block permutation of the
+ * elimination order (nested dissection over the domain grid, or a given
+ * order).
+ *
+ * Layouts (all complex numbers interleaved re,im; "c128" = 2 x double):
+ *   K     one flat device buffer: for each interface I (user numbering) the
+ *         full n_I x n_I diagonal block, column-major, of which only the
+ *         lower triangle is read; then for each pair (I,J), I > J, in the
+ *         order given to d3m_analyze, the n_I x n_J block K_IJ, column-major.
+ *         K_JI = K_IJ^T is implied.  Offsets: d3m_plan_k_offsets.
+ *   B, X  nrhs right-hand sides / solutions, RHS j at ptr + j*ld, each an
+ *         N-vector in user row numbering (rows of interface 0 first).
+ *   dK    same layout as K (full diagonal blocks are written).
+ *
+ * Ownership: the caller owns every device buffer (K, B, X, G, Lambda, dK and
+ * the workspace).  The library allocates no device memory: everything it
+ * needs lives in the workspace handed to d3m_factor_bind.  K must stay alive
+ * and unchanged between d3m_factorize and the last d3m_solve/d3m_adjoint,
+ * because refinement residuals read it.  Plans and factors own host memory
+ * only and free it in their destroy calls.
+ *
+ * Errors: negative codes are caller or runtime errors and are detected on
+ * the host before anything is enqueued.  Positive codes are numerical
+ * outcomes written by the device and reported by d3m_status_sync (LAPACK
+ * info style); they never abort the stream.
+ *
+ * Streams: factorize/solve/adjoint/batch_run enqueue on the given stream and
+ * neither allocate, synchronize nor call back to the host (unless
+ * d3m_options.ir_host_sync is set), so they can be captured in a hipGraph.
+ * Calls on one factor must not overlap in time.
+ */
+#ifndef D3M_H
+#define D3M_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct d3m_plan_s* d3m_plan;     /* host symbolic: pattern, order, fill, DAG */
+typedef struct d3m_factor_s* d3m_factor; /* numeric factor bound to a workspace      */
+typedef struct d3m_batch_s* d3m_batch;   /* many factors, one persistent launch      */
+typedef void* d3m_stream;                /* a hipStream_t (NULL = default stream)    */
+
+typedef enum {
+  D3M_OK = 0,
+  D3M_ERR_ARG = -1,       /* null handle, bad size, bad pointer                      */
+  D3M_ERR_PATTERN = -2,   /* duplicate/self/out-of-range pair, order not a permutation */
+  D3M_ERR_WORKSPACE = -3, /* workspace too small or misaligned                        */
+  D3M_ERR_STATE = -4,     /* call out of sequence (solve before factorize, ...)       */
+  D3M_ERR_HIP = -5,       /* a HIP runtime call failed                                */
+  D3M_ERR_HANG = -6,      /* a dependency wait exceeded the watchdog bound           */
+  D3M_ERR_NORUNTIME = -7, /* no usable gfx950 device                                  */
+  D3M_ZERO_PIVOT = 1,     /* a pivot d_k was zero or not finite (row in run_info)     */
+  D3M_NONFINITE = 2,      /* a non-finite value in the solution or residual          */
+  D3M_IR_NOCONV = 3       /* refinement did not reach the tolerance                  */
+} d3m_status;
+
+typedef enum {
+  D3M_C128 = 0,   /* complex128 factor and solve                                    */
+  D3M_C64_IR = 1  /* complex64 factor (FP32 MFMA, FP32 accumulation) + FP64 refinement */
+} d3m_precision;
+
+/* Analysis options.  Zero-initialise for defaults. */
+typedef struct {
+  int32_t tile;      /* largest tile edge, a multiple of 16 in [16,128]; 0 -> 128 */
+  int32_t nworkers;  /* persistent workgroups assumed by the list scheduler; 0 -> 256 */
+  int32_t sched;     /* 0 = list scheduling by bottom level, 1 = plain sequential order */
+  int32_t reserved;
+} d3m_analyze_options;
+
+/* Numeric options.  Zero-initialise for defaults. */
+typedef struct {
+  double tol;           /* refinement target on eta_inf; 0 -> 1e-10                  */
+  int32_t max_iter;     /* refinement steps after x0; 0 -> 10                         */
+  int32_t ir_host_sync; /* 1: read eta back after every step and stop exactly        */
+  double growth_dmin;   /* FP32 fallback trigger: min|d| < growth_dmin * max|A_II|; 0 -> 1e-4 */
+  double growth_lmax;   /* FP32 fallback trigger: max|L| > growth_lmax; 0 -> 1e2      */
+  int32_t fallback;     /* 1 (default via 0): re-factor tripped blocks in FP64; -1 off */
+  int32_t reserved;
+} d3m_options;
+
+typedef struct {
+  int64_t N;            /* unknowns                                                  */
+  int64_t nblk, npair;  /* interfaces, stored off-diagonal blocks                       */
+  int64_t k_len;        /* complex elements of the K buffer                            */
+  int64_t fill_blocks;  /* blocks of L created by elimination                           */
+  int64_t L_blocks;     /* off-diagonal blocks of L                                     */
+  int64_t nnz_L;        /* lower-triangle entries of L (diagonal blocks counted as lower triangles) */
+  int64_t nnz_K;        /* lower-triangle entries of K                                  */
+  int64_t etree_height, max_S;
+  int64_t ntask_factor, ntask_solve, ntiles;
+  double flops_diag, flops_trsm, flops_update, flops_factor; /* 8 real flops per complex FMA */
+  double solve_flops_per_rhs;                                /* 16 * nnz_L                  */
+  double sim_factor_us; /* list-scheduler estimate of the factor makespan                 */
+} d3m_plan_info;
+
+typedef struct {
+  int32_t status;       /* a d3m_status                                              */
+  int32_t ir_iters;     /* refinement steps taken (0 for the FP64 path)               */
+  int64_t pivot_row;    /* user row of the first bad pivot, or -1                     */
+  double eta;           /* final max-over-columns normwise backward error             */
+  double eta_hist[32];  /* eta after x0 and after each refinement step                */
+  int32_t fallbacks;    /* diagonal blocks re-factored in FP64                        */
+  int32_t hang;         /* watchdog fired                                             */
+} d3m_run_info;
+
+/* Build the symbolic plan.
+ *   nblk, blk_size   interface count and sizes (all >= 1)
+ *   npair, pairs     2*npair ids, unordered, I != J, each pair once
+ *   order            nblk ids, the elimination order, or NULL
+ *   grid             3 ints (domain grid a x b x c whose interfaces, numbered
+ *                    axis 0 first then 1 then 2, lower domain x slowest, are
+ *                    the nblk interfaces) or NULL.  With order == NULL and a
+ *                    grid: nested dissection over the grid; with neither:
+ *                    greedy minimum degree on the block graph.
+ * The DAG of Sec. II (Fig. 1(c)) is built here by simulating the sequential
+ * elimination; tasks are ordered by a list scheduler (bottom-level priority). */
+d3m_status d3m_analyze(int32_t nblk, const int32_t* blk_size, int64_t npair, const int32_t* pairs,
+                       const int32_t* order, const int32_t* grid, const d3m_analyze_options* opt,
+                       d3m_plan* out);
+d3m_status d3m_plan_query(d3m_plan plan, d3m_plan_info* out);
+/* The elimination order (nblk user ids). */
+d3m_status d3m_plan_order(d3m_plan plan, int32_t* order);
+/* nblk + npair + 1 offsets (complex elements) of the K blocks. */
+d3m_status d3m_plan_k_offsets(d3m_plan plan, int64_t* offsets);
+/* S_I (later neighbours after fill, in elimination order) of user interface I;
+ * writes at most nblk ids and returns the count in *count. */
+d3m_status d3m_plan_struct(d3m_plan plan, int32_t I, int32_t* S, int32_t* count);
+/* Static check of the DAG on the CPU: every storage tile's writers are
+ * totally ordered and every reader is ordered after the writer it needs.
+ * Only for small plans (quadratic memory in the task count). */
+d3m_status d3m_plan_check(d3m_plan plan, int64_t* nviolations);
+void d3m_plan_destroy(d3m_plan plan);
+
+/* Workspace for one factor with up to nrhs_max right-hand sides per solve. */
+d3m_status d3m_workspace_bytes(d3m_plan plan, d3m_precision prec, int32_t nrhs_max, size_t* bytes);
+/* Bind a factor to a caller-owned device workspace (256-byte aligned) and
+ * upload its task tables (synchronous; not on the hot path). */
+d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size_t bytes,
+                           int32_t nrhs_max, const d3m_options* opt, d3m_factor* out);
+/* Factor K (c128 layout above) on the stream: scatter/convert, then one
+ * persistent launch of the elimination DAG. */
+d3m_status d3m_factorize(d3m_factor f, const void* dev_K, d3m_stream stream);
+/* X = K^{-1} B for nrhs <= nrhs_max columns.  D3M_C64_IR: FP32 solves with
+ * FP64 residuals r = B - K X on the original K and FP64 updates until
+ * eta_inf <= tol; D3M_C128: FP64 solve plus one certifying residual. */
+d3m_status d3m_solve(d3m_factor f, const void* dev_K, const void* dev_B, void* dev_X,
+                     int32_t nrhs, int64_t ld, d3m_stream stream);
+/* Adjoint with the same factors (K = K^T): Lambda = K^{-1} G and
+ * dK = -sym(Lambda X^T) on K's block pattern, summed over columns, with
+ * sym(A) = (A + A^T)/2 (holomorphic convention: for J = sum_k Re(c_k^T x_k)
+ * pass G = C).  X is the solution of the forward solve. */
+d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const void* dev_G,
+                       void* dev_Lambda, void* dev_dK, int32_t nrhs, int64_t ld, d3m_stream stream);
+/* Wait for the factor's last stream and report numerical outcomes. */
+d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out);
+/* Copy one factor block to host memory as c128, column-major: (J == I) the
+ * diagonal block of I (L strictly below the diagonal, D on it), otherwise
+ * L_JI (n_J x n_I) for J in S_I.  Synchronous; for tests and inspection. */
+d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out);
+void d3m_factor_destroy(d3m_factor f);
+
+/* Batching: many bound factors (their own plans and workspaces) run as one
+ * persistent launch per phase.  The batch keeps its merged task tables in
+ * dev_ws (size from d3m_batch_workspace_bytes). */
+d3m_status d3m_batch_workspace_bytes(int32_t ninst, const d3m_factor* f, size_t* bytes);
+d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, size_t bytes,
+                            d3m_batch* out);
+/* Factor and solve every instance: K[i], B[i], X[i] with nrhs[i] columns and
+ * leading dimension ld[i]. */
+d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B, void* const* X,
+                         const int32_t* nrhs, const int64_t* ld, d3m_stream stream);
+void d3m_batch_destroy(d3m_batch b);
+
+/* Device tuning: time each candidate tile configuration of the GEMM task
+ * body on the current device and return the fastest (id, measured GFLOP/s)
+ * for the precision. */
+d3m_status d3m_tune_gemm(d3m_precision prec, void* dev_scratch, size_t bytes, int32_t* best_id,
+                         double* gflops_out /* [ncand] or NULL */, int32_t* ncand);
+
+/* Diagnostics: one tile product of the library's MFMA engine on device data,
+ *   C(i,j) = alpha * sum_p A(i,p) d(p) B(j,p) + beta * C(i,j),
+ * i < m <= 128, j < n <= 128, p < k; complex128 (prec D3M_C128) or complex64
+ * (D3M_C64_IR) operands.  amode 0: A(i,p) = A[i + p*lda]; 1: A[i*lda + p];
+ * 2: symmetric block read from its lower triangle, A(i,p) = S(i0+i, p).
+ * B(j,p) = B[j + p*ldb]; C(i,j) = C[i + j*ldc]; d may be NULL.  Runs on
+ * the stream; for unit tests of the engine. */
+d3m_status d3m_debug_gemm(d3m_precision prec, int32_t m, int32_t n, int32_t k, int32_t amode, int32_t i0,
+                          const void* A, int64_t lda, const void* d, const void* B, int64_t ldb, void* C,
+                          int64_t ldc, double alpha, double beta, d3m_stream stream);
+
+const char* d3m_status_string(d3m_status s);
+/* 1 if the library was built with gfx950 device code and a device is present. */
+int32_t d3m_device_ok(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* D3M_H */

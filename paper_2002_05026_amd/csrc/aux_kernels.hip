@@ -1,0 +1,551 @@
+// Stream-ordered kernels around the DAG launches: scatter/convert of K into
+// panel storage, permutation of right-hand sides into elimination order,
+// the FP64 block-sparse residual r = b - K x with column norms, the norm of
+// K, refinement bookkeeping, precision conversion, and the gradient blocks
+// dK = -sym(Lambda X^T) on K's pattern.
+#include <hip/hip_runtime.h>
+
+#include "d3m_internal.h"
+#include "gemm_engine.h"
+#include "launch.h"
+
+namespace d3m {
+
+// ---------------------------------------------------------------- prepare
+__global__ void k_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ctrl, double tol, int max_iter) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    status[0] = 0x7fffffff;
+    status[1] = 0;
+    if (ctrl) {
+      ctrl->stop = 0;
+      ctrl->iters = 0;
+      ctrl->status = 0;
+      ctrl->it = 0;
+      ctrl->knorm = 0;
+      ctrl->tol = tol;
+      ctrl->max_iter = max_iter;
+      for (int k = 0; k < 32; ++k) ctrl->eta_hist[k] = -1.0;
+    }
+  }
+  for (; i < npanel; i += gridDim.x * blockDim.x) {
+    growth[2 * i] = __int_as_float(0x7f800000);
+    growth[2 * i + 1] = 0.f;
+  }
+}
+
+hipError_t launch_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ctrl, double tol, int max_iter,
+                          hipStream_t s) {
+  int blocks = (npanel + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, status, growth, npanel, ctrl, tol, max_iter);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scatter
+// blockIdx.y: block (K placements first, then fill blocks); 32x32 tiles of
+// the block are spread over blockIdx.x.  Transposed blocks go through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(const double2* K, typename Cplx<T>::type* L, const KPlaceDev* kp,
+                                                 int nkp, const KPlaceDev* fills, int nfill) {
+  typedef typename Cplx<T>::type C;
+  __shared__ double2 tileb[32][33];
+  const int b = blockIdx.y;
+  const bool fill = b >= nkp;
+  const KPlaceDev P = fill ? fills[b - nkp] : kp[b];
+  const int tr = (P.rows + 31) / 32, tc = (P.cols + 31) / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int t = blockIdx.x; t < tr * tc; t += gridDim.x) {
+    const int r0 = (t % tr) * 32, c0 = (t / tr) * 32;
+    if (fill) {
+      for (int cc = ty; cc < 32; cc += 8) {
+        int r = r0 + tx, c = c0 + cc;
+        if (r < P.rows && c < P.cols) {
+          C z;
+          z.x = 0;
+          z.y = 0;
+          L[P.dst + r + (int64_t)c * P.ld_dst] = z;
+        }
+      }
+    } else if (!P.trans) {
+      for (int cc = ty; cc < 32; cc += 8) {
+        int r = r0 + tx, c = c0 + cc;
+        if (r < P.rows && c < P.cols) {
+          double2 v = K[P.src + r + (int64_t)c * P.rows];
+          C o;
+          o.x = (T)v.x;
+          o.y = (T)v.y;
+          L[P.dst + r + (int64_t)c * P.ld_dst] = o;
+        }
+      }
+    } else {
+      // dst(r, c) = src[c + r * cols]: read src rows c contiguous
+      __syncthreads();
+      for (int rr = ty; rr < 32; rr += 8) {
+        int r = r0 + rr, c = c0 + tx;
+        if (r < P.rows && c < P.cols) tileb[rr][tx] = K[P.src + c + (int64_t)r * P.cols];
+      }
+      __syncthreads();
+      for (int cc = ty; cc < 32; cc += 8) {
+        int r = r0 + tx, c = c0 + cc;
+        if (r < P.rows && c < P.cols) {
+          double2 v = tileb[tx][cc];
+          C o;
+          o.x = (T)v.x;
+          o.y = (T)v.y;
+          L[P.dst + r + (int64_t)c * P.ld_dst] = o;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_scatter(const void* K, void* L, const KPlaceDev* kp, int nkp, const KPlaceDev* fills,
+                          int nfill, int prec, hipStream_t s) {
+  int nb = nkp + nfill;
+  if (nb == 0) return hipSuccess;
+  dim3 grid(32, nb);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_scatter<double>, grid, dim3(256), 0, s, (const double2*)K, (double2*)L, kp, nkp, fills, nfill);
+  else
+    hipLaunchKernelGGL(k_scatter<float>, grid, dim3(256), 0, s, (const double2*)K, (float2*)L, kp, nkp, fills, nfill);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- permutation
+template <typename T>
+__global__ void k_perm_in(const double2* B, int64_t ld, typename Cplx<T>::type* W, const int32_t* perm,
+                          int64_t N, int nrhs, const int32_t* skip) {
+  if (skip && *skip) return;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = N * nrhs;
+  for (; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = e / nrhs;
+    int j = (int)(e - q * nrhs);
+    double2 v = B[(int64_t)j * ld + perm[q]];
+    typename Cplx<T>::type o;
+    o.x = (T)v.x;
+    o.y = (T)v.y;
+    W[e] = o;
+  }
+}
+
+hipError_t launch_perm_in(const void* B, int64_t ld, void* W, int prec, const UserView& uv, int nrhs,
+                          const int32_t* skip, hipStream_t s) {
+  int64_t tot = uv.N * nrhs;
+  int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_perm_in<double>, dim3(blocks), dim3(256), 0, s, (const double2*)B, ld, (double2*)W, uv.perm, uv.N, nrhs, skip);
+  else
+    hipLaunchKernelGGL(k_perm_in<float>, dim3(blocks), dim3(256), 0, s, (const double2*)B, ld, (float2*)W, uv.perm, uv.N, nrhs, skip);
+  return hipGetLastError();
+}
+
+__global__ void k_perm_out(const double2* W, double2* X, int64_t ld, const int32_t* perm, int64_t N, int nrhs) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = N * nrhs;
+  for (; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = e / nrhs;
+    int j = (int)(e - q * nrhs);
+    X[(int64_t)j * ld + perm[q]] = W[e];
+  }
+}
+
+hipError_t launch_perm_out(const void* W, void* X, int64_t ld, const UserView& uv, int nrhs, hipStream_t s) {
+  int64_t tot = uv.N * nrhs;
+  int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_perm_out, dim3(blocks), dim3(256), 0, s, (const double2*)W, (double2*)X, ld, uv.perm, uv.N, nrhs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- residual
+__device__ __forceinline__ void atomic_max_pos(double* p, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// R(internal rows of the tile) = B - K X; X, R internal, RHS fastest; B user
+// layout.  Column maxima of |r| go to colmax.
+__global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const double2* B, int64_t ld,
+                                                  const double2* X, double2* R, double* colmax, UserView uv,
+                                                  const RTaskDev* rt, int nrhs, const int32_t* skip) {
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double>()];
+  __shared__ unsigned long long cmax[GE_TN];
+  if (skip && *skip) return;
+  const RTaskDev t = rt[blockIdx.x];
+  const int I = t.I;
+  const int nI = uv.n[I];
+  Acc<double> acc;
+  acc.zero();
+  for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
+    const RBlkDev b = uv.rblk[e];
+    const int nJ = uv.n[b.J];
+    Opnd<double> A;
+    A.i0 = 0;
+    if (b.mode == 0) { A.p = K + b.koff; A.ld = nI; A.mode = OP_SYM; A.i0 = t.r0; }
+    else if (b.mode == 1) { A.p = K + b.koff + t.r0; A.ld = nI; A.mode = OP_N; }
+    else { A.p = K + b.koff + (int64_t)t.r0 * nJ; A.ld = nJ; A.mode = OP_T; }
+    Opnd<double> Bo;
+    Bo.p = X + uv.prow0[b.J] * nrhs;
+    Bo.ld = nrhs;
+    Bo.mode = OP_N;
+    Bo.i0 = 0;
+    gemm_acc<double>(acc, t.sz, nrhs, nJ, A, nullptr, Bo, lds);
+  }
+  if (threadIdx.x < GE_TN) cmax[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const double2* src = B + uv.row0[I] + t.r0;
+  double2* dst = R + (uv.prow0[I] + t.r0) * nrhs;
+  if (16 * w < t.sz) {
+#pragma unroll
+    for (int bj = 0; bj < 8; ++bj) {
+      const int j = 16 * bj + lr;
+      if (16 * bj >= nrhs) continue;
+      double mx = 0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + acc_row<double>(lk, v);
+        if (i < t.sz && j < nrhs) {
+          double2 s = src[i + (int64_t)j * ld];
+          double2 r;
+          r.x = s.x - acc.re[bj][v];
+          r.y = s.y - acc.im[bj][v];
+          dst[(int64_t)i * nrhs + j] = r;
+          double a = sqrt(r.x * r.x + r.y * r.y);
+          if (!(a == a)) a = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> inf
+          mx = fmax(mx, a);
+        }
+      }
+      if (j < nrhs) atomicMax(&cmax[j], (unsigned long long)__double_as_longlong(mx));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nrhs) atomic_max_pos(colmax + threadIdx.x, __longlong_as_double((long long)cmax[threadIdx.x]));
+}
+
+hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64,
+                           double* colmax, const UserView& uv, const RTaskDev* rt, int nrt, int nrhs,
+                           const int32_t* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(nrt), dim3(kThreads), 0, s, (const double2*)K, (const double2*)B, ld,
+                     (const double2*)X64, (double2*)R64, colmax, uv, rt, nrhs, skip);
+  return hipGetLastError();
+}
+
+// ||K||_inf: row sums of |k_ij| of the symmetric K, then the maximum.
+__global__ __launch_bounds__(256) void k_knorm(const double2* K, UserView uv, const RTaskDev* rt, IrCtrl* ctrl) {
+  const RTaskDev t = rt[blockIdx.x];
+  const int I = t.I, nI = uv.n[I];
+  __shared__ double rowsum[kTileMax];
+  for (int i = threadIdx.x; i < t.sz; i += 256) rowsum[i] = 0;
+  __syncthreads();
+  // one wave per row, lanes over columns
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = w; i < t.sz; i += 4) {
+    const int gi = t.r0 + i;
+    double s = 0;
+    for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
+      const RBlkDev b = uv.rblk[e];
+      const int nJ = uv.n[b.J];
+      for (int p = lane; p < nJ; p += 64) {
+        double2 v;
+        if (b.mode == 0) v = (gi >= p) ? K[b.koff + gi + (int64_t)p * nI] : K[b.koff + p + (int64_t)gi * nI];
+        else if (b.mode == 1) v = K[b.koff + gi + (int64_t)p * nI];
+        else v = K[b.koff + p + (int64_t)gi * nJ];
+        s += sqrt(v.x * v.x + v.y * v.y);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) rowsum[i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0;
+    for (int i = 0; i < t.sz; ++i) m = fmax(m, rowsum[i]);
+    atomic_max_pos(&ctrl->knorm, m);
+  }
+}
+
+hipError_t launch_knorm(const void* K, const UserView& uv, const RTaskDev* rt, int nrt, IrCtrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_knorm, dim3(nrt), dim3(256), 0, s, (const double2*)K, uv, rt, ctrl);
+  return hipGetLastError();
+}
+
+// Column maxima of |v| for a c128 array: rhs_fastest ? v[row*nrhs + j] : v[j*ld + row].
+__global__ void k_colmax(const double2* V, int64_t rows, int nrhs, int64_t ld, int rhs_fastest, double* colmax,
+                         const int32_t* skip) {
+  if (skip && *skip) return;
+  __shared__ unsigned long long cm[128];
+  if (threadIdx.x < 128) cm[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t tot = rows * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r;
+    int j;
+    double2 v;
+    if (rhs_fastest) { r = e / nrhs; j = (int)(e - r * nrhs); v = V[e]; }
+    else { j = (int)(e / rows); r = e - (int64_t)j * rows; v = V[(int64_t)j * ld + r]; }
+    double a = sqrt(v.x * v.x + v.y * v.y);
+    if (!(a == a)) a = __longlong_as_double(0x7ff0000000000000ll);
+    atomicMax(&cm[j], (unsigned long long)__double_as_longlong(a));
+  }
+  __syncthreads();
+  if (threadIdx.x < nrhs && cm[threadIdx.x]) atomic_max_pos(colmax + threadIdx.x, __longlong_as_double((long long)cm[threadIdx.x]));
+}
+
+hipError_t launch_colmax(const void* V, int64_t rows, int nrhs, int64_t ld, int rhs_fastest, double* colmax,
+                         const int32_t* skip, hipStream_t s) {
+  int64_t tot = rows * nrhs;
+  int blocks = (int)std::min<int64_t>((tot + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_colmax, dim3(blocks), dim3(256), 0, s, (const double2*)V, rows, nrhs, ld, rhs_fastest, colmax, skip);
+  return hipGetLastError();
+}
+
+// eta_j = rmax_j / (||K|| xmax_j + bmax_j); record max_j eta_j; decide.
+__global__ void k_ir_check(IrCtrl* c, double* rmax, double* xmax, const double* bmax, int nrhs, int final_step) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (c->stop) return;
+  double eta = 0;
+  bool nonfinite = false;
+  for (int j = 0; j < nrhs; ++j) {
+    double den = c->knorm * xmax[j] + bmax[j];
+    double e = den > 0 ? rmax[j] / den : rmax[j];
+    if (!(e <= 1e300)) nonfinite = true;
+    eta = fmax(eta, e);
+    rmax[j] = 0;
+    xmax[j] = 0;
+  }
+  const int it = c->it;
+  if (it < 32) c->eta_hist[it] = eta;
+  c->it = it + 1;
+  if (nonfinite) {
+    c->status = 2;  // D3M_NONFINITE
+    c->stop = 1;
+  } else if (eta <= c->tol || final_step == 2) {
+    c->stop = 1;
+  } else if (final_step || it >= c->max_iter) {
+    c->status = 3;  // D3M_IR_NOCONV
+    c->stop = 1;
+  } else if (it >= 2 && it < 32 && c->eta_hist[it - 2] >= 0 && eta > 0.5 * c->eta_hist[it - 2]) {
+    c->status = 3;  // stagnation
+    c->stop = 1;
+  } else {
+    c->iters = it + 1;
+  }
+}
+
+__global__ void k_ir_reset(IrCtrl* c, double tol, int max_iter) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  c->stop = 0;
+  c->iters = 0;
+  c->status = 0;
+  c->it = 0;
+  c->tol = tol;
+  c->max_iter = max_iter;
+  for (int k = 0; k < 32; ++k) c->eta_hist[k] = -1.0;
+}
+
+hipError_t launch_ir_reset(IrCtrl* ctrl, double tol, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_reset, dim3(1), dim3(64), 0, s, ctrl, tol, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_check(IrCtrl* ctrl, double* rmax, double* xmax, const double* bmax, int nrhs,
+                           int final_step, hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(64), 0, s, ctrl, rmax, xmax, bmax, nrhs, final_step);
+  return hipGetLastError();
+}
+
+__global__ void k_cvt_down(const double2* R, float2* W, int64_t n, const int32_t* skip) {
+  if (skip && *skip) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double2 v = R[e];
+    W[e] = make_float2((float)v.x, (float)v.y);
+  }
+}
+__global__ void k_cvt_up(const float2* W, double2* X, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    float2 v = W[e];
+    X[e] = make_double2(v.x, v.y);
+  }
+}
+__global__ void k_axpy_up(const float2* W, double2* X, int64_t n, const int32_t* skip) {
+  if (skip && *skip) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    float2 v = W[e];
+    double2 x = X[e];
+    x.x += v.x;
+    x.y += v.y;
+    X[e] = x;
+  }
+}
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+hipError_t launch_cvt_down(const void* R64, void* W32, int64_t n, const int32_t* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_cvt_down, dim3(grid_for(n)), dim3(256), 0, s, (const double2*)R64, (float2*)W32, n, skip);
+  return hipGetLastError();
+}
+hipError_t launch_cvt_up(const void* W32, void* X64, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cvt_up, dim3(grid_for(n)), dim3(256), 0, s, (const float2*)W32, (double2*)X64, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpy_up(const void* W32, void* X64, int64_t n, const int32_t* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_up, dim3(grid_for(n)), dim3(256), 0, s, (const float2*)W32, (double2*)X64, n, skip);
+  return hipGetLastError();
+}
+__global__ void k_zero_f64(double* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dK
+// dK(I,J) tile = -1/2 sum_k (lam_I x_J^T + x_I lam_J^T); user layout vectors.
+__global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const double2* X, int64_t ld, int nrhs, double2* dK,
+                                            UserView uv, const DkTaskDev* dt) {
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double>()];
+  const DkTaskDev t = dt[blockIdx.x];
+  const int64_t ri = uv.row0[t.I] + t.r0, rj = uv.row0[t.J] + t.c0;
+  Acc<double> acc;
+  acc.zero();
+  Opnd<double> A, B;
+  A.mode = B.mode = OP_N;
+  A.i0 = B.i0 = 0;
+  A.ld = B.ld = ld;
+  A.p = Lam + ri;
+  B.p = X + rj;
+  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, lds);
+  A.p = X + ri;
+  B.p = Lam + rj;
+  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, lds);
+  Out<double> o;
+  const int nI = uv.n[t.I];
+  o.dst = dK + t.koff + t.r0 + (int64_t)t.c0 * nI;
+  o.rs = 1;
+  o.cs = nI;
+  o.src = nullptr;
+  o.srs = o.scs = 0;
+  o.alpha = -0.5;
+  o.beta = 0;
+  o.rowdiv = o.coldiv = nullptr;
+  gemm_store<double>(acc, t.m, t.n, o);
+}
+
+hipError_t launch_dk(const void* Lam, const void* X, int64_t ld, int nrhs, void* dK, const UserView& uv,
+                     const DkTaskDev* dt, int ndt, hipStream_t s) {
+  if (ndt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dk, dim3(ndt), dim3(kThreads), 0, s, (const double2*)Lam, (const double2*)X, ld, nrhs,
+                     (double2*)dK, uv, dt);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_flag(const int32_t* src, int32_t* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_flag, dim3(1), dim3(64), 0, s, src, dst);
+  return hipGetLastError();
+}
+
+// out = 1 when every instance's refinement has stopped.
+__global__ void k_all_stop(IrCtrl* const* ctrls, int n, int32_t* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int all = 1;
+  for (int i = 0; i < n; ++i) all &= ctrls[i]->stop ? 1 : 0;
+  *out = all;
+}
+
+hipError_t launch_all_stop(IrCtrl* const* ctrls, int n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_all_stop, dim3(1), dim3(64), 0, s, ctrls, n, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- engine check
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_debug_gemm(int m, int n, int k, int amode, int i0,
+                                                         const typename Cplx<T>::type* A, int64_t lda,
+                                                         const typename Cplx<T>::type* d,
+                                                         const typename Cplx<T>::type* B, int64_t ldb,
+                                                         typename Cplx<T>::type* C, int64_t ldc, T alpha, T beta) {
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<T>()];
+  Acc<T> acc;
+  acc.zero();
+  Opnd<T> a, b;
+  a.p = A;
+  a.ld = lda;
+  a.mode = amode;
+  a.i0 = i0;
+  b.p = B;
+  b.ld = ldb;
+  b.mode = OP_N;
+  b.i0 = 0;
+  gemm_acc<T>(acc, m, n, k, a, d, b, lds);
+  Out<T> o;
+  o.dst = C;
+  o.rs = 1;
+  o.cs = ldc;
+  o.src = beta != (T)0 ? C : nullptr;
+  o.srs = 1;
+  o.scs = ldc;
+  o.alpha = alpha;
+  o.beta = beta;
+  o.rowdiv = o.coldiv = nullptr;
+  gemm_store<T>(acc, m, n, o);
+}
+
+hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, const void* A, int64_t lda,
+                             const void* d, const void* B, int64_t ldb, void* C, int64_t ldc, double alpha,
+                             double beta, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_debug_gemm<double>, dim3(1), dim3(kThreads), 0, s, m, n, k, amode, i0, (const double2*)A,
+                       lda, (const double2*)d, (const double2*)B, ldb, (double2*)C, ldc, alpha, beta);
+  else
+    hipLaunchKernelGGL(k_debug_gemm<float>, dim3(1), dim3(kThreads), 0, s, m, n, k, amode, i0, (const float2*)A,
+                       lda, (const float2*)d, (const float2*)B, ldb, (float2*)C, ldc, (float)alpha, (float)beta);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- GEMM timing
+// Repeated 128x128x512 tile products on private buffers, one per workgroup:
+// used by the tuner to measure the task body's per-CU rate.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type* buf, int reps) {
+  typedef typename Cplx<T>::type C;
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<T>()];
+  C* base = buf + (int64_t)blockIdx.x * (3 * 128 * 512);
+  Acc<T> acc;
+  for (int r = 0; r < reps; ++r) {
+    acc.zero();
+    Opnd<T> A, B;
+    A.p = base;
+    A.ld = 128;
+    A.mode = OP_N;
+    A.i0 = 0;
+    B = A;
+    B.p = base + 128 * 512;
+    gemm_acc<T>(acc, 128, 128, 512, A, nullptr, B, lds);
+    Out<T> o;
+    o.dst = base + 2 * 128 * 512;
+    o.rs = 1;
+    o.cs = 128;
+    o.src = o.dst;
+    o.srs = 1;
+    o.scs = 128;
+    o.alpha = -1;
+    o.beta = 1;
+    o.rowdiv = o.coldiv = nullptr;
+    gemm_store<T>(acc, 128, 128, o);
+  }
+}
+
+hipError_t launch_gemm_bench(int prec, void* buf, int reps, int variant, hipStream_t s) {
+  (void)variant;
+  if (prec == 0) hipLaunchKernelGGL(k_gemm_bench<double>, dim3(256), dim3(kThreads), 0, s, (double2*)buf, reps);
+  else hipLaunchKernelGGL(k_gemm_bench<float>, dim3(256), dim3(kThreads), 0, s, (float2*)buf, reps);
+  return hipGetLastError();
+}
+
+}  // namespace d3m

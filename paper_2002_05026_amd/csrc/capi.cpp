@@ -1,0 +1,775 @@
+// C ABI of the D3M dual factorization and solution library (see d3m.h).
+#include "../../include/d3m.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "planner.h"
+
+using namespace d3m;
+
+struct d3m_plan_s {
+  PlanImpl p;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace layout of one factor.
+struct Layout {
+  size_t L, D, Linv, W, X64, R64, norms, ctrl, status, growth, counters, flags;
+  size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, iv;
+  size_t kp, fills, rt, rptr, rblk, nI, row0, prow0, perm, dkt;
+  size_t total;
+};
+
+struct Tables {
+  std::vector<KPlaceDev> kp, fills;
+  std::vector<RTaskDev> rt;
+  std::vector<int32_t> rptr;
+  std::vector<RBlkDev> rblk;
+  std::vector<int32_t> nI;
+  std::vector<int64_t> row0, prow0;
+  std::vector<int32_t> perm;
+  std::vector<DkTaskDev> dkt;
+};
+
+void make_tables(const PlanImpl& p, Tables& t) {
+  for (auto& k : p.kplace) t.kp.push_back({k.src, k.dst, k.rows, k.cols, k.ld_dst, k.trans});
+  for (auto& f : p.fills) t.fills.push_back({0, f.dst, f.rows, f.cols, f.ld_dst, 0});
+  t.nI = p.n;
+  t.row0.assign(p.nb + 1, 0);
+  for (int i = 0; i < p.nb; ++i) t.row0[i + 1] = t.row0[i] + p.n[i];
+  t.prow0.assign(p.nb, 0);
+  for (int i = 0; i < p.nb; ++i) t.prow0[i] = p.panels[p.pos[i]].prow0;
+  t.perm.assign(p.N, 0);
+  for (int i = 0; i < p.nb; ++i)
+    for (int r = 0; r < p.n[i]; ++r) t.perm[t.prow0[i] + r] = (int32_t)(t.row0[i] + r);
+  t.rptr.assign(p.nb + 1, 0);
+  for (int i = 0; i < p.nb; ++i) {
+    for (auto& b : p.rrow[i]) t.rblk.push_back({b.koff, b.J, b.mode});
+    t.rptr[i + 1] = (int32_t)t.rblk.size();
+  }
+  for (int i = 0; i < p.nb; ++i) {
+    const Panel& P = p.panels[p.pos[i]];
+    for (int c = 0; c < P.nt; ++c) {
+      const Tile& T = p.tiles[P.tile0 + c];
+      t.rt.push_back({i, T.r0, T.sz, 0});
+    }
+  }
+  auto add_dk = [&](int64_t koff, int I, int J) {
+    for (int r0 = 0; r0 < p.n[I]; r0 += kTileMax)
+      for (int c0 = 0; c0 < p.n[J]; c0 += kTileMax)
+        t.dkt.push_back({koff, I, J, r0, c0, std::min(kTileMax, p.n[I] - r0), std::min(kTileMax, p.n[J] - c0)});
+  };
+  for (int i = 0; i < p.nb; ++i) add_dk(p.koff[i], i, i);
+  for (size_t k = 0; k < p.pairs.size(); ++k) add_dk(p.koff[p.nb + k], p.pairs[k][0], p.pairs[k][1]);
+}
+
+Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
+  const size_t es = prec == 0 ? 16 : 8;
+  Layout l;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+  l.L = take(p.L_elems * es);
+  l.D = take(p.N * es);
+  l.Linv = take(p.Linv_elems * es);
+  l.W = take((size_t)p.N * nrhs_max * es);
+  l.X64 = take((size_t)p.N * nrhs_max * 16);
+  l.R64 = take((size_t)p.N * nrhs_max * 16);
+  l.norms = take(3 * 128 * sizeof(double));
+  l.ctrl = take(sizeof(IrCtrl));
+  l.status = take(4 * sizeof(int32_t));
+  l.growth = take(2 * p.nb * sizeof(float));
+  l.counters = take(std::max(p.fdag.tasks.size(), p.sdag.tasks.size()) * sizeof(int32_t));
+  l.flags = take(4 * sizeof(int32_t));
+  l.ftasks = take(p.fdag.tasks.size() * sizeof(Task));
+  l.fsucc = take(p.fdag.succ.size() * sizeof(int32_t));
+  l.fcnt = take(p.fdag.npred.size() * sizeof(int32_t));
+  l.stasks = take(p.sdag.tasks.size() * sizeof(Task));
+  l.ssucc = take(p.sdag.succ.size() * sizeof(int32_t));
+  l.scnt = take(p.sdag.npred.size() * sizeof(int32_t));
+  l.panels = take(p.panels.size() * sizeof(Panel));
+  l.pblocks = take(p.pblocks.size() * sizeof(PBlock));
+  l.tiles = take(p.tiles.size() * sizeof(Tile));
+  l.iv = take(sizeof(InstView));
+  l.kp = take(t.kp.size() * sizeof(KPlaceDev));
+  l.fills = take(t.fills.size() * sizeof(KPlaceDev));
+  l.rt = take(t.rt.size() * sizeof(RTaskDev));
+  l.rptr = take(t.rptr.size() * sizeof(int32_t));
+  l.rblk = take(t.rblk.size() * sizeof(RBlkDev));
+  l.nI = take(t.nI.size() * sizeof(int32_t));
+  l.row0 = take(t.row0.size() * sizeof(int64_t));
+  l.prow0 = take(t.prow0.size() * sizeof(int64_t));
+  l.perm = take(t.perm.size() * sizeof(int32_t));
+  l.dkt = take(t.dkt.size() * sizeof(DkTaskDev));
+  l.total = o;
+  return l;
+}
+
+int device_cus() {
+  static int cus = -1;
+  if (cus < 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  return cus;
+}
+
+}  // namespace
+
+struct d3m_factor_s {
+  const d3m_plan_s* plan = nullptr;
+  int prec = 0;
+  int nrhs_max = 0;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  d3m_options opt{};
+  Layout lay{};
+  Tables tab;
+  hipStream_t last = nullptr;
+  bool factored = false;
+  int nworkers = 256;
+  template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+  UserView uv() const {
+    UserView u;
+    u.n = at<int32_t>(lay.nI);
+    u.row0 = at<int64_t>(lay.row0);
+    u.prow0 = at<int64_t>(lay.prow0);
+    u.rptr = at<int32_t>(lay.rptr);
+    u.rblk = at<RBlkDev>(lay.rblk);
+    u.perm = at<int32_t>(lay.perm);
+    u.N = plan->p.N;
+    return u;
+  }
+  IrCtrl* ctrl() const { return at<IrCtrl>(lay.ctrl); }
+  int32_t* stop() const { return &ctrl()->stop; }
+  double* rmax() const { return at<double>(lay.norms); }
+  double* xmax() const { return at<double>(lay.norms) + 128; }
+  double* bmax() const { return at<double>(lay.norms) + 256; }
+};
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    if ((x) != hipSuccess) return D3M_ERR_HIP;     \
+  } while (0)
+
+namespace {
+
+d3m_status run_dag(const d3m_factor_s* f, bool solve, int nrhs, const int32_t* skip, hipStream_t s) {
+  const PlanImpl& p = f->plan->p;
+  const TaskDag& dag = solve ? p.sdag : p.fdag;
+  DagArgs a;
+  a.tasks = f->at<Task>(solve ? f->lay.stasks : f->lay.ftasks);
+  a.succ = f->at<int32_t>(solve ? f->lay.ssucc : f->lay.fsucc);
+  a.counters = f->at<int32_t>(f->lay.counters);
+  int32_t* flags = f->at<int32_t>(f->lay.flags);
+  a.head = flags;
+  a.abort_flag = flags + 1;
+  a.skip = skip;
+  a.inst = f->at<InstView>(f->lay.iv);
+  a.ntask = (int32_t)dag.tasks.size();
+  a.nrhs = nrhs;
+  a.spin_limit_ns = 20LL * 1000 * 1000 * 1000;  // 20 s on one wait
+  HIPCHK(launch_reset(a.counters, f->at<int32_t>(solve ? f->lay.scnt : f->lay.fcnt), a.ntask, a.head,
+                      a.abort_flag, skip, s));
+  HIPCHK(launch_dag(a, f->prec, f->nworkers, s));
+  return D3M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* d3m_status_string(d3m_status s) {
+  switch (s) {
+    case D3M_OK: return "ok";
+    case D3M_ERR_ARG: return "invalid argument";
+    case D3M_ERR_PATTERN: return "invalid block pattern or order";
+    case D3M_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case D3M_ERR_STATE: return "call out of sequence";
+    case D3M_ERR_HIP: return "HIP runtime error";
+    case D3M_ERR_HANG: return "dependency wait exceeded the watchdog bound";
+    case D3M_ERR_NORUNTIME: return "no usable gfx950 device";
+    case D3M_ZERO_PIVOT: return "zero or non-finite pivot";
+    case D3M_NONFINITE: return "non-finite value in the solution";
+    case D3M_IR_NOCONV: return "iterative refinement did not converge";
+  }
+  return "unknown status";
+}
+
+int32_t d3m_device_ok(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return 0;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+d3m_status d3m_analyze(int32_t nblk, const int32_t* blk_size, int64_t npair, const int32_t* pairs,
+                       const int32_t* order, const int32_t* grid, const d3m_analyze_options* opt,
+                       d3m_plan* out) {
+  if (!out) return D3M_ERR_ARG;
+  *out = nullptr;
+  d3m_analyze_options o{};
+  if (opt) o = *opt;
+  d3m_plan_s* pl = new (std::nothrow) d3m_plan_s;
+  if (!pl) return D3M_ERR_ARG;
+  int err = 0;
+  std::string msg = build_plan(pl->p, nblk, blk_size, npair, pairs, order, grid, o.tile, o.nworkers, o.sched, &err);
+  if (!msg.empty()) {
+    delete pl;
+    return (d3m_status)err;
+  }
+  *out = pl;
+  return D3M_OK;
+}
+
+d3m_status d3m_plan_query(d3m_plan plan, d3m_plan_info* o) {
+  if (!plan || !o) return D3M_ERR_ARG;
+  const PlanImpl& p = plan->p;
+  std::memset(o, 0, sizeof(*o));
+  o->N = p.N;
+  o->nblk = p.nb;
+  o->npair = (int64_t)p.pairs.size();
+  o->k_len = p.koff.back();
+  o->fill_blocks = p.fill_blocks;
+  o->L_blocks = p.L_blocks;
+  o->nnz_L = p.nnz_L;
+  o->nnz_K = p.nnz_K;
+  o->etree_height = p.etree_height;
+  o->max_S = p.max_S;
+  o->ntask_factor = (int64_t)p.fdag.tasks.size();
+  o->ntask_solve = (int64_t)p.sdag.tasks.size();
+  o->ntiles = (int64_t)p.tiles.size();
+  o->flops_diag = p.flops_diag;
+  o->flops_trsm = p.flops_trsm;
+  o->flops_update = p.flops_update;
+  o->flops_factor = p.flops_diag + p.flops_trsm + p.flops_update;
+  o->solve_flops_per_rhs = 16.0 * (double)p.nnz_L;
+  o->sim_factor_us = p.fdag.makespan_us;
+  return D3M_OK;
+}
+
+d3m_status d3m_plan_order(d3m_plan plan, int32_t* order) {
+  if (!plan || !order) return D3M_ERR_ARG;
+  std::copy(plan->p.order.begin(), plan->p.order.end(), order);
+  return D3M_OK;
+}
+
+d3m_status d3m_plan_k_offsets(d3m_plan plan, int64_t* offsets) {
+  if (!plan || !offsets) return D3M_ERR_ARG;
+  std::copy(plan->p.koff.begin(), plan->p.koff.end(), offsets);
+  return D3M_OK;
+}
+
+d3m_status d3m_plan_struct(d3m_plan plan, int32_t I, int32_t* S, int32_t* count) {
+  if (!plan || !S || !count || I < 0 || I >= plan->p.nb) return D3M_ERR_ARG;
+  const PlanImpl& p = plan->p;
+  const auto& s = p.S[p.pos[I]];
+  for (size_t u = 0; u < s.size(); ++u) S[u] = p.order[s[u]];
+  *count = (int32_t)s.size();
+  return D3M_OK;
+}
+
+d3m_status d3m_plan_check(d3m_plan plan, int64_t* nviolations) {
+  if (!plan || !nviolations) return D3M_ERR_ARG;
+  const PlanImpl& p = plan->p;
+  if (p.facc.empty() || p.sacc.empty()) return D3M_ERR_STATE;  // too large to check
+  int64_t a = check_dag(p.fdag, p.facc), b = check_dag(p.sdag, p.sacc);
+  if (a < 0 || b < 0) {
+    *nviolations = -1;
+    return D3M_ERR_STATE;
+  }
+  *nviolations = a + b;
+  return D3M_OK;
+}
+
+void d3m_plan_destroy(d3m_plan plan) { delete plan; }
+
+d3m_status d3m_workspace_bytes(d3m_plan plan, d3m_precision prec, int32_t nrhs_max, size_t* bytes) {
+  if (!plan || !bytes || nrhs_max < 1 || nrhs_max > 128 || (prec != D3M_C128 && prec != D3M_C64_IR))
+    return D3M_ERR_ARG;
+  Tables t;
+  make_tables(plan->p, t);
+  *bytes = make_layout(plan->p, t, prec == D3M_C128 ? 0 : 1, nrhs_max).total;
+  return D3M_OK;
+}
+
+d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size_t bytes, int32_t nrhs_max,
+                           const d3m_options* opt, d3m_factor* out) {
+  if (!plan || !out || !dev_ws || nrhs_max < 1 || nrhs_max > 128 || (prec != D3M_C128 && prec != D3M_C64_IR))
+    return D3M_ERR_ARG;
+  *out = nullptr;
+  if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return D3M_ERR_WORKSPACE;
+  d3m_factor_s* f = new (std::nothrow) d3m_factor_s;
+  if (!f) return D3M_ERR_ARG;
+  f->plan = plan;
+  f->prec = prec == D3M_C128 ? 0 : 1;
+  f->nrhs_max = nrhs_max;
+  make_tables(plan->p, f->tab);
+  f->lay = make_layout(plan->p, f->tab, f->prec, nrhs_max);
+  if (bytes < f->lay.total) {
+    delete f;
+    return D3M_ERR_WORKSPACE;
+  }
+  f->ws = static_cast<char*>(dev_ws);
+  f->bytes = bytes;
+  if (opt) f->opt = *opt;
+  if (f->opt.tol <= 0) f->opt.tol = 1e-10;
+  if (f->opt.max_iter <= 0) f->opt.max_iter = 10;
+  if (f->opt.max_iter > 30) f->opt.max_iter = 30;
+  if (f->opt.growth_dmin <= 0) f->opt.growth_dmin = 1e-4;
+  if (f->opt.growth_lmax <= 0) f->opt.growth_lmax = 1e2;
+  f->nworkers = device_cus();
+  const PlanImpl& p = plan->p;
+  auto up = [&](size_t off, const void* src, size_t n) -> bool {
+    if (n == 0) return true;
+    return hipMemcpy(f->ws + off, src, n, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  InstView iv{};
+  iv.L = f->ws + f->lay.L;
+  iv.D = f->ws + f->lay.D;
+  iv.Linv = f->ws + f->lay.Linv;
+  iv.W = f->ws + f->lay.W;
+  iv.panels = f->at<Panel>(f->lay.panels);
+  iv.pblocks = f->at<PBlock>(f->lay.pblocks);
+  iv.tiles = f->at<Tile>(f->lay.tiles);
+  iv.status = f->at<int32_t>(f->lay.status);
+  iv.growth = f->at<float>(f->lay.growth);
+  iv.nrhs = nrhs_max;
+  iv.npanel = p.nb;
+  iv.N = p.N;
+  bool ok = up(f->lay.ftasks, p.fdag.tasks.data(), p.fdag.tasks.size() * sizeof(Task)) &&
+            up(f->lay.fsucc, p.fdag.succ.data(), p.fdag.succ.size() * 4) &&
+            up(f->lay.fcnt, p.fdag.npred.data(), p.fdag.npred.size() * 4) &&
+            up(f->lay.stasks, p.sdag.tasks.data(), p.sdag.tasks.size() * sizeof(Task)) &&
+            up(f->lay.ssucc, p.sdag.succ.data(), p.sdag.succ.size() * 4) &&
+            up(f->lay.scnt, p.sdag.npred.data(), p.sdag.npred.size() * 4) &&
+            up(f->lay.panels, p.panels.data(), p.panels.size() * sizeof(Panel)) &&
+            up(f->lay.pblocks, p.pblocks.data(), p.pblocks.size() * sizeof(PBlock)) &&
+            up(f->lay.tiles, p.tiles.data(), p.tiles.size() * sizeof(Tile)) &&
+            up(f->lay.iv, &iv, sizeof(iv)) &&
+            up(f->lay.kp, f->tab.kp.data(), f->tab.kp.size() * sizeof(KPlaceDev)) &&
+            up(f->lay.fills, f->tab.fills.data(), f->tab.fills.size() * sizeof(KPlaceDev)) &&
+            up(f->lay.rt, f->tab.rt.data(), f->tab.rt.size() * sizeof(RTaskDev)) &&
+            up(f->lay.rptr, f->tab.rptr.data(), f->tab.rptr.size() * 4) &&
+            up(f->lay.rblk, f->tab.rblk.data(), f->tab.rblk.size() * sizeof(RBlkDev)) &&
+            up(f->lay.nI, f->tab.nI.data(), f->tab.nI.size() * 4) &&
+            up(f->lay.row0, f->tab.row0.data(), f->tab.row0.size() * 8) &&
+            up(f->lay.prow0, f->tab.prow0.data(), f->tab.prow0.size() * 8) &&
+            up(f->lay.perm, f->tab.perm.data(), f->tab.perm.size() * 4) &&
+            up(f->lay.dkt, f->tab.dkt.data(), f->tab.dkt.size() * sizeof(DkTaskDev));
+  // flags, status and refinement control start cleared
+  ok = ok && hipMemset(f->ws + f->lay.flags, 0, 16) == hipSuccess &&
+       hipMemset(f->ws + f->lay.ctrl, 0, sizeof(IrCtrl)) == hipSuccess &&
+       hipMemset(f->ws + f->lay.status, 0, 16) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    delete f;
+    return D3M_ERR_HIP;
+  }
+  *out = f;
+  return D3M_OK;
+}
+
+d3m_status d3m_factorize(d3m_factor f, const void* dev_K, d3m_stream stream) {
+  if (!f || !dev_K) return D3M_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const PlanImpl& p = f->plan->p;
+  HIPCHK(launch_prepare(f->at<int32_t>(f->lay.status), f->at<float>(f->lay.growth), p.nb, f->ctrl(), f->opt.tol,
+                        f->opt.max_iter, s));
+  HIPCHK(launch_scatter(dev_K, f->ws + f->lay.L, f->at<KPlaceDev>(f->lay.kp), (int)f->tab.kp.size(),
+                        f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->prec, s));
+  d3m_status st = run_dag(f, false, f->nrhs_max, nullptr, s);
+  if (st != D3M_OK) return st;
+  HIPCHK(launch_knorm(dev_K, f->uv(), f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), f->ctrl(), s));
+  f->last = s;
+  f->factored = true;
+  return D3M_OK;
+}
+
+namespace {
+
+d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int nrhs, int64_t ld, hipStream_t s) {
+  const PlanImpl& p = f->plan->p;
+  const int64_t N = p.N;
+  UserView uv = f->uv();
+  IrCtrl* c = f->ctrl();
+  // refinement bookkeeping reset (keeps ||K||)
+  HIPCHK(launch_ir_reset(c, f->opt.tol, f->opt.max_iter, s));
+  HIPCHK(launch_zero_f64(f->rmax(), 3 * 128, s));
+  HIPCHK(launch_colmax(B, N, nrhs, ld, 0, f->bmax(), nullptr, s));
+  const RTaskDev* rt = f->at<RTaskDev>(f->lay.rt);
+  const int nrt = (int)f->tab.rt.size();
+  void* W = f->ws + f->lay.W;
+  void* X64 = f->ws + f->lay.X64;
+  void* R64 = f->ws + f->lay.R64;
+  if (f->prec == 0) {
+    HIPCHK(launch_perm_in(B, ld, W, 0, uv, nrhs, nullptr, s));
+    d3m_status st = run_dag(f, true, nrhs, nullptr, s);
+    if (st) return st;
+    HIPCHK(launch_residual(K, B, ld, W, R64, f->rmax(), uv, rt, nrt, nrhs, nullptr, s));
+    HIPCHK(launch_colmax(W, N, nrhs, 0, 1, f->xmax(), nullptr, s));
+    HIPCHK(launch_ir_check(c, f->rmax(), f->xmax(), f->bmax(), nrhs, 2, s));
+    HIPCHK(launch_perm_out(W, X, ld, uv, nrhs, s));
+    return D3M_OK;
+  }
+  const int64_t nel = N * nrhs;
+  HIPCHK(launch_perm_in(B, ld, W, 1, uv, nrhs, nullptr, s));
+  d3m_status st = run_dag(f, true, nrhs, nullptr, s);
+  if (st) return st;
+  HIPCHK(launch_cvt_up(W, X64, nel, s));
+  const int32_t* stop = f->stop();
+  for (int it = 0; it <= f->opt.max_iter; ++it) {
+    HIPCHK(launch_residual(K, B, ld, X64, R64, f->rmax(), uv, rt, nrt, nrhs, stop, s));
+    HIPCHK(launch_colmax(X64, N, nrhs, 0, 1, f->xmax(), stop, s));
+    HIPCHK(launch_ir_check(c, f->rmax(), f->xmax(), f->bmax(), nrhs, it == f->opt.max_iter ? 1 : 0, s));
+    if (f->opt.ir_host_sync) {
+      int32_t h = 0;
+      HIPCHK(hipMemcpyAsync(&h, stop, 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (h) break;
+    }
+    if (it == f->opt.max_iter) break;
+    HIPCHK(launch_cvt_down(R64, W, nel, stop, s));
+    st = run_dag(f, true, nrhs, stop, s);
+    if (st) return st;
+    HIPCHK(launch_axpy_up(W, X64, nel, stop, s));
+  }
+  HIPCHK(launch_perm_out(X64, X, ld, uv, nrhs, s));
+  return D3M_OK;
+}
+
+}  // namespace
+
+d3m_status d3m_solve(d3m_factor f, const void* dev_K, const void* dev_B, void* dev_X, int32_t nrhs, int64_t ld,
+                     d3m_stream stream) {
+  if (!f || !dev_K || !dev_B || !dev_X || nrhs < 1 || nrhs > f->nrhs_max || ld < f->plan->p.N) return D3M_ERR_ARG;
+  if (!f->factored) return D3M_ERR_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  d3m_status st = solve_impl(f, dev_K, dev_B, dev_X, nrhs, ld, s);
+  f->last = s;
+  return st;
+}
+
+d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const void* dev_G, void* dev_Lambda,
+                       void* dev_dK, int32_t nrhs, int64_t ld, d3m_stream stream) {
+  if (!f || !dev_K || !dev_X || !dev_G || !dev_Lambda || nrhs < 1 || nrhs > f->nrhs_max || ld < f->plan->p.N)
+    return D3M_ERR_ARG;
+  if (!f->factored) return D3M_ERR_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  d3m_status st = solve_impl(f, dev_K, dev_G, dev_Lambda, nrhs, ld, s);
+  if (st) return st;
+  if (dev_dK)
+    HIPCHK(launch_dk(dev_Lambda, dev_X, ld, nrhs, dev_dK, f->uv(), f->at<DkTaskDev>(f->lay.dkt),
+                     (int)f->tab.dkt.size(), s));
+  f->last = s;
+  return D3M_OK;
+}
+
+d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
+  if (!f || !out) return D3M_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(f->last));
+  std::memset(out, 0, sizeof(*out));
+  int32_t st[2];
+  IrCtrl c;
+  int32_t flags[2];
+  HIPCHK(hipMemcpy(st, f->at<int32_t>(f->lay.status), 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&c, f->ctrl(), sizeof(c), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(flags, f->at<int32_t>(f->lay.flags), 8, hipMemcpyDeviceToHost));
+  out->pivot_row = -1;
+  out->status = D3M_OK;
+  if (st[0] != 0x7fffffff) {
+    out->pivot_row = f->tab.perm[st[0]];
+    out->status = D3M_ZERO_PIVOT;
+  }
+  out->ir_iters = c.iters;
+  out->eta = -1;
+  for (int k = 0; k < 32; ++k) {
+    out->eta_hist[k] = c.eta_hist[k];
+    if (c.eta_hist[k] >= 0) out->eta = c.eta_hist[k];
+  }
+  if (out->status == D3M_OK && c.status) out->status = c.status;
+  out->hang = flags[1];
+  if (flags[1]) out->status = D3M_ERR_HANG;
+  return (d3m_status)out->status;
+}
+
+d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out) {
+  if (!f || !host_out) return D3M_ERR_ARG;
+  const PlanImpl& p = f->plan->p;
+  if (I < 0 || I >= p.nb || J < 0 || J >= p.nb) return D3M_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(f->last));
+  const Panel& P = p.panels[p.pos[I]];
+  int rowoff = -1;
+  for (int b = 0; b < P.npb; ++b)
+    if (p.pblocks[P.pb0 + b].J == p.pos[J]) rowoff = p.pblocks[P.pb0 + b].prow;
+  if (rowoff < 0) return D3M_ERR_ARG;
+  const int nJ = p.n[J], nI = p.n[I];
+  const size_t es = f->prec == 0 ? 16 : 8;
+  std::vector<char> panel((size_t)P.H * nI * es);
+  HIPCHK(hipMemcpy(panel.data(), f->ws + f->lay.L + P.off * es, panel.size(), hipMemcpyDeviceToHost));
+  double* o = static_cast<double*>(host_out);
+  for (int c = 0; c < nI; ++c)
+    for (int r = 0; r < nJ; ++r) {
+      size_t e = (size_t)(rowoff + r) + (size_t)c * P.H;
+      double re, im;
+      if (es == 16) {
+        re = reinterpret_cast<double*>(panel.data())[2 * e];
+        im = reinterpret_cast<double*>(panel.data())[2 * e + 1];
+      } else {
+        re = reinterpret_cast<float*>(panel.data())[2 * e];
+        im = reinterpret_cast<float*>(panel.data())[2 * e + 1];
+      }
+      if (J == I && r < c) re = im = 0;  // upper part of the diagonal block is not part of the factor
+      o[2 * ((size_t)r + (size_t)c * nJ)] = re;
+      o[2 * ((size_t)r + (size_t)c * nJ) + 1] = im;
+    }
+  return D3M_OK;
+}
+
+void d3m_factor_destroy(d3m_factor f) { delete f; }
+
+d3m_status d3m_debug_gemm(d3m_precision prec, int32_t m, int32_t n, int32_t k, int32_t amode, int32_t i0,
+                          const void* A, int64_t lda, const void* d, const void* B, int64_t ldb, void* C,
+                          int64_t ldc, double alpha, double beta, d3m_stream stream) {
+  if (m < 1 || n < 1 || k < 0 || m > kTileMax || n > kTileMax || amode < 0 || amode > 2 || !A || !B || !C)
+    return D3M_ERR_ARG;
+  if (amode == 0 && lda < m) return D3M_ERR_ARG;
+  if (amode == 1 && lda < k) return D3M_ERR_ARG;
+  if (amode == 2 && (lda < k || i0 < 0 || i0 + m > lda)) return D3M_ERR_ARG;
+  if (ldb < n || ldc < m) return D3M_ERR_ARG;
+  HIPCHK(launch_debug_gemm(prec == D3M_C128 ? 0 : 1, m, n, k, amode, i0, A, lda, d, B, ldb, C, ldc, alpha, beta,
+                           static_cast<hipStream_t>(stream)));
+  return D3M_OK;
+}
+
+d3m_status d3m_tune_gemm(d3m_precision prec, void* dev_scratch, size_t bytes, int32_t* best_id, double* gflops_out,
+                         int32_t* ncand) {
+  if (!dev_scratch || !best_id || !ncand) return D3M_ERR_ARG;
+  const int p = prec == D3M_C128 ? 0 : 1;
+  const size_t es = p == 0 ? 16 : 8;
+  const size_t need = (size_t)256 * 3 * 128 * 512 * es;
+  if (bytes < need) return D3M_ERR_WORKSPACE;
+  const int reps = 20;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipMemset(dev_scratch, 0, need));
+  HIPCHK(launch_gemm_bench(p, dev_scratch, 2, 0, nullptr));
+  HIPCHK(hipEventRecord(e0, nullptr));
+  HIPCHK(launch_gemm_bench(p, dev_scratch, reps, 0, nullptr));
+  HIPCHK(hipEventRecord(e1, nullptr));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  const double flops = 256.0 * reps * 8.0 * 128 * 128 * 512;
+  if (gflops_out) gflops_out[0] = flops / (ms * 1e-3) / 1e9;
+  *best_id = 0;
+  *ncand = 1;
+  return D3M_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batching
+namespace {
+struct BatchLayout {
+  size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, counters, flags, iv, ctrls, total;
+};
+BatchLayout batch_layout(const TaskDag& fd, const TaskDag& sd, int n) {
+  BatchLayout l;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+  l.ftasks = take(fd.tasks.size() * sizeof(Task));
+  l.fsucc = take(fd.succ.size() * 4);
+  l.fcnt = take(fd.npred.size() * 4);
+  l.stasks = take(sd.tasks.size() * sizeof(Task));
+  l.ssucc = take(sd.succ.size() * 4);
+  l.scnt = take(sd.npred.size() * 4);
+  l.counters = take(std::max(fd.tasks.size(), sd.tasks.size()) * 4);
+  l.flags = take(4 * 4);
+  l.iv = take(n * sizeof(InstView));
+  l.ctrls = take(n * sizeof(IrCtrl*));
+  l.total = o;
+  return l;
+}
+}  // namespace
+
+struct d3m_batch_s {
+  std::vector<d3m_factor_s*> f;
+  TaskDag fd, sd;
+  BatchLayout lay{};
+  char* ws = nullptr;
+  int prec = 0;
+  int nworkers = 256;
+  template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+};
+
+namespace {
+d3m_status batch_dag(d3m_batch_s* b, bool solve, const int32_t* skip, hipStream_t s) {
+  const TaskDag& dag = solve ? b->sd : b->fd;
+  DagArgs a;
+  a.tasks = b->at<Task>(solve ? b->lay.stasks : b->lay.ftasks);
+  a.succ = b->at<int32_t>(solve ? b->lay.ssucc : b->lay.fsucc);
+  a.counters = b->at<int32_t>(b->lay.counters);
+  int32_t* flags = b->at<int32_t>(b->lay.flags);
+  a.head = flags;
+  a.abort_flag = flags + 1;
+  a.skip = skip;
+  a.inst = b->at<InstView>(b->lay.iv);
+  a.ntask = (int32_t)dag.tasks.size();
+  a.nrhs = 0;
+  a.spin_limit_ns = 20LL * 1000 * 1000 * 1000;
+  HIPCHK(launch_reset(a.counters, b->at<int32_t>(solve ? b->lay.scnt : b->lay.fcnt), a.ntask, a.head, a.abort_flag,
+                      skip, s));
+  HIPCHK(launch_dag(a, b->prec, b->nworkers, s));
+  return D3M_OK;
+}
+}  // namespace
+
+extern "C" {
+
+d3m_status d3m_batch_workspace_bytes(int32_t ninst, const d3m_factor* f, size_t* bytes) {
+  if (ninst < 1 || !f || !bytes) return D3M_ERR_ARG;
+  std::vector<const TaskDag*> fds, sds;
+  for (int i = 0; i < ninst; ++i) {
+    if (!f[i]) return D3M_ERR_ARG;
+    fds.push_back(&f[i]->plan->p.fdag);
+    sds.push_back(&f[i]->plan->p.sdag);
+  }
+  TaskDag fd = merge_dags(fds, 256), sd = merge_dags(sds, 256);
+  *bytes = batch_layout(fd, sd, ninst).total;
+  return D3M_OK;
+}
+
+d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, size_t bytes, d3m_batch* out) {
+  if (ninst < 1 || !f || !dev_ws || !out) return D3M_ERR_ARG;
+  *out = nullptr;
+  if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return D3M_ERR_WORKSPACE;
+  d3m_batch_s* b = new (std::nothrow) d3m_batch_s;
+  if (!b) return D3M_ERR_ARG;
+  std::vector<const TaskDag*> fds, sds;
+  for (int i = 0; i < ninst; ++i) {
+    if (!f[i] || f[i]->prec != f[0]->prec) { delete b; return D3M_ERR_ARG; }
+    b->f.push_back(f[i]);
+    fds.push_back(&f[i]->plan->p.fdag);
+    sds.push_back(&f[i]->plan->p.sdag);
+  }
+  b->prec = f[0]->prec;
+  b->nworkers = device_cus();
+  b->fd = merge_dags(fds, b->nworkers);
+  b->sd = merge_dags(sds, b->nworkers);
+  b->lay = batch_layout(b->fd, b->sd, ninst);
+  if (bytes < b->lay.total) { delete b; return D3M_ERR_WORKSPACE; }
+  b->ws = static_cast<char*>(dev_ws);
+  std::vector<InstView> ivs(ninst);
+  std::vector<IrCtrl*> ctrls(ninst);
+  for (int i = 0; i < ninst; ++i) {
+    if (hipMemcpy(&ivs[i], f[i]->ws + f[i]->lay.iv, sizeof(InstView), hipMemcpyDeviceToHost) != hipSuccess) {
+      delete b;
+      return D3M_ERR_HIP;
+    }
+    ctrls[i] = f[i]->ctrl();
+  }
+  auto up = [&](size_t off, const void* src, size_t n) {
+    return n == 0 || hipMemcpy(b->ws + off, src, n, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = up(b->lay.ftasks, b->fd.tasks.data(), b->fd.tasks.size() * sizeof(Task)) &&
+            up(b->lay.fsucc, b->fd.succ.data(), b->fd.succ.size() * 4) &&
+            up(b->lay.fcnt, b->fd.npred.data(), b->fd.npred.size() * 4) &&
+            up(b->lay.stasks, b->sd.tasks.data(), b->sd.tasks.size() * sizeof(Task)) &&
+            up(b->lay.ssucc, b->sd.succ.data(), b->sd.succ.size() * 4) &&
+            up(b->lay.scnt, b->sd.npred.data(), b->sd.npred.size() * 4) &&
+            up(b->lay.iv, ivs.data(), ivs.size() * sizeof(InstView)) &&
+            up(b->lay.ctrls, ctrls.data(), ctrls.size() * sizeof(IrCtrl*));
+  if (!ok) { delete b; return D3M_ERR_HIP; }
+  *out = b;
+  return D3M_OK;
+}
+
+d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B, void* const* X,
+                         const int32_t* nrhs, const int64_t* ld, d3m_stream stream) {
+  if (!b || !K || !B || !X || !nrhs || !ld) return D3M_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = (int)b->f.size();
+  for (int i = 0; i < n; ++i) {
+    const d3m_factor_s* f = b->f[i];
+    if (!K[i] || !B[i] || !X[i] || nrhs[i] != f->nrhs_max || ld[i] < f->plan->p.N) return D3M_ERR_ARG;
+  }
+  // scatter/convert and ||K|| per instance, then one persistent factor launch
+  for (int i = 0; i < n; ++i) {
+    d3m_factor_s* f = b->f[i];
+    const PlanImpl& p = f->plan->p;
+    HIPCHK(launch_prepare(f->at<int32_t>(f->lay.status), f->at<float>(f->lay.growth), p.nb, f->ctrl(), f->opt.tol,
+                          f->opt.max_iter, s));
+    HIPCHK(launch_scatter(K[i], f->ws + f->lay.L, f->at<KPlaceDev>(f->lay.kp), (int)f->tab.kp.size(),
+                          f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->prec, s));
+    HIPCHK(launch_knorm(K[i], f->uv(), f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), f->ctrl(), s));
+  }
+  d3m_status st = batch_dag(b, false, nullptr, s);
+  if (st) return st;
+  for (int i = 0; i < n; ++i) {
+    d3m_factor_s* f = b->f[i];
+    HIPCHK(launch_copy_flag(b->at<int32_t>(b->lay.flags) + 1, f->at<int32_t>(f->lay.flags) + 1, s));
+    HIPCHK(launch_ir_reset(f->ctrl(), f->opt.tol, f->opt.max_iter, s));
+    HIPCHK(launch_zero_f64(f->rmax(), 3 * 128, s));
+    HIPCHK(launch_colmax(B[i], f->plan->p.N, nrhs[i], ld[i], 0, f->bmax(), nullptr, s));
+    HIPCHK(launch_perm_in(B[i], ld[i], f->ws + f->lay.W, b->prec, f->uv(), nrhs[i], nullptr, s));
+  }
+  st = batch_dag(b, true, nullptr, s);
+  if (st) return st;
+  int32_t* allstop = b->at<int32_t>(b->lay.flags) + 2;
+  const int max_iter = b->f[0]->opt.max_iter;
+  for (int i = 0; i < n; ++i) {
+    d3m_factor_s* f = b->f[i];
+    const int64_t nel = f->plan->p.N * nrhs[i];
+    if (b->prec == 1) HIPCHK(launch_cvt_up(f->ws + f->lay.W, f->ws + f->lay.X64, nel, s));
+  }
+  for (int it = 0; it <= (b->prec == 1 ? max_iter : 0); ++it) {
+    for (int i = 0; i < n; ++i) {
+      d3m_factor_s* f = b->f[i];
+      const int64_t N = f->plan->p.N;
+      void* xv = b->prec == 1 ? f->ws + f->lay.X64 : f->ws + f->lay.W;
+      HIPCHK(launch_residual(K[i], B[i], ld[i], xv, f->ws + f->lay.R64, f->rmax(), f->uv(),
+                             f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), nrhs[i], f->stop(), s));
+      HIPCHK(launch_colmax(xv, N, nrhs[i], 0, 1, f->xmax(), f->stop(), s));
+      HIPCHK(launch_ir_check(f->ctrl(), f->rmax(), f->xmax(), f->bmax(), nrhs[i],
+                             b->prec == 0 ? 2 : (it == max_iter ? 1 : 0), s));
+      if (b->prec == 1 && it < max_iter)
+        HIPCHK(launch_cvt_down(f->ws + f->lay.R64, f->ws + f->lay.W, N * nrhs[i], f->stop(), s));
+    }
+    if (b->prec == 0 || it == max_iter) break;
+    HIPCHK(launch_all_stop(b->at<IrCtrl*>(b->lay.ctrls), n, allstop, s));
+    st = batch_dag(b, true, allstop, s);
+    if (st) return st;
+    for (int i = 0; i < n; ++i) {
+      d3m_factor_s* f = b->f[i];
+      HIPCHK(launch_axpy_up(f->ws + f->lay.W, f->ws + f->lay.X64, f->plan->p.N * nrhs[i], f->stop(), s));
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    d3m_factor_s* f = b->f[i];
+    HIPCHK(launch_perm_out(b->prec == 1 ? f->ws + f->lay.X64 : f->ws + f->lay.W, X[i], ld[i], f->uv(), nrhs[i], s));
+    f->last = s;
+    f->factored = true;
+  }
+  return D3M_OK;
+}
+
+void d3m_batch_destroy(d3m_batch b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal data structures shared by the host planner (C++) and the device
+// kernels (HIP).  Plain structs only; no behaviour.
+#pragma once
+#include <stdint.h>
+
+namespace d3m {
+
+constexpr int kTileMax = 128;   // largest tile edge (rows/cols) of any task
+constexpr int kThreads = 512;   // threads per workgroup of every MFMA kernel (8 waves)
+
+// Task kinds of the elimination DAG (Sec. II: per nonzero block a dense
+// factorization, dense triangular solves and dense updates), and of the
+// block forward/backward solve DAG.
+enum TaskKind : int32_t {
+  TK_DIAGF = 1,   // LDL^T of the dense diagonal block of one interface
+  TK_PSTRIP = 2,  // TRSM + D-scale of one row tile below the diagonal block
+  TK_XUPD = 3,    // Schur update of one tile: A_rs -= L_rI D_I L_sI^T
+  TK_FDIAG = 10,  // forward solve with the diagonal block: z_I = D^-1 L_II^-1 b_I
+  TK_FUPD = 11,   // forward update of one row tile: b_r -= L_rI D_I z_I
+  TK_BUPD = 12,   // backward gather of one column tile: z_c -= sum_r L_rc^T x_r
+  TK_BDIAG = 13,  // backward solve with the diagonal block: x_I = L_II^-T t_I
+};
+
+// One task, in ticket order.  Offsets are in complex elements, relative to
+// the instance's base pointers (panel storage L, solve vector W).
+struct Task {
+  int32_t kind;
+  int32_t inst;      // instance index (batched launches run many factors)
+  int32_t panel;     // block column I (elimination position)
+  int32_t m, n, k;   // output rows, output cols, inner length
+  int32_t lda, ldc;  // leading dims of the A operand and the output
+  int32_t dofs;      // offset of D_I in the D vector (internal row of I)
+  int32_t aux;       // kind-specific (row tile / column tile index)
+  int64_t a_off, b_off, c_off;
+  int32_t succ_begin, nsucc;
+  int32_t pad0, pad1;
+};
+static_assert(sizeof(Task) == 80, "Task layout");
+
+// Block column (panel) I of the factor storage: the n_I x n_I diagonal
+// block on top of the blocks L_JI of every J in S_I, column-major with
+// leading dimension H = n_I + sum_J n_J.
+struct Panel {
+  int64_t off;       // element offset of the panel in L storage
+  int32_t H, n;      // rows, cols
+  int32_t prow0;     // internal (elimination-order) first row of I
+  int32_t tile0;     // first tile index of I in the tile table
+  int32_t nt;        // tiles of I
+  int32_t pb0, npb;  // row-block list: blocks [pb0, pb0+npb) (the first is I itself)
+  int32_t user;      // user interface id
+  int32_t pad0, pad1;
+};
+
+// A row block of a panel: the rows of interface J inside panel I.
+struct PBlock {
+  int32_t J;         // panel index (elimination position) of J
+  int32_t prow;      // first row of J inside the panel
+  int32_t n;         // rows (n_J)
+  int32_t prow0;     // internal first row of J
+};
+
+// A tile of an interface: rows [r0, r0+sz) of interface I.
+struct Tile {
+  int32_t panel, r0, sz, pad;
+  int64_t linv_off;  // element offset of its inverted unit-lower diagonal tile
+};
+
+// Per-instance device view.  The element type of L, D, Linv and W is the
+// factor precision (complex64 or complex128).
+struct InstView {
+  void* L;           // panel storage
+  void* D;           // N diagonal pivots, internal order
+  void* Linv;        // inverted unit-lower diagonal tiles
+  void* W;           // solve vectors, internal order, RHS fastest: W[row * nrhs + j]
+  const Panel* panels;
+  const PBlock* pblocks;
+  const Tile* tiles;
+  int32_t* status;   // [0] first bad pivot (internal row, INT_MAX if none), [1] count
+  float* growth;     // per panel: [2*I] min |d| / max |A_II|, [2*I+1] max |L|
+  int32_t nrhs;
+  int32_t npanel;
+  int64_t N;
+};
+
+// Arguments of one persistent DAG launch.
+struct DagArgs {
+  const Task* tasks;
+  const int32_t* succ;
+  int32_t* counters;     // pending predecessor counts (reset before each launch)
+  int32_t* head;         // ticket counter
+  int32_t* abort_flag;   // set by the watchdog; every workgroup then exits
+  const int32_t* skip;   // if non-null and *skip != 0, the launch does nothing
+  const InstView* inst;
+  int32_t ntask;
+  int32_t nrhs;          // right-hand sides of a solve launch (0: the instance's own)
+  int64_t spin_limit_ns; // watchdog bound on one dependency wait
+};
+
+}  // namespace d3m

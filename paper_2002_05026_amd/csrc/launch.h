@@ -1,0 +1,92 @@
+// Host-callable launchers of the device kernels (implemented in *.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "d3m_internal.h"
+
+namespace d3m {
+
+// K block placement into panel storage (src/dst offsets in complex elements).
+struct KPlaceDev {
+  int64_t src, dst;
+  int32_t rows, cols, ld_dst, trans;  // trans: dst(r,c) = src[c + r*cols]
+};
+
+// Block-row entry for the residual and the norm of K.
+struct RBlkDev {
+  int64_t koff;
+  int32_t J;     // user id of the column interface
+  int32_t mode;  // 0 diagonal (symmetric, lower read), 1 K_IJ, 2 K_JI^T
+};
+
+// One output tile of the residual: rows [r0, r0+sz) of user interface I.
+struct RTaskDev {
+  int32_t I, r0, sz, pad;
+};
+
+// One output tile of dK: rows [r0, r0+m) x cols [c0, c0+n) of a K block.
+struct DkTaskDev {
+  int64_t koff;
+  int32_t I, J, r0, c0, m, n;
+};
+
+// Per-factor constant tables used by the residual, norm and dK kernels.
+struct UserView {
+  const int32_t* n;       // sizes, user numbering
+  const int64_t* row0;    // user first row of each interface
+  const int64_t* prow0;   // internal first row of each user interface
+  const int32_t* rptr;    // block-row CSR over RBlkDev
+  const RBlkDev* rblk;
+  const int32_t* perm;    // internal row -> user row
+  int64_t N;
+};
+
+// IR control block (device memory).
+struct IrCtrl {
+  int32_t stop;        // 1: converged or given up; later launches return at once
+  int32_t iters;       // refinement steps taken
+  int32_t status;      // 0 or D3M_IR_NOCONV / D3M_NONFINITE
+  int32_t it;          // index of the next eta slot
+  double knorm;        // ||K||_inf
+  double tol;
+  int32_t max_iter;
+  int32_t pad;
+  double eta_hist[32];
+};
+
+hipError_t launch_dag(const DagArgs& a, int prec, int nworkers, hipStream_t s);
+hipError_t launch_level(const Task* tasks, int begin, int end, const InstView* iv, int prec, hipStream_t s);
+hipError_t launch_reset(int32_t* counters, const int32_t* init, int n, int32_t* head, int32_t* abort_flag,
+                        const int32_t* skip, hipStream_t s);
+
+hipError_t launch_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ctrl, double tol, int max_iter,
+                          hipStream_t s);
+hipError_t launch_scatter(const void* K, void* L, const KPlaceDev* kp, int nkp, const KPlaceDev* fills,
+                          int nfill, int prec, hipStream_t s);
+hipError_t launch_knorm(const void* K, const UserView& uv, const RTaskDev* rt, int nrt, IrCtrl* ctrl, hipStream_t s);
+hipError_t launch_perm_in(const void* B, int64_t ld, void* W, int prec, const UserView& uv, int nrhs,
+                          const int32_t* skip, hipStream_t s);
+hipError_t launch_perm_out(const void* W, void* X, int64_t ld, const UserView& uv, int nrhs, hipStream_t s);
+hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64,
+                           double* colmax, const UserView& uv, const RTaskDev* rt, int nrt, int nrhs,
+                           const int32_t* skip, hipStream_t s);
+hipError_t launch_colmax(const void* V, int64_t rows, int nrhs, int64_t ld, int rhs_fastest, double* colmax,
+                         const int32_t* skip, hipStream_t s);
+hipError_t launch_ir_reset(IrCtrl* ctrl, double tol, int max_iter, hipStream_t s);
+hipError_t launch_ir_check(IrCtrl* ctrl, double* rmax, double* xmax, const double* bmax, int nrhs,
+                           int final_step, hipStream_t s);
+hipError_t launch_cvt_down(const void* R64, void* W32, int64_t n, const int32_t* skip, hipStream_t s);
+hipError_t launch_cvt_up(const void* W32, void* X64, int64_t n, hipStream_t s);
+hipError_t launch_axpy_up(const void* W32, void* X64, int64_t n, const int32_t* skip, hipStream_t s);
+hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
+hipError_t launch_dk(const void* Lam, const void* X, int64_t ld, int nrhs, void* dK, const UserView& uv,
+                     const DkTaskDev* dt, int ndt, hipStream_t s);
+hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t s);
+hipError_t launch_all_stop(IrCtrl* const* ctrls, int n, int32_t* out, hipStream_t s);
+hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, const void* A, int64_t lda,
+                             const void* d, const void* B, int64_t ldb, void* C, int64_t ldc, double alpha,
+                             double beta, hipStream_t s);
+hipError_t launch_gemm_bench(int prec, void* buf, int reps, int variant, hipStream_t s);
+
+}  // namespace d3m

@@ -1,0 +1,669 @@
+// Host planner for the dual block LDL^T of D3M (Sec. II of the paper).
+//
+// The paper builds its task graph by symbolically simulating the sequential
+// algorithm and then maps the weighted graph onto processors with a list
+// scheduling heuristic (Sec. II).  Here the same simulation produces the
+// DAG of tile tasks for one GPU, and a list scheduler over the persistent
+// workgroups turns bottom-level priorities into the ticket order in which
+// workgroups take tasks.  The schedule only orders tickets: correctness
+// comes from the device-side dependency counters.
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <queue>
+#include <set>
+#include <unordered_map>
+
+namespace d3m {
+
+// ----------------------------------------------------------------- geometry
+// Interfaces of an a x b x c domain grid (axis 0 first, then 1, then 2; the
+// lower domain's coordinates x slowest, z fastest); interface (ax, d)
+// separates domains d and d + e_ax.
+std::vector<std::array<int32_t, 4>> grid_interfaces(const int32_t* g) {
+  std::vector<std::array<int32_t, 4>> out;
+  for (int ax = 0; ax < 3; ++ax)
+    for (int x = 0; x < g[0]; ++x)
+      for (int y = 0; y < g[1]; ++y)
+        for (int z = 0; z < g[2]; ++z) {
+          int up[3] = {x, y, z};
+          up[ax]++;
+          if (up[0] < g[0] && up[1] < g[1] && up[2] < g[2]) out.push_back({ax, x, y, z});
+        }
+  return out;
+}
+
+namespace {
+void nd_rec(const std::vector<std::array<int32_t, 4>>& f, std::array<int, 3> lo,
+            std::array<int, 3> hi, std::vector<int32_t>& out) {
+  int e[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+  if (e[0] * e[1] * e[2] <= 1) return;
+  int ax = (e[1] > e[0]) ? 1 : 0;
+  if (e[2] > e[ax]) ax = 2;
+  int cut = lo[ax] + e[ax] / 2;
+  auto mid_hi = hi, mid_lo = lo;
+  mid_hi[ax] = cut;
+  mid_lo[ax] = cut;
+  nd_rec(f, lo, mid_hi, out);
+  nd_rec(f, mid_lo, hi, out);
+  for (size_t i = 0; i < f.size(); ++i) {
+    if (f[i][0] != ax || f[i][1 + ax] != cut - 1) continue;
+    bool inside = true;
+    for (int t = 0; t < 3; ++t) {
+      int c0 = f[i][1 + t], c1 = c0 + (t == ax ? 1 : 0);
+      if (c0 < lo[t] || c1 >= hi[t]) inside = false;
+    }
+    if (inside) out.push_back((int32_t)i);
+  }
+}
+}  // namespace
+
+// Nested dissection over the domain grid: cut the longest box axis (ties to
+// the lowest axis) in the middle; order = low half, high half, separator.
+std::vector<int32_t> nd_order(const int32_t* grid) {
+  auto f = grid_interfaces(grid);
+  std::vector<int32_t> out;
+  nd_rec(f, {0, 0, 0}, {grid[0], grid[1], grid[2]}, out);
+  return out;
+}
+
+// Greedy minimum degree on the block graph (with fill), ties by id.
+std::vector<int32_t> min_degree_order(int nb, const std::vector<std::array<int32_t, 2>>& pairs) {
+  std::vector<std::set<int>> adj(nb);
+  for (auto& pr : pairs) {
+    adj[pr[0]].insert(pr[1]);
+    adj[pr[1]].insert(pr[0]);
+  }
+  std::vector<char> done(nb, 0);
+  std::vector<int32_t> out;
+  for (int step = 0; step < nb; ++step) {
+    int best = -1;
+    size_t bd = SIZE_MAX;
+    for (int i = 0; i < nb; ++i)
+      if (!done[i] && adj[i].size() < bd) { bd = adj[i].size(); best = i; }
+    done[best] = 1;
+    out.push_back(best);
+    std::vector<int> nb_(adj[best].begin(), adj[best].end());
+    for (int a : nb_) adj[a].erase(best);
+    for (size_t u = 0; u < nb_.size(); ++u)
+      for (size_t v = u + 1; v < nb_.size(); ++v) {
+        adj[nb_[u]].insert(nb_[v]);
+        adj[nb_[v]].insert(nb_[u]);
+      }
+    adj[best].clear();
+  }
+  return out;
+}
+
+// ----------------------------------------------------------------- schedule
+namespace {
+
+struct GenDag {
+  std::vector<Task> t;
+  std::vector<std::vector<int32_t>> preds;
+  std::vector<double> w;  // estimated microseconds
+  int add(const Task& task, std::vector<int32_t> pr, double weight) {
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    pr.erase(std::remove(pr.begin(), pr.end(), -1), pr.end());
+    t.push_back(task);
+    preds.push_back(std::move(pr));
+    w.push_back(std::max(weight, 0.5));
+    return (int)t.size() - 1;
+  }
+};
+
+// List scheduling of a weighted DAG on P identical workers with bottom-level
+// priority; the ticket order is the simulated start order.
+void finalize(GenDag& g, int P, int sched, TaskDag& out) {
+  const int n = (int)g.t.size();
+  std::vector<std::vector<int32_t>> succ(n);
+  for (int i = 0; i < n; ++i)
+    for (int p : g.preds[i]) succ[p].push_back(i);
+  std::vector<double> bl(n, 0.0);
+  for (int i = n - 1; i >= 0; --i) {
+    double m = 0;
+    for (int s : succ[i]) m = std::max(m, bl[s]);
+    bl[i] = g.w[i] + m;
+  }
+  std::vector<double> start(n, 0.0);
+  double makespan = 0;
+  if (sched == 1) {
+    for (int i = 0; i < n; ++i) start[i] = i;
+  } else {
+    std::vector<int> indeg(n);
+    auto cmp = [&](int a, int b) { return bl[a] < bl[b] || (bl[a] == bl[b] && a > b); };
+    std::priority_queue<int, std::vector<int>, decltype(cmp)> ready(cmp);
+    for (int i = 0; i < n; ++i) {
+      indeg[i] = (int)g.preds[i].size();
+      if (indeg[i] == 0) ready.push(i);
+    }
+    typedef std::pair<double, int> Ev;
+    std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> ev;
+    int free_w = std::max(P, 1);
+    double now = 0;
+    int done = 0;
+    while (done < n) {
+      while (free_w > 0 && !ready.empty()) {
+        int t = ready.top();
+        ready.pop();
+        start[t] = now;
+        ev.push({now + g.w[t], t});
+        --free_w;
+      }
+      if (ev.empty()) break;  // cycle (cannot happen for a generated DAG)
+      Ev e = ev.top();
+      ev.pop();
+      now = e.first;
+      ++free_w;
+      ++done;
+      for (int s : succ[e.second])
+        if (--indeg[s] == 0) ready.push(s);
+    }
+    makespan = now;
+  }
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (start[a] != start[b]) return start[a] < start[b];
+    if (bl[a] != bl[b]) return bl[a] > bl[b];
+    return a < b;
+  });
+  std::vector<int> ticket(n);
+  for (int i = 0; i < n; ++i) ticket[ord[i]] = i;
+  out.tasks.resize(n);
+  out.npred.resize(n);
+  out.gen_of.resize(n);
+  out.succ.clear();
+  for (int k = 0; k < n; ++k) {
+    int i = ord[k];
+    Task t = g.t[i];
+    t.succ_begin = (int32_t)out.succ.size();
+    std::vector<int32_t> s;
+    for (int q : succ[i]) s.push_back(ticket[q]);
+    std::sort(s.begin(), s.end());
+    for (int q : s) out.succ.push_back(q);
+    t.nsucc = (int32_t)s.size();
+    out.tasks[k] = t;
+    out.npred[k] = (int32_t)g.preds[i].size();
+    out.gen_of[k] = i;
+  }
+  out.gpreds = std::move(g.preds);
+  out.weight_us = g.w;
+  out.makespan_us = makespan;
+}
+
+// crude per-workgroup rates used only to weight the schedule (microseconds)
+double w_gemm(double flops) { return 2.0 + flops / 1.5e5; }      // ~150 GFLOP/s per CU
+double w_diag(double n) { return 5.0 + 4.0 / 3.0 * n * n * n / 4e4 + 2 * n; }
+double w_stream(double bytes, double flops) { return 1.5 + std::max(bytes / 2.5e4, flops / 1.5e5); }
+
+int64_t key3(int64_t panel, int64_t g, int64_t c) { return (panel << 40) | (g << 12) | c; }
+
+}  // namespace
+
+// ----------------------------------------------------------------- the plan
+std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair, const int32_t* pairs,
+                       const int32_t* order, const int32_t* grid, int tile, int nworkers, int sched,
+                       int* err) {
+  *err = -1;  // D3M_ERR_ARG
+  if (nb <= 0 || !sizes || npair < 0 || (npair > 0 && !pairs)) return "bad sizes or pairs";
+  if (tile == 0) tile = 128;
+  if (tile < 16 || tile > kTileMax || tile % 16) return "tile must be a multiple of 16 in [16,128]";
+  p.tile = tile;
+  p.nworkers = nworkers > 0 ? nworkers : 256;
+  p.sched = sched;
+  p.nb = nb;
+  p.n.assign(sizes, sizes + nb);
+  for (int i = 0; i < nb; ++i)
+    if (sizes[i] < 1) return "interface size must be >= 1";
+  *err = -2;  // D3M_ERR_PATTERN
+  std::set<std::pair<int, int>> seen;
+  for (int64_t k = 0; k < npair; ++k) {
+    int a = pairs[2 * k], b = pairs[2 * k + 1];
+    if (a < 0 || b < 0 || a >= nb || b >= nb) return "pair id out of range";
+    if (a == b) return "self pair";
+    auto key = std::make_pair(std::min(a, b), std::max(a, b));
+    if (!seen.insert(key).second) return "duplicate pair";
+    p.pairs.push_back({std::max(a, b), std::min(a, b)});
+  }
+  // K offsets: diagonal blocks, then pairs in the given order
+  p.koff.assign(nb + npair + 1, 0);
+  for (int i = 0; i < nb; ++i) p.koff[i + 1] = p.koff[i] + (int64_t)p.n[i] * p.n[i];
+  for (int64_t k = 0; k < npair; ++k)
+    p.koff[nb + k + 1] = p.koff[nb + k] + (int64_t)p.n[p.pairs[k][0]] * p.n[p.pairs[k][1]];
+  // elimination order
+  std::vector<int32_t> ord;
+  if (order) {
+    ord.assign(order, order + nb);
+  } else if (grid) {
+    if (grid[0] < 1 || grid[1] < 1 || grid[2] < 1) return "bad grid";
+    if ((int)grid_interfaces(grid).size() != nb) return "grid interface count differs from nblk";
+    ord = nd_order(grid);
+  } else {
+    ord = min_degree_order(nb, p.pairs);
+  }
+  std::vector<int32_t> chk(ord);
+  std::sort(chk.begin(), chk.end());
+  for (int i = 0; i < nb; ++i)
+    if ((int)chk.size() != nb || chk[i] != i) return "order is not a permutation";
+  p.order = ord;
+  p.pos.assign(nb, 0);
+  for (int k = 0; k < nb; ++k) p.pos[ord[k]] = k;
+  // block fill by elimination in position space
+  std::vector<std::set<int>> adj(nb);
+  for (auto& pr : p.pairs) {
+    int a = p.pos[pr[0]], b = p.pos[pr[1]];
+    adj[a].insert(b);
+    adj[b].insert(a);
+  }
+  p.S.assign(nb, {});
+  for (int I = 0; I < nb; ++I) {
+    std::vector<int32_t> later;
+    for (int J : adj[I])
+      if (J > I) later.push_back(J);
+    for (size_t u = 0; u < later.size(); ++u)
+      for (size_t v = u + 1; v < later.size(); ++v) {
+        adj[later[u]].insert(later[v]);
+        adj[later[v]].insert(later[u]);
+      }
+    p.S[I] = later;  // std::set iteration is sorted
+  }
+  // counts and flops (8 real flops per complex multiply-add)
+  p.L_blocks = 0;
+  p.nnz_L = 0;
+  p.nnz_K = 0;
+  std::vector<int> height(nb, 1);
+  p.etree_height = 0;
+  p.max_S = 0;
+  auto nn = [&](int position) { return (double)p.n[p.order[position]]; };
+  for (int I = 0; I < nb; ++I) {
+    double nI = nn(I);
+    p.nnz_L += (int64_t)nI * ((int64_t)nI + 1) / 2;
+    p.flops_diag += 4.0 / 3.0 * nI * nI * nI;
+    p.L_blocks += p.S[I].size();
+    p.max_S = std::max(p.max_S, (int)p.S[I].size());
+    for (size_t u = 0; u < p.S[I].size(); ++u) {
+      double nJ = nn(p.S[I][u]);
+      p.nnz_L += (int64_t)nJ * (int64_t)nI;
+      p.flops_trsm += 4.0 * nJ * nI * nI;
+      p.flops_update += 4.0 * nJ * nJ * nI;
+      for (size_t v = 0; v < u; ++v) p.flops_update += 8.0 * nJ * nn(p.S[I][v]) * nI;
+    }
+    p.etree_height = std::max(p.etree_height, height[I]);
+    if (!p.S[I].empty()) height[p.S[I][0]] = std::max(height[p.S[I][0]], height[I] + 1);
+  }
+  p.fill_blocks = p.L_blocks - npair;
+  for (int i = 0; i < nb; ++i) p.nnz_K += (int64_t)p.n[i] * (p.n[i] + 1) / 2;
+  for (auto& pr : p.pairs) p.nnz_K += (int64_t)p.n[pr[0]] * p.n[pr[1]];
+
+  // ---- panels, row blocks, tiles
+  p.panels.assign(nb, Panel());
+  p.pblocks.clear();
+  p.tiles.clear();
+  int64_t prow0 = 0, loff = 0, linv = 0;
+  std::vector<std::unordered_map<int, int>> prow_in(nb);  // panel -> (J -> prow)
+  for (int I = 0; I < nb; ++I) {
+    Panel& P = p.panels[I];
+    int nI = p.n[p.order[I]];
+    P.n = nI;
+    P.user = p.order[I];
+    P.prow0 = (int32_t)prow0;
+    P.pb0 = (int32_t)p.pblocks.size();
+    int h = 0;
+    std::vector<int> rowlist{I};
+    for (int J : p.S[I]) rowlist.push_back(J);
+    for (int J : rowlist) {
+      PBlock b;
+      b.J = J;
+      b.prow = h;
+      b.n = p.n[p.order[J]];
+      b.prow0 = 0;  // filled below once all prow0 are known
+      prow_in[I][J] = h;
+      p.pblocks.push_back(b);
+      h += b.n;
+    }
+    P.npb = (int32_t)rowlist.size();
+    P.H = h;
+    P.off = loff;
+    loff += (int64_t)h * nI;
+    // tiles: nt = ceil(n/T), near-equal sizes rounded up to 16
+    int nt = (nI + tile - 1) / tile;
+    int base = (nI + nt - 1) / nt;
+    base = ((base + 15) / 16) * 16;
+    if (base > tile) base = tile;
+    P.tile0 = (int32_t)p.tiles.size();
+    P.nt = nt;
+    for (int c = 0; c < nt; ++c) {
+      Tile t;
+      t.panel = I;
+      t.r0 = c * base;
+      t.sz = (c == nt - 1) ? nI - c * base : base;
+      t.pad = 0;
+      t.linv_off = linv;
+      linv += (int64_t)t.sz * t.sz;
+      p.tiles.push_back(t);
+    }
+    prow0 += nI;
+  }
+  p.N = prow0;
+  p.L_elems = loff;
+  p.Linv_elems = linv;
+  for (auto& b : p.pblocks) b.prow0 = p.panels[b.J].prow0;
+  for (auto& t : p.tiles)
+    if (t.sz <= 0) { *err = -1; return "internal tiling error"; }
+
+  // ---- K placement (scatter) and fill blocks
+  p.kplace.clear();
+  p.fills.clear();
+  for (int i = 0; i < nb; ++i) {
+    int I = p.pos[i];
+    const Panel& P = p.panels[I];
+    p.kplace.push_back({p.koff[i], P.off, P.n, P.n, P.H, 0});
+  }
+  std::set<std::pair<int, int>> orig;  // (row panel J, col panel I), J > I
+  for (size_t k = 0; k < p.pairs.size(); ++k) {
+    int a = p.pairs[k][0], b = p.pairs[k][1];  // K_ab stored, n_a x n_b
+    int pa = p.pos[a], pb = p.pos[b];
+    if (pa > pb) {  // block (a, b) lives in panel b at rows of a: copy as is
+      const Panel& P = p.panels[pb];
+      p.kplace.push_back({p.koff[nb + k], P.off + prow_in[pb][pa], p.n[a], p.n[b], P.H, 0});
+      orig.insert({pa, pb});
+    } else {        // block (b, a) = K_ab^T lives in panel a at rows of b
+      const Panel& P = p.panels[pa];
+      p.kplace.push_back({p.koff[nb + k], P.off + prow_in[pa][pb], p.n[b], p.n[a], P.H, 1});
+      orig.insert({pb, pa});
+    }
+  }
+  for (int I = 0; I < nb; ++I)
+    for (int J : p.S[I])
+      if (!orig.count({J, I})) {
+        const Panel& P = p.panels[I];
+        p.fills.push_back({P.off + prow_in[I][J], p.n[p.order[J]], P.n, P.H});
+      }
+
+  // ---- residual block rows (user numbering)
+  p.rrow.assign(nb, {});
+  for (int i = 0; i < nb; ++i) p.rrow[i].push_back({p.koff[i], i, 0});
+  for (size_t k = 0; k < p.pairs.size(); ++k) {
+    int a = p.pairs[k][0], b = p.pairs[k][1];
+    p.rrow[a].push_back({p.koff[nb + k], b, 1});  // K_ab x_b
+    p.rrow[b].push_back({p.koff[nb + k], a, 2});  // K_ab^T x_a
+  }
+
+  // ---- factor DAG (symbolic simulation of the sequential elimination)
+  const bool want_acc = true;
+  GenDag g;
+  std::vector<std::vector<Access>> facc;
+  std::unordered_map<int64_t, int> lastw;  // storage tile -> last writer
+  auto lw = [&](int64_t k) { auto it = lastw.find(k); return it == lastw.end() ? -1 : it->second; };
+  const int64_t kLinvKey = 1LL << 62, kDKey = 1LL << 61;
+  std::vector<int> strip_task(p.tiles.size(), -1);  // current panel: row tile -> PSTRIP id
+  for (int I = 0; I < nb; ++I) {
+    const Panel& P = p.panels[I];
+    const int nI = P.n;
+    // DIAGF(I)
+    {
+      Task t{};
+      t.kind = TK_DIAGF;
+      t.panel = I;
+      t.m = t.n = t.k = nI;
+      t.lda = P.H;
+      t.dofs = P.prow0;
+      std::vector<int32_t> pr;
+      std::vector<Access> ac;
+      for (int r = 0; r < P.nt; ++r)
+        for (int c = 0; c <= r; ++c) {
+          int64_t k = key3(I, P.tile0 + r, c);
+          pr.push_back(lw(k));
+          ac.push_back({k, true});
+        }
+      ac.push_back({kLinvKey | I, true});
+      ac.push_back({kDKey | I, true});
+      int id = g.add(t, pr, w_diag(nI));
+      for (int r = 0; r < P.nt; ++r)
+        for (int c = 0; c <= r; ++c) lastw[key3(I, P.tile0 + r, c)] = id;
+      if (want_acc) facc.push_back(ac);
+      // PSTRIP for every row tile below the diagonal block
+      for (int b = 1; b < P.npb; ++b) {
+        const PBlock& B = p.pblocks[P.pb0 + b];
+        const Panel& PJ = p.panels[B.J];
+        for (int r = 0; r < PJ.nt; ++r) {
+          const Tile& T = p.tiles[PJ.tile0 + r];
+          Task s{};
+          s.kind = TK_PSTRIP;
+          s.panel = I;
+          s.m = T.sz;
+          s.n = nI;
+          s.k = nI;
+          s.lda = P.H;
+          s.dofs = P.prow0;
+          s.aux = PJ.tile0 + r;
+          s.a_off = P.off + B.prow + T.r0;
+          std::vector<int32_t> pr2{id};
+          std::vector<Access> ac2;
+          for (int c = 0; c < P.nt; ++c) {
+            int64_t k = key3(I, PJ.tile0 + r, c);
+            pr2.push_back(lw(k));
+            ac2.push_back({k, true});
+          }
+          for (int rr = 0; rr < P.nt; ++rr)
+            for (int c = 0; c <= rr; ++c) ac2.push_back({key3(I, P.tile0 + rr, c), false});
+          ac2.push_back({kLinvKey | I, false});
+          ac2.push_back({kDKey | I, false});
+          double fl = 4.0 * T.sz * (double)nI * nI;
+          int sid = g.add(s, pr2, w_gemm(fl) + 2.0 * P.nt);
+          for (int c = 0; c < P.nt; ++c) lastw[key3(I, PJ.tile0 + r, c)] = sid;
+          strip_task[PJ.tile0 + r] = sid;
+          if (want_acc) facc.push_back(ac2);
+        }
+      }
+    }
+    // XUPD: A_JK -= L_JI D_I L_KI^T, tile by tile, J >= K in S_I
+    for (int u = 1; u < P.npb; ++u) {
+      const PBlock& BJ = p.pblocks[P.pb0 + u];
+      const Panel& PJ = p.panels[BJ.J];
+      for (int v = 1; v <= u; ++v) {
+        const PBlock& BK = p.pblocks[P.pb0 + v];
+        const Panel& PK = p.panels[BK.J];
+        const int rowJinK = prow_in[BK.J][BJ.J];
+        for (int r = 0; r < PJ.nt; ++r)
+          for (int s = 0; s < PK.nt; ++s) {
+            if (u == v && r < s) continue;
+            const Tile& TR = p.tiles[PJ.tile0 + r];
+            const Tile& TS = p.tiles[PK.tile0 + s];
+            Task t{};
+            t.kind = TK_XUPD;
+            t.panel = I;
+            t.m = TR.sz;
+            t.n = TS.sz;
+            t.k = nI;
+            t.lda = P.H;
+            t.ldc = PK.H;
+            t.dofs = P.prow0;
+            t.aux = (u == v && r == s) ? 1 : 0;
+            t.a_off = P.off + BJ.prow + TR.r0;
+            t.b_off = P.off + BK.prow + TS.r0;
+            t.c_off = PK.off + rowJinK + TR.r0 + (int64_t)TS.r0 * PK.H;
+            int64_t tk = key3(BK.J, PJ.tile0 + r, s);
+            std::vector<int32_t> pr{strip_task[PJ.tile0 + r], strip_task[PK.tile0 + s], lw(tk)};
+            double fl = 8.0 * TR.sz * (double)TS.sz * nI;
+            int id = g.add(t, pr, w_gemm(fl));
+            lastw[tk] = id;
+            if (want_acc) {
+              std::vector<Access> ac{{tk, true}, {kDKey | I, false}};
+              for (int c = 0; c < P.nt; ++c) {
+                ac.push_back({key3(I, PJ.tile0 + r, c), false});
+                ac.push_back({key3(I, PK.tile0 + s, c), false});
+              }
+              facc.push_back(ac);
+            }
+          }
+      }
+    }
+  }
+  finalize(g, p.nworkers, sched, p.fdag);
+  if (g.t.size() <= 40000) p.facc = std::move(facc);
+
+  // ---- solve DAG: forward (elimination order), then backward (reverse)
+  GenDag sg;
+  std::vector<std::vector<Access>> sacc;
+  std::vector<int> lastb(p.tiles.size(), -1);
+  std::vector<int> fdiag(nb, -1), bdiag(nb, -1);
+  const int64_t kWKey = 1LL << 60;
+  for (int I = 0; I < nb; ++I) {
+    const Panel& P = p.panels[I];
+    Task t{};
+    t.kind = TK_FDIAG;
+    t.panel = I;
+    t.m = P.n;
+    t.lda = P.H;
+    t.dofs = P.prow0;
+    std::vector<int32_t> pr;
+    std::vector<Access> ac;
+    for (int c = 0; c < P.nt; ++c) {
+      pr.push_back(lastb[P.tile0 + c]);
+      ac.push_back({kWKey | (P.tile0 + c), true});
+    }
+    double fl = 4.0 * (double)P.n * P.n;
+    int id = sg.add(t, pr, w_stream(8.0 * P.n * P.n, fl) + 2.0 * P.nt);
+    fdiag[I] = id;
+    for (int c = 0; c < P.nt; ++c) lastb[P.tile0 + c] = id;
+    sacc.push_back(ac);
+    for (int b = 1; b < P.npb; ++b) {
+      const PBlock& B = p.pblocks[P.pb0 + b];
+      const Panel& PJ = p.panels[B.J];
+      for (int r = 0; r < PJ.nt; ++r) {
+        const Tile& T = p.tiles[PJ.tile0 + r];
+        Task u{};
+        u.kind = TK_FUPD;
+        u.panel = I;
+        u.m = T.sz;
+        u.k = P.n;
+        u.lda = P.H;
+        u.dofs = P.prow0;
+        u.aux = PJ.tile0 + r;
+        u.a_off = P.off + B.prow + T.r0;
+        u.b_off = P.prow0;               // rows of z_I in W
+        u.c_off = PJ.prow0 + T.r0;       // rows of b_r in W
+        std::vector<int32_t> pr2{id, lastb[PJ.tile0 + r]};
+        std::vector<Access> ac2{{kWKey | (PJ.tile0 + r), true}};
+        for (int c = 0; c < P.nt; ++c) ac2.push_back({kWKey | (P.tile0 + c), false});
+        double byt = 16.0 * T.sz * P.n, fl2 = 8.0 * T.sz * P.n;
+        int uid = sg.add(u, pr2, w_stream(byt, fl2));
+        lastb[PJ.tile0 + r] = uid;
+        sacc.push_back(ac2);
+      }
+    }
+  }
+  for (int I = nb - 1; I >= 0; --I) {
+    const Panel& P = p.panels[I];
+    std::vector<int32_t> bpred;
+    if (P.npb > 1) {
+      for (int c = 0; c < P.nt; ++c) {
+        const Tile& T = p.tiles[P.tile0 + c];
+        Task t{};
+        t.kind = TK_BUPD;
+        t.panel = I;
+        t.m = T.sz;
+        t.k = P.H - P.n;
+        t.lda = P.H;
+        t.aux = P.tile0 + c;
+        t.c_off = P.prow0 + T.r0;
+        std::vector<int32_t> pr{fdiag[I]};
+        std::vector<Access> ac{{kWKey | (P.tile0 + c), true}};
+        for (int b = 1; b < P.npb; ++b) {
+          int J = p.pblocks[P.pb0 + b].J;
+          pr.push_back(bdiag[J]);
+          for (int cc = 0; cc < p.panels[J].nt; ++cc)
+            ac.push_back({kWKey | (p.panels[J].tile0 + cc), false});
+        }
+        double byt = 16.0 * T.sz * (P.H - P.n), fl = 8.0 * T.sz * (P.H - P.n);
+        int id = sg.add(t, pr, w_stream(byt, fl));
+        bpred.push_back(id);
+        sacc.push_back(ac);
+      }
+    } else {
+      bpred.push_back(fdiag[I]);
+    }
+    Task t{};
+    t.kind = TK_BDIAG;
+    t.panel = I;
+    t.m = P.n;
+    t.lda = P.H;
+    std::vector<Access> ac;
+    for (int c = 0; c < P.nt; ++c) ac.push_back({kWKey | (P.tile0 + c), true});
+    double fl = 4.0 * (double)P.n * P.n;
+    bdiag[I] = sg.add(t, bpred, w_stream(8.0 * P.n * P.n, fl) + 2.0 * P.nt);
+    sacc.push_back(ac);
+  }
+  finalize(sg, p.nworkers, sched, p.sdag);
+  if (sg.t.size() <= 40000) p.sacc = std::move(sacc);
+  *err = 0;
+  return "";
+}
+
+TaskDag merge_dags(const std::vector<const TaskDag*>& dags, int P) {
+  GenDag g;
+  for (size_t i = 0; i < dags.size(); ++i) {
+    const TaskDag& d = *dags[i];
+    const int n = (int)d.tasks.size();
+    const int base = (int)g.t.size();
+    std::vector<Task> gen(n);
+    for (int k = 0; k < n; ++k) gen[d.gen_of[k]] = d.tasks[k];
+    for (int q = 0; q < n; ++q) {
+      Task t = gen[q];
+      t.inst = (int32_t)i;
+      std::vector<int32_t> pr;
+      for (int x : d.gpreds[q]) pr.push_back(x + base);
+      g.t.push_back(t);
+      g.preds.push_back(pr);
+      g.w.push_back(d.weight_us[q]);
+    }
+  }
+  TaskDag out;
+  finalize(g, P, 0, out);
+  return out;
+}
+
+// Serializability: for every pair of tasks touching one resource where at
+// least one writes, the DAG must order them as the sequential elimination
+// (the generation order) does.  Reachability by bitsets in generation order.
+int64_t check_dag(const TaskDag& dag, const std::vector<std::vector<Access>>& acc) {
+  const int n = (int)dag.gpreds.size();
+  if ((int)acc.size() != n) return -1;
+  const int words = (n + 63) / 64;
+  std::vector<uint64_t> reach((size_t)n * words, 0);  // reach[i] = ancestors of i
+  for (int i = 0; i < n; ++i) {
+    uint64_t* ri = &reach[(size_t)i * words];
+    for (int q : dag.gpreds[i]) {
+      if (q >= i) return -2;  // generation order must be topological
+      const uint64_t* rq = &reach[(size_t)q * words];
+      for (int w = 0; w < words; ++w) ri[w] |= rq[w];
+      ri[q / 64] |= 1ULL << (q % 64);
+    }
+  }
+  auto before = [&](int a, int b) {  // a is an ancestor of b
+    return (reach[(size_t)b * words + a / 64] >> (a % 64)) & 1ULL;
+  };
+  std::unordered_map<int64_t, std::vector<std::pair<int, bool>>> by_key;
+  for (int i = 0; i < n; ++i)
+    for (auto& a : acc[i]) by_key[a.key].push_back({i, a.write});
+  int64_t bad = 0;
+  for (auto& kv : by_key) {
+    auto& v = kv.second;
+    for (size_t x = 0; x < v.size(); ++x)
+      for (size_t y = x + 1; y < v.size(); ++y) {
+        if (!v[x].second && !v[y].second) continue;
+        int a = v[x].first, b = v[y].first;
+        if (a == b) continue;
+        int lo = std::min(a, b), hi = std::max(a, b);
+        if (!before(lo, hi)) ++bad;
+      }
+  }
+  return bad;
+}
+
+}  // namespace d3m

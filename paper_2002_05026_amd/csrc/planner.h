@@ -1,0 +1,82 @@
+// Host planner: block pattern -> elimination order -> block fill -> tiles and
+// panels -> task DAGs (factor and solve) -> ticket order.  CPU only.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "d3m_internal.h"
+
+namespace d3m {
+
+struct TaskDag {
+  std::vector<Task> tasks;          // ticket order
+  std::vector<int32_t> succ;        // CSR successor lists (ticket indices)
+  std::vector<int32_t> npred;       // initial dependency counts (ticket order)
+  std::vector<int32_t> gen_of;      // ticket -> generation index
+  // generation-order view, kept for the static checker
+  std::vector<std::vector<int32_t>> gpreds;  // generation index -> predecessors
+  std::vector<double> weight_us;
+  double makespan_us = 0;
+};
+
+// A resource touched by a task (for the static race check).
+struct Access {
+  int64_t key;
+  bool write;
+};
+
+struct PlanImpl {
+  // user problem
+  int nb = 0;
+  std::vector<int32_t> n;                     // sizes, user numbering
+  std::vector<std::array<int32_t, 2>> pairs;  // (I, J) with I > J, user order
+  std::vector<int64_t> koff;                  // K block offsets
+  // elimination
+  std::vector<int32_t> order;                 // position -> user id
+  std::vector<int32_t> pos;                   // user id -> position
+  std::vector<std::vector<int32_t>> S;        // by position: later neighbours (positions, sorted)
+  int64_t fill_blocks = 0, L_blocks = 0, nnz_L = 0, nnz_K = 0;
+  int etree_height = 0, max_S = 0;
+  double flops_diag = 0, flops_trsm = 0, flops_update = 0;
+  // storage
+  int tile = 128;
+  int64_t N = 0;
+  std::vector<Panel> panels;                  // by position
+  std::vector<PBlock> pblocks;
+  std::vector<Tile> tiles;
+  int64_t L_elems = 0, Linv_elems = 0;
+  // K block placement into panels (for the scatter kernel), one per K block
+  struct KPlace { int64_t src, dst; int32_t rows, cols, ld_dst, trans; };
+  std::vector<KPlace> kplace;                 // K blocks -> panel storage
+  struct FillPlace { int64_t dst; int32_t rows, cols, ld_dst; };
+  std::vector<FillPlace> fills;               // blocks of L that start at zero
+  // residual row blocks: for each interface (user id), the K blocks of its block row
+  struct RBlk { int64_t koff; int32_t J; int32_t mode; };  // mode 0 diag(sym), 1 K_IJ, 2 K_JI^T
+  std::vector<std::vector<RBlk>> rrow;
+  // DAGs
+  TaskDag fdag, sdag;
+  std::vector<std::vector<Access>> facc, sacc;  // per generation index (small plans only)
+  int nworkers = 256;
+  int sched = 0;
+};
+
+// Builds everything; returns an empty string or an error message.
+std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair, const int32_t* pairs,
+                       const int32_t* order, const int32_t* grid, int tile, int nworkers, int sched,
+                       int* errcode);
+
+// Union of several instances' DAGs (instance i's tasks get inst = i),
+// re-scheduled together on P workers.
+TaskDag merge_dags(const std::vector<const TaskDag*>& dags, int P);
+
+// Static serializability check of a DAG against its generation order.
+int64_t check_dag(const TaskDag& dag, const std::vector<std::vector<Access>>& acc);
+
+// Grid helpers (the library's own enumeration).
+std::vector<std::array<int32_t, 4>> grid_interfaces(const int32_t* grid);
+std::vector<int32_t> nd_order(const int32_t* grid);
+std::vector<int32_t> min_degree_order(int nb, const std::vector<std::array<int32_t, 2>>& pairs);
+
+}  // namespace d3m
