@@ -91,7 +91,7 @@ typedef struct {
   double growth_dmin;   /* FP32 fallback trigger: min|d| < growth_dmin * max|A_II|; 0 -> 1e-4 */
   double growth_lmax;   /* FP32 fallback trigger: max|L| > growth_lmax; 0 -> 1e2      */
   int32_t fallback;     /* 1 (default via 0): re-factor tripped blocks in FP64; -1 off */
-  int32_t reserved;
+  int32_t timing;       /* 1: record HIP events around every DAG launch (run_info times) */
 } d3m_options;
 
 typedef struct {
@@ -117,6 +117,10 @@ typedef struct {
   double eta_hist[32];  /* eta after x0 and after each refinement step                */
   int32_t fallbacks;    /* diagonal blocks re-factored in FP64                        */
   int32_t hang;         /* watchdog fired                                             */
+  /* with d3m_options.timing: HIP-event time of the persistent DAG launches
+   * since the previous d3m_status_sync (summed), and their counts */
+  double t_factor_dag_ms, t_solve_dag_ms;
+  int32_t n_factor_dag, n_solve_dag;
 } d3m_run_info;
 
 /* Build the symbolic plan.

@@ -44,7 +44,7 @@ class AnalyzeOptions(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("ir_host_sync", ctypes.c_int32),
                 ("growth_dmin", ctypes.c_double), ("growth_lmax", ctypes.c_double),
-                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("timing", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -57,7 +57,8 @@ class PlanInfo(ctypes.Structure):
 class RunInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("ir_iters", ctypes.c_int32), ("pivot_row", ctypes.c_int64),
                 ("eta", ctypes.c_double), ("eta_hist", ctypes.c_double * 32), ("fallbacks", ctypes.c_int32),
-                ("hang", ctypes.c_int32)]
+                ("hang", ctypes.c_int32), ("t_factor_dag_ms", ctypes.c_double), ("t_solve_dag_ms", ctypes.c_double),
+                ("n_factor_dag", ctypes.c_int32), ("n_solve_dag", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -204,7 +205,7 @@ class Factor:
     """A numeric factor bound to a torch-owned device workspace."""
 
     def __init__(self, plan: Plan, precision: int = C128, nrhs_max: int = 1, tol: float = 1e-10,
-                 max_iter: int = 10, ir_host_sync: bool = False, device=None):
+                 max_iter: int = 10, ir_host_sync: bool = False, timing: bool = False, device=None):
         import torch
         self.plan = plan
         self.precision = int(precision)
@@ -214,7 +215,7 @@ class Factor:
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
         self._off = (-base) % 256
-        opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), 0.0, 0.0, 0, 0)
+        opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), 0.0, 0.0, 0, int(bool(timing)))
         h = _vp()
         _check(lib().d3m_factor_bind(plan._h, self.precision, ctypes.c_void_p(base + self._off), nbytes,
                                      self.nrhs_max, ctypes.byref(opts), ctypes.byref(h)), "d3m_factor_bind")
@@ -279,7 +280,9 @@ class Factor:
         code = lib().d3m_status_sync(self._h, ctypes.byref(ri))
         hist = [v for v in ri.eta_hist if v >= 0]
         return {"status": int(code), "ir_iters": int(ri.ir_iters), "pivot_row": int(ri.pivot_row),
-                "eta": float(ri.eta), "eta_hist": hist, "fallbacks": int(ri.fallbacks), "hang": int(ri.hang)}
+                "eta": float(ri.eta), "eta_hist": hist, "fallbacks": int(ri.fallbacks), "hang": int(ri.hang),
+                "t_factor_dag_ms": float(ri.t_factor_dag_ms), "t_solve_dag_ms": float(ri.t_solve_dag_ms),
+                "n_factor_dag": int(ri.n_factor_dag), "n_solve_dag": int(ri.n_solve_dag)}
 
     def block(self, J: int, I: int) -> np.ndarray:
         nJ, nI = int(self.plan.sizes[J]), int(self.plan.sizes[I])
@@ -350,3 +353,18 @@ class Batch:
         _check(lib().d3m_batch_run(self._h, kp, bp, xp, _p32(nr), ld.ctypes.data_as(_i64p), _stream(stream)),
                "d3m_batch_run")
         return Xs
+
+
+def gemm_rate(precision: int = C128) -> float:
+    """Measured aggregate GFLOP/s of the task-body GEMM (256 workgroups, each
+    repeating 128x128x512 complex tile products)."""
+    import torch
+    es = 16 if precision == C128 else 8
+    nbytes = 256 * 3 * 128 * 512 * es
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    best = _i32()
+    nc = _i32()
+    g = (ctypes.c_double * 8)()
+    _check(lib().d3m_tune_gemm(int(precision), _ptr(buf), nbytes, ctypes.byref(best), g, ctypes.byref(nc)),
+           "d3m_tune_gemm")
+    return float(g[0])

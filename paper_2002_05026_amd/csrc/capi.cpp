@@ -140,6 +140,10 @@ struct d3m_factor_s {
   hipStream_t last = nullptr;
   bool factored = false;
   int nworkers = 256;
+  // timing: event pairs around DAG launches, [0] factor, [1] solve
+  static constexpr int kRing = 64;
+  std::vector<hipEvent_t> ev[2];
+  int nev[2] = {0, 0};
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
   UserView uv() const {
     UserView u;
@@ -166,7 +170,7 @@ struct d3m_factor_s {
 
 namespace {
 
-d3m_status run_dag(const d3m_factor_s* f, bool solve, int nrhs, const int32_t* skip, hipStream_t s) {
+d3m_status run_dag(d3m_factor_s* f, bool solve, int nrhs, const int32_t* skip, hipStream_t s) {
   const PlanImpl& p = f->plan->p;
   const TaskDag& dag = solve ? p.sdag : p.fdag;
   DagArgs a;
@@ -183,7 +187,14 @@ d3m_status run_dag(const d3m_factor_s* f, bool solve, int nrhs, const int32_t* s
   a.spin_limit_ns = 20LL * 1000 * 1000 * 1000;  // 20 s on one wait
   HIPCHK(launch_reset(a.counters, f->at<int32_t>(solve ? f->lay.scnt : f->lay.fcnt), a.ntask, a.head,
                       a.abort_flag, skip, s));
+  const int w = solve ? 1 : 0;
+  const bool timed = f->opt.timing && !skip && f->nev[w] < d3m_factor_s::kRing;
+  if (timed) HIPCHK(hipEventRecord(f->ev[w][2 * f->nev[w]], s));
   HIPCHK(launch_dag(a, f->prec, f->nworkers, s));
+  if (timed) {
+    HIPCHK(hipEventRecord(f->ev[w][2 * f->nev[w] + 1], s));
+    f->nev[w]++;
+  }
   return D3M_OK;
 }
 
@@ -371,6 +382,12 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
             up(f->lay.prow0, f->tab.prow0.data(), f->tab.prow0.size() * 8) &&
             up(f->lay.perm, f->tab.perm.data(), f->tab.perm.size() * 4) &&
             up(f->lay.dkt, f->tab.dkt.data(), f->tab.dkt.size() * sizeof(DkTaskDev));
+  if (f->opt.timing) {
+    for (int w = 0; w < 2; ++w) {
+      f->ev[w].resize(2 * d3m_factor_s::kRing);
+      for (auto& e : f->ev[w]) ok = ok && hipEventCreate(&e) == hipSuccess;
+    }
+  }
   // flags, status and refinement control start cleared
   ok = ok && hipMemset(f->ws + f->lay.flags, 0, 16) == hipSuccess &&
        hipMemset(f->ws + f->lay.ctrl, 0, sizeof(IrCtrl)) == hipSuccess &&
@@ -503,6 +520,17 @@ d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
   if (out->status == D3M_OK && c.status) out->status = c.status;
   out->hang = flags[1];
   if (flags[1]) out->status = D3M_ERR_HANG;
+  for (int w = 0; w < 2; ++w) {
+    double tot = 0;
+    for (int i = 0; i < f->nev[w]; ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, f->ev[w][2 * i], f->ev[w][2 * i + 1]));
+      tot += ms;
+    }
+    if (w == 0) { out->t_factor_dag_ms = tot; out->n_factor_dag = f->nev[0]; }
+    else { out->t_solve_dag_ms = tot; out->n_solve_dag = f->nev[1]; }
+    f->nev[w] = 0;
+  }
   return (d3m_status)out->status;
 }
 
@@ -539,7 +567,12 @@ d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out) 
   return D3M_OK;
 }
 
-void d3m_factor_destroy(d3m_factor f) { delete f; }
+void d3m_factor_destroy(d3m_factor f) {
+  if (!f) return;
+  for (int w = 0; w < 2; ++w)
+    for (auto& e : f->ev[w]) hipEventDestroy(e);
+  delete f;
+}
 
 d3m_status d3m_debug_gemm(d3m_precision prec, int32_t m, int32_t n, int32_t k, int32_t amode, int32_t i0,
                           const void* A, int64_t lda, const void* d, const void* B, int64_t ldb, void* C,
