@@ -177,6 +177,17 @@ d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out);
  * diagonal block of I (L strictly below the diagonal, D on it), otherwise
  * L_JI (n_J x n_I) for J in S_I.  Synchronous; for tests and inspection. */
 d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out);
+/* Diagnostics: record, for every ticket of the following DAG launches, four
+ * int64 values {taken, dependencies met, done, workgroup} (times on the
+ * device's 100 MHz constant clock) into dev_buf: factor launches in the
+ * first half, solve launches in the second half (each half must hold
+ * 32 bytes per task, else that DAG is not traced).  NULL stops tracing. */
+d3m_status d3m_factor_set_trace(d3m_factor f, void* dev_buf, size_t bytes);
+/* Task list of the factor (solve = 0) or solve (1) DAG in ticket order:
+ * kinds, panels (elimination position) and m,n,k triples; NULL arrays
+ * query the count only. */
+d3m_status d3m_factor_tasks(d3m_factor f, int32_t solve, int32_t* kinds, int32_t* panels, int32_t* mnk,
+                            int32_t* count);
 void d3m_factor_destroy(d3m_factor f);
 
 /* Batching: many bound factors (their own plans and workspaces) run as one

@@ -86,6 +86,8 @@ SIGNATURES = {
     "d3m_status_sync": (_i32, [_vp, ctypes.POINTER(RunInfo)]),
     "d3m_factor_block": (_i32, [_vp, _i32, _i32, _vp]),
     "d3m_factor_destroy": (None, [_vp]),
+    "d3m_factor_set_trace": (_i32, [_vp, _vp, ctypes.c_size_t]),
+    "d3m_factor_tasks": (_i32, [_vp, _i32, _i32p, _i32p, _i32p, _i32p]),
     "d3m_batch_workspace_bytes": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]),
     "d3m_batch_create": (_i32, [_i32, ctypes.POINTER(_vp), _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     "d3m_batch_run": (_i32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32p, _i64p,
@@ -283,6 +285,26 @@ class Factor:
                 "eta": float(ri.eta), "eta_hist": hist, "fallbacks": int(ri.fallbacks), "hang": int(ri.hang),
                 "t_factor_dag_ms": float(ri.t_factor_dag_ms), "t_solve_dag_ms": float(ri.t_solve_dag_ms),
                 "n_factor_dag": int(ri.n_factor_dag), "n_solve_dag": int(ri.n_solve_dag)}
+
+    def set_trace(self, buf=None):
+        """Record per-task timestamps of later DAG launches into the uint8
+        CUDA tensor buf (None stops)."""
+        if buf is None:
+            _check(lib().d3m_factor_set_trace(self._h, None, 0), "d3m_factor_set_trace")
+        else:
+            _check(lib().d3m_factor_set_trace(self._h, _ptr(buf), buf.numel()), "d3m_factor_set_trace")
+        self._trace = buf
+
+    def tasks(self, solve: bool = False) -> dict:
+        cnt = _i32()
+        _check(lib().d3m_factor_tasks(self._h, int(solve), None, None, None, ctypes.byref(cnt)), "d3m_factor_tasks")
+        n = cnt.value
+        kinds = np.zeros(n, dtype=np.int32)
+        panels = np.zeros(n, dtype=np.int32)
+        mnk = np.zeros(3 * n, dtype=np.int32)
+        _check(lib().d3m_factor_tasks(self._h, int(solve), _p32(kinds), _p32(panels), _p32(mnk), ctypes.byref(cnt)),
+               "d3m_factor_tasks")
+        return {"kind": kinds, "panel": panels, "mnk": mnk.reshape(n, 3)}
 
     def block(self, J: int, I: int) -> np.ndarray:
         nJ, nI = int(self.plan.sizes[J]), int(self.plan.sizes[I])

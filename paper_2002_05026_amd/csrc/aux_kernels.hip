@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const d
     Bo.ld = nrhs;
     Bo.mode = OP_N;
     Bo.i0 = 0;
-    gemm_acc<double>(acc, t.sz, nrhs, nJ, A, nullptr, Bo, lds);
+    gemm_acc<double>(acc, t.sz, nrhs, nJ, A, nullptr, Bo, (lds_char*)lds);
   }
   if (threadIdx.x < GE_TN) cmax[threadIdx.x] = 0ull;
   __syncthreads();
@@ -416,10 +416,10 @@ __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const doubl
   A.ld = B.ld = ld;
   A.p = Lam + ri;
   B.p = X + rj;
-  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, lds);
+  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
   A.p = X + ri;
   B.p = Lam + rj;
-  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, lds);
+  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
   Out<double> o;
   const int nI = uv.n[t.I];
   o.dst = dK + t.koff + t.r0 + (int64_t)t.c0 * nI;
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_debug_gemm(int m, int n, int k, in
   b.ld = ldb;
   b.mode = OP_N;
   b.i0 = 0;
-  gemm_acc<T>(acc, m, n, k, a, d, b, lds);
+  gemm_acc<T>(acc, m, n, k, a, d, b, (lds_char*)lds);
   Out<T> o;
   o.dst = C;
   o.rs = 1;
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type*
     A.i0 = 0;
     B = A;
     B.p = base + 128 * 512;
-    gemm_acc<T>(acc, 128, 128, 512, A, nullptr, B, lds);
+    gemm_acc<T>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
     Out<T> o;
     o.dst = base + 2 * 128 * 512;
     o.rs = 1;

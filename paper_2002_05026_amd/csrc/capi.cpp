@@ -142,6 +142,8 @@ struct d3m_factor_s {
   int nworkers = 256;
   // timing: event pairs around DAG launches, [0] factor, [1] solve
   static constexpr int kRing = 64;
+  void* trace = nullptr;  // optional task trace buffer (caller-owned device memory)
+  size_t trace_bytes = 0;
   std::vector<hipEvent_t> ev[2];
   int nev[2] = {0, 0};
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
@@ -185,6 +187,9 @@ d3m_status run_dag(d3m_factor_s* f, bool solve, int nrhs, const int32_t* skip, h
   a.ntask = (int32_t)dag.tasks.size();
   a.nrhs = nrhs;
   a.spin_limit_ns = 20LL * 1000 * 1000 * 1000;  // 20 s on one wait
+  a.trace = nullptr;
+  if (f->trace && (size_t)a.ntask * 32 <= f->trace_bytes / 2)
+    a.trace = reinterpret_cast<int64_t*>(static_cast<char*>(f->trace) + (solve ? f->trace_bytes / 2 : 0));
   HIPCHK(launch_reset(a.counters, f->at<int32_t>(solve ? f->lay.scnt : f->lay.fcnt), a.ntask, a.head,
                       a.abort_flag, skip, s));
   const int w = solve ? 1 : 0;
@@ -567,6 +572,29 @@ d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out) 
   return D3M_OK;
 }
 
+d3m_status d3m_factor_set_trace(d3m_factor f, void* dev_buf, size_t bytes) {
+  if (!f) return D3M_ERR_ARG;
+  f->trace = dev_buf;
+  f->trace_bytes = dev_buf ? bytes : 0;
+  return D3M_OK;
+}
+
+d3m_status d3m_factor_tasks(d3m_factor f, int32_t solve, int32_t* kinds, int32_t* panels, int32_t* mnk, int32_t* count) {
+  if (!f || !count) return D3M_ERR_ARG;
+  const TaskDag& dag = solve ? f->plan->p.sdag : f->plan->p.fdag;
+  const int n = (int)dag.tasks.size();
+  if (kinds && panels && mnk)
+    for (int i = 0; i < n; ++i) {
+      kinds[i] = dag.tasks[i].kind;
+      panels[i] = dag.tasks[i].panel;
+      mnk[3 * i] = dag.tasks[i].m;
+      mnk[3 * i + 1] = dag.tasks[i].n;
+      mnk[3 * i + 2] = dag.tasks[i].k;
+    }
+  *count = n;
+  return D3M_OK;
+}
+
 void d3m_factor_destroy(d3m_factor f) {
   if (!f) return;
   for (int w = 0; w < 2; ++w)
@@ -667,6 +695,7 @@ d3m_status batch_dag(d3m_batch_s* b, bool solve, const int32_t* skip, hipStream_
   a.ntask = (int32_t)dag.tasks.size();
   a.nrhs = 0;
   a.spin_limit_ns = 20LL * 1000 * 1000 * 1000;
+  a.trace = nullptr;
   HIPCHK(launch_reset(a.counters, b->at<int32_t>(solve ? b->lay.scnt : b->lay.fcnt), a.ntask, a.head, a.abort_flag,
                       skip, s));
   HIPCHK(launch_dag(a, b->prec, b->nworkers, s));

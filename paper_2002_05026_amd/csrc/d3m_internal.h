@@ -17,7 +17,7 @@ enum TaskKind : int32_t {
   TK_XUPD = 3,    // Schur update of one tile: A_rs -= L_rI D_I L_sI^T
   TK_FDIAG = 10,  // forward solve with the diagonal block: z_I = D^-1 L_II^-1 b_I
   TK_FUPD = 11,   // forward update of one row tile: b_r -= L_rI D_I z_I
-  TK_BUPD = 12,   // backward gather of one column tile: z_c -= sum_r L_rc^T x_r
+  TK_BUPD = 12,   // backward push into one column tile: z_c(I) -= L_Jc^T x_J
   TK_BDIAG = 13,  // backward solve with the diagonal block: x_I = L_II^-T t_I
 };
 
@@ -94,6 +94,7 @@ struct DagArgs {
   int32_t ntask;
   int32_t nrhs;          // right-hand sides of a solve launch (0: the instance's own)
   int64_t spin_limit_ns; // watchdog bound on one dependency wait
+  int64_t* trace;        // optional: per ticket {taken, ready, done, workgroup} (100 MHz clock)
 };
 
 }  // namespace d3m

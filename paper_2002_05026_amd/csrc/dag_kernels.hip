@@ -33,12 +33,14 @@ template <typename T> constexpr int fact_lds_bytes() {
 }
 
 template <typename T>
-__device__ __noinline__ void fact_tile(typename Cplx<T>::type* a, int64_t lda, int m, typename Cplx<T>::type* dout,
-                          typename Cplx<T>::type* linv, int row0, int32_t* status, float* gmin_d,
-                          float* gmax_l, char* lds) {
-  typedef typename Cplx<T>::type C;
-  C* L = reinterpret_cast<C*>(lds);
-  C* U = L + kTileMax * (kTileMax + 1) / 2;
+__device__ __noinline__ void fact_tile(typename Cplx<T>::type* a_, int64_t lda, int m, typename Cplx<T>::type* dout_,
+                                       typename Cplx<T>::type* linv_, int row0, int32_t* status, float* gmin_d,
+                                       float* gmax_l, lds_char* lds) {
+  D3M_LDS cpx<T>* L = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
+  D3M_LDS cpx<T>* U = L + kTileMax * (kTileMax + 1) / 2;
+  D3M_GLB cpx<T>* a = gptr_mut<T>(a_);
+  D3M_GLB cpx<T>* dout = gptr_mut<T>(dout_);
+  D3M_GLB cpx<T>* linv = gptr_mut<T>(linv_);
   const int tid = threadIdx.x;
   auto idx = [m](int i, int j) { return j * (2 * m - j + 1) / 2 + (i - j); };
   wg_sync_global();
@@ -47,9 +49,9 @@ __device__ __noinline__ void fact_tile(typename Cplx<T>::type* a, int64_t lda, i
     if (i >= j) L[idx(i, j)] = a[i + (int64_t)j * lda];
   }
   __syncthreads();
-  // right-looking elimination
+  // right-looking elimination: u = L(:,k)/d, trailing lower part -= u L(:,k)^T
   for (int k = 0; k < m; ++k) {
-    C d = L[idx(k, k)];
+    const cpx<T> d = L[idx(k, k)];
     if (tid == 0) {
       T ad = sqrt(d.x * d.x + d.y * d.y);
       bool bad = !(ad > (T)0) || !isfinite(d.x) || !isfinite(d.y);
@@ -59,17 +61,18 @@ __device__ __noinline__ void fact_tile(typename Cplx<T>::type* a, int64_t lda, i
       }
       if (gmin_d) atomicMin(reinterpret_cast<int*>(gmin_d), __float_as_int((float)ad));
     }
-    for (int i = k + 1 + tid; i < m; i += kThreads) U[i] = cdiv(L[idx(i, k)], d);
+    for (int i = k + 1 + tid; i < m; i += kThreads) U[i] = cpx_div(L[idx(i, k)], d);
     __syncthreads();
     const int R = m - k - 1;
     for (int e = tid; e < R * R; e += kThreads) {
       int ii = e % R, jj = e / R;
       if (ii >= jj) {
         int i = k + 1 + ii, j = k + 1 + jj;
-        C u = U[i], l = L[idx(j, k)];
-        C& t = L[idx(i, j)];
+        const cpx<T> u = U[i], l = L[idx(j, k)];
+        cpx<T> t = L[idx(i, j)];
         t.x -= u.x * l.x - u.y * l.y;
         t.y -= u.x * l.y + u.y * l.x;
+        L[idx(i, j)] = t;
       }
     }
     __syncthreads();
@@ -81,7 +84,7 @@ __device__ __noinline__ void fact_tile(typename Cplx<T>::type* a, int64_t lda, i
   for (int e = tid; e < m * m; e += kThreads) {
     int i = e % m, j = e / m;
     if (i >= j) {
-      C v = L[idx(i, j)];
+      const cpx<T> v = L[idx(i, j)];
       a[i + (int64_t)j * lda] = v;
       if (i == j) dout[i] = v;
       else lmax = fmaxf(lmax, (float)sqrt(v.x * v.x + v.y * v.y));
@@ -95,9 +98,9 @@ __device__ __noinline__ void fact_tile(typename Cplx<T>::type* a, int64_t lda, i
     for (int i = j + 1 + tid; i < m; i += kThreads) U[i] = L[idx(i, j)];
     __syncthreads();
     for (int i = j + 1 + tid; i < m; i += kThreads) {
-      C s = U[i];
+      cpx<T> s = U[i];
       for (int q = j + 1; q < i; ++q) {
-        C x = L[idx(i, q)], v = U[q];
+        const cpx<T> x = L[idx(i, q)], v = U[q];
         s.x += x.x * v.x - x.y * v.y;
         s.y += x.x * v.y + x.y * v.x;
       }
@@ -109,7 +112,7 @@ __device__ __noinline__ void fact_tile(typename Cplx<T>::type* a, int64_t lda, i
   }
   for (int e = tid; e < m * m; e += kThreads) {
     int i = e % m, j = e / m;
-    C v;
+    cpx<T> v;
     if (i > j) v = L[idx(i, j)];
     else { v.x = (i == j) ? (T)1 : (T)0; v.y = 0; }
     linv[e] = v;
@@ -125,7 +128,7 @@ template <typename T> struct Ctx {
   C* Li;
   C* W;
   const InstView* iv;
-  char* lds;
+  lds_char* lds;
   int nrhs;
 };
 
@@ -252,19 +255,14 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
 
-// backward gather: z_c -= sum_{J in S_I} L_Jc^T x_J
+// backward push: z_c(I) -= L_Jc^T x_J for one row block J of panel I
 template <typename T>
 __device__ __noinline__ void task_bupd(const Ctx<T>& cx, const Task& t) {
-  const Panel P = cx.iv->panels[t.panel];
-  const Tile tc = cx.iv->tiles[t.aux];
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  for (int b = 1; b < P.npb; ++b) {
-    const PBlock B = cx.iv->pblocks[P.pb0 + b];
-    gemm_acc<T>(acc, t.m, nr, B.n, opn<T>(cx.L + P.off + B.prow + (int64_t)tc.r0 * P.H, P.H, OP_T), nullptr,
-                opn<T>(cx.W + (int64_t)B.prow0 * nr, nr), cx.lds);
-  }
+  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T), nullptr, opn<T>(cx.W + t.b_off * nr, nr),
+              cx.lds);
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
 
@@ -294,7 +292,7 @@ __device__ __noinline__ void task_bdiag(const Ctx<T>& cx, const Task& t) {
 }
 
 template <typename T>
-__device__ void run_task(const Task& t, const InstView* ivs, int nrhs, char* lds) {
+__device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char* lds) {
   typedef typename Cplx<T>::type C;
   Ctx<T> cx;
   cx.iv = ivs + t.inst;
@@ -333,8 +331,8 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
         t = __hip_atomic_fetch_add(a.head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (t >= a.ntask) t = -1;
       }
+      uint64_t t0 = wall_clock64();
       if (t >= 0) {
-        uint64_t t0 = wall_clock64();
         while (__hip_atomic_load(&a.counters[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
           __builtin_amdgcn_s_sleep(2);
           if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { t = -1; break; }
@@ -346,18 +344,27 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
           }
         }
       }
+      // acquire on behalf of the workgroup (its waves share the CU's caches)
+      if (t >= 0) __scoped_atomic_thread_fence(__ATOMIC_ACQUIRE, __MEMORY_SCOPE_DEVICE);
       s_ticket = t;
+      if (t >= 0 && a.trace) {
+        a.trace[4 * t] = (int64_t)t0;
+        a.trace[4 * t + 1] = (int64_t)wall_clock64();
+        a.trace[4 * t + 3] = blockIdx.x;
+      }
     }
     __syncthreads();
     const int t = s_ticket;
     if (t < 0) break;
-    __scoped_atomic_thread_fence(__ATOMIC_ACQUIRE, __MEMORY_SCOPE_DEVICE);
     const Task task = a.tasks[t];
-    run_task<T>(task, a.inst, a.nrhs, lds);
+    run_task<T>(task, a.inst, a.nrhs, (lds_char*)lds);
+    // every wave's stores complete, then one agent-scope release for the
+    // workgroup before the successors are told
     __builtin_amdgcn_s_waitcnt(0);
-    __scoped_atomic_thread_fence(__ATOMIC_RELEASE, __MEMORY_SCOPE_DEVICE);
     __syncthreads();
     if (threadIdx.x == 0) {
+      __scoped_atomic_thread_fence(__ATOMIC_RELEASE, __MEMORY_SCOPE_DEVICE);
+      if (a.trace) a.trace[4 * t + 2] = (int64_t)wall_clock64();
       for (int s = 0; s < task.nsucc; ++s)
         __hip_atomic_fetch_add(&a.counters[a.succ[task.succ_begin + s]], -1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -373,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const Task* tasks, int begin
   int t = begin + blockIdx.x;
   if (t >= end) return;
   const Task task = tasks[t];
-  run_task<T>(task, iv, 0, lds);
+  run_task<T>(task, iv, 0, (lds_char*)lds);
 }
 
 __global__ void k_reset(int32_t* counters, const int32_t* init, int n, int32_t* head, int32_t* abort_flag,

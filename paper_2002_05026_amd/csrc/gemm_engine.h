@@ -65,11 +65,37 @@ __device__ __forceinline__ void wg_sync_global() {
   __syncthreads();
 }
 
+// LDS pointers keep their address space through non-inlined task bodies so
+// that LDS accesses compile to ds_* instructions (a generic pointer would
+// turn them into flat accesses that wait on outstanding global loads).
+#define D3M_LDS __attribute__((address_space(3)))
+#define D3M_GLB __attribute__((address_space(1)))
+typedef D3M_LDS char lds_char;
+
+// Complex pair used for LDS and global accesses inside the engine: a
+// builtin 2-vector, which loads and stores in every address space.
+template <typename T> using cpx = T __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ const D3M_GLB cpx<T>* gptr(const typename Cplx<T>::type* p) {
+  return (const D3M_GLB cpx<T>*)(p);
+}
+template <typename T>
+__device__ __forceinline__ D3M_GLB cpx<T>* gptr_mut(typename Cplx<T>::type* p) {
+  return (D3M_GLB cpx<T>*)(p);
+}
+
 constexpr int GE_TM = 128;        // output tile rows
 constexpr int GE_TN = 128;        // output tile cols
-constexpr int GE_KB = 16;         // complex columns per slab
 constexpr int GE_LDP = GE_TM + 2; // padded LDS row (complex elements)
 constexpr int GE_THREADS = 512;  // 8 waves
+
+// Complex columns per slab: 16 for complex64, 8 for complex128 (keeps the
+// FP64 accumulator, prefetch and fragment registers within 256 per wave).
+template <typename T> struct GeKB;
+template <> struct GeKB<float> { static constexpr int KB = 16, LOG = 4; };
+template <> struct GeKB<double> { static constexpr int KB = 8, LOG = 3; };
+constexpr int GE_KBMAX = 16;
 
 enum OpMode : int { OP_N = 0, OP_T = 1, OP_SYM = 2 };
 
@@ -104,70 +130,112 @@ template <typename T> struct Acc {
 
 // LDS bytes the engine needs.
 template <typename T> constexpr int ge_lds_bytes() {
-  return 2 * GE_KB * GE_LDP * (int)sizeof(typename Cplx<T>::type);
+  return 2 * GeKB<T>::KB * GE_LDP * (int)sizeof(typename Cplx<T>::type);
 }
 
+// Address of A(i, p) for the operand mode (i, p inside the operand).
 template <typename T>
-__device__ __forceinline__ typename Cplx<T>::type ld_op(const Opnd<T>& A, int i, int p) {
-  typedef typename Cplx<T>::type C;
-  if (A.mode == OP_N) return A.p[i + (int64_t)p * A.ld];
-  if (A.mode == OP_T) return A.p[(int64_t)i * A.ld + p];
-  int gi = A.i0 + i;
-  C v = (gi >= p) ? A.p[gi + (int64_t)p * A.ld] : A.p[p + (int64_t)gi * A.ld];
-  return v;
+__device__ __forceinline__ const typename Cplx<T>::type* op_addr(const Opnd<T>& A, int i, int p) {
+  if (A.mode == OP_N) return A.p + i + (int64_t)p * A.ld;
+  if (A.mode == OP_T) return A.p + (int64_t)i * A.ld + p;
+  const int gi = A.i0 + i;
+  return (gi >= p) ? A.p + gi + (int64_t)p * A.ld : A.p + p + (int64_t)gi * A.ld;
 }
 
-// Load one slab (columns [p0, p0+KB)) of A (m rows) and B (n rows) into
-// registers: 4 + 4 complex per thread.
+// Slab registers: raw loads of one slab (columns [p0, p0+KB)) of A (m rows)
+// and B (n rows), 4 + 4 complex per thread, plus the D entries of A's
+// columns.  Loads are issued unconditionally from clamped addresses (out of
+// range elements read the operand's first element) so that they stay in
+// flight while the previous slab is multiplied; masking and the D scaling
+// happen when the slab is written to LDS.
+template <typename T> struct Slab {
+  static constexpr int NE = GeKB<T>::KB * GE_TM / GE_THREADS;  // elements per thread per operand
+  cpx<T> a[NE], b[NE], d[NE];
+  uint32_t amask, bmask;
+};
+
 template <typename T>
-__device__ __forceinline__ void ge_fetch(typename Cplx<T>::type (&ra)[4], typename Cplx<T>::type (&rb)[4],
-                                         const Opnd<T>& A, const typename Cplx<T>::type* dA,
+__device__ __forceinline__ void ge_fetch(Slab<T>& sl, const Opnd<T>& A, const typename Cplx<T>::type* dA,
                                          const Opnd<T>& B, int m, int n, int k, int p0) {
   typedef typename Cplx<T>::type C;
   const int tid = threadIdx.x;
+  constexpr int KB = GeKB<T>::KB, NE = Slab<T>::NE;
+  sl.amask = 0;
+  sl.bmask = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + GE_THREADS * q;
+  for (int q = 0; q < NE; ++q) {
+    const int e = tid + GE_THREADS * q;
     int i, pp;
-    if (A.mode == OP_T) { pp = e & (GE_KB - 1); i = e >> 4; }
+    if (A.mode == OP_T) { pp = e & (KB - 1); i = e >> GeKB<T>::LOG; }
     else { i = e & (GE_TM - 1); pp = e >> 7; }
-    int p = p0 + pp;
-    C v;
-    v.x = 0; v.y = 0;
-    if (i < m && p < k) {
-      v = ld_op(A, i, p);
-      if (dA) v = cmul(v, dA[p]);
-    }
-    ra[q] = v;
+    const int p = p0 + pp;
+    const bool ok = (i < m) & (p < k);
+    const C* src = ok ? op_addr(A, i, p) : A.p;
+    sl.a[q] = *gptr<T>(src);
+    if (dA) sl.d[q] = *gptr<T>(dA + (ok ? p : 0));
+    sl.amask |= (ok ? 1u : 0u) << q;
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + GE_THREADS * q;
-    int j = e & (GE_TN - 1), pp = e >> 7;
-    int p = p0 + pp;
-    C v;
-    v.x = 0; v.y = 0;
-    if (j < n && p < k) v = B.p[j + (int64_t)p * B.ld];
-    rb[q] = v;
+  for (int q = 0; q < NE; ++q) {
+    const int e = tid + GE_THREADS * q;
+    const int j = e & (GE_TN - 1), p = p0 + (e >> 7);
+    const bool ok = (j < n) & (p < k);
+    const C* src = ok ? B.p + j + (int64_t)p * B.ld : B.p;
+    sl.b[q] = *gptr<T>(src);
+    sl.bmask |= (ok ? 1u : 0u) << q;
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void ge_stash(const typename Cplx<T>::type (&ra)[4], const typename Cplx<T>::type (&rb)[4],
-                                         int amode, typename Cplx<T>::type* As, typename Cplx<T>::type* Bs) {
+__device__ __forceinline__ void ge_stash(const Slab<T>& sl, int amode, bool scaled, D3M_LDS cpx<T>* As,
+                                         D3M_LDS cpx<T>* Bs) {
   const int tid = threadIdx.x;
+  constexpr int KB = GeKB<T>::KB, NE = Slab<T>::NE;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + GE_THREADS * q;
+  for (int q = 0; q < NE; ++q) {
+    const int e = tid + GE_THREADS * q;
     int i, pp;
-    if (amode == OP_T) { pp = e & (GE_KB - 1); i = e >> 4; }
+    if (amode == OP_T) { pp = e & (KB - 1); i = e >> GeKB<T>::LOG; }
     else { i = e & (GE_TM - 1); pp = e >> 7; }
-    As[pp * GE_LDP + i] = ra[q];
+    cpx<T> v = sl.a[q];
+    if (scaled) {
+      const cpx<T> d = sl.d[q];
+      const T re = v.x * d.x - v.y * d.y;
+      v.y = v.x * d.y + v.y * d.x;
+      v.x = re;
+    }
+    if (!((sl.amask >> q) & 1u)) { v.x = 0; v.y = 0; }
+    As[pp * GE_LDP + i] = v;
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + GE_THREADS * q;
-    Bs[(e >> 7) * GE_LDP + (e & (GE_TN - 1))] = rb[q];
+  for (int q = 0; q < NE; ++q) {
+    const int e = tid + GE_THREADS * q;
+    cpx<T> v = sl.b[q];
+    if (!((sl.bmask >> q) & 1u)) { v.x = 0; v.y = 0; }
+    Bs[(e >> 7) * GE_LDP + (e & (GE_TN - 1))] = v;
+  }
+}
+
+// One LDS slab into the accumulator: NBJ column blocks (compile time, so the
+// fragment reads of a k-step are issued together ahead of its MFMAs).
+template <typename T, int NBJ>
+__device__ __forceinline__ void ge_mma(Acc<T>& acc, const D3M_LDS cpx<T>* ap, const D3M_LDS cpx<T>* bp) {
+  // one k-step at a time keeps the fragment registers few (the other wave
+  // on the SIMD covers the LDS latency)
+#pragma unroll 1
+  for (int kk = 0; kk < GeKB<T>::KB; kk += 4) {
+    const cpx<T> a0 = ap[kk * GE_LDP];
+    cpx<T> b[NBJ];
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj) b[bj] = bp[kk * GE_LDP + 16 * bj];
+    const T nai = -a0.y;
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj) {
+      acc.re[bj] = mfma16(a0.x, b[bj].x, acc.re[bj]);
+      acc.re[bj] = mfma16(nai, b[bj].y, acc.re[bj]);
+      acc.im[bj] = mfma16(a0.x, b[bj].y, acc.im[bj]);
+      acc.im[bj] = mfma16(a0.y, b[bj].x, acc.im[bj]);
+    }
   }
 }
 
@@ -175,72 +243,96 @@ __device__ __forceinline__ void ge_stash(const typename Cplx<T>::type (&ra)[4], 
 // so callers may overwrite the operands (or LDS) right after it returns.
 template <typename T>
 __device__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
-                         const typename Cplx<T>::type* dA, const Opnd<T>& B, char* lds) {
-  typedef typename Cplx<T>::type C;
-  C* As = reinterpret_cast<C*>(lds);
-  C* Bs = As + GE_KB * GE_LDP;
+                         const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
+  D3M_LDS cpx<T>* As = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
+  constexpr int KB = GeKB<T>::KB;
+  D3M_LDS cpx<T>* Bs = As + KB * GE_LDP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const bool rowok = 16 * w < m;
   const int nbj = (n + 15) >> 4;
-  C ra[4], rb[4];
+  Slab<T> sl;
+  const bool scaled = dA != nullptr;
   wg_sync_global();
   if (k <= 0 || m <= 0 || n <= 0) return;
-  ge_fetch<T>(ra, rb, A, dA, B, m, n, k, 0);
-  for (int p0 = 0; p0 < k; p0 += GE_KB) {
+  ge_fetch<T>(sl, A, dA, B, m, n, k, 0);
+  for (int p0 = 0; p0 < k; p0 += KB) {
     __syncthreads();
-    ge_stash<T>(ra, rb, A.mode, As, Bs);
+    ge_stash<T>(sl, A.mode, scaled, As, Bs);
     __syncthreads();
-    if (p0 + GE_KB < k) ge_fetch<T>(ra, rb, A, dA, B, m, n, k, p0 + GE_KB);
+    if (p0 + KB < k) ge_fetch<T>(sl, A, dA, B, m, n, k, p0 + KB);
     if (rowok) {
-#pragma unroll
-      for (int kk = 0; kk < GE_KB; kk += 4) {
-        const C* ap = As + (kk + lk) * GE_LDP + 16 * w + lr;
-        const C* bp = Bs + (kk + lk) * GE_LDP + lr;
-        const C a0 = ap[0];
-        const T nai = -a0.y;
-#pragma unroll
-        for (int bj = 0; bj < 8; ++bj) {
-          if (bj < nbj) {
-            const C b = bp[16 * bj];
-            acc.re[bj] = mfma16(a0.x, b.x, acc.re[bj]);
-            acc.re[bj] = mfma16(nai, b.y, acc.re[bj]);
-            acc.im[bj] = mfma16(a0.x, b.y, acc.im[bj]);
-            acc.im[bj] = mfma16(a0.y, b.x, acc.im[bj]);
-          }
-        }
-      }
+      const D3M_LDS cpx<T>* ap = As + lk * GE_LDP + 16 * w + lr;
+      const D3M_LDS cpx<T>* bp = Bs + lk * GE_LDP + lr;
+      // three widths only (more variants make the allocator copy the
+      // accumulator); LDS columns beyond n hold zeros
+      if (nbj > 4) ge_mma<T, 8>(acc, ap, bp);
+      else if (nbj > 1) ge_mma<T, 4>(acc, ap, bp);
+      else ge_mma<T, 1>(acc, ap, bp);
     }
   }
   __syncthreads();
 }
 
-// Write the accumulator through the store descriptor.
+template <typename T> __device__ __forceinline__ cpx<T> cpx_div(cpx<T> a, cpx<T> b) {
+  const T den = b.x * b.x + b.y * b.y;
+  cpx<T> r;
+  r.x = (a.x * b.x + a.y * b.y) / den;
+  r.y = (a.y * b.x - a.x * b.y) / den;
+  return r;
+}
+
+// Write the accumulator through the store descriptor.  All loads (beta
+// term, divisors) are issued first from clamped addresses, then the results
+// are formed and stored.
 template <typename T>
 __device__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
-  typedef typename Cplx<T>::type C;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   if (16 * w >= m) return;
-#pragma unroll
-  for (int bj = 0; bj < 8; ++bj) {
-    const int j = 16 * bj + lr;
-    if (16 * bj >= n) continue;
+  D3M_GLB cpx<T>* dst = gptr_mut<T>(o.dst);
+  cpx<T> rd[4];
+  if (o.rowdiv) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 16 * w + acc_row<T>(lk, v);
-      if (i < m && j < n) {
-        C r;
+      rd[v] = *gptr<T>(o.rowdiv + (i < m ? i : 0));
+    }
+  }
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if (64 * half >= n) break;
+    cpx<T> src[4][4], cd[4];
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      const int bj = 4 * half + b4;
+      const int j = 16 * bj + lr;
+      const int jc = j < n ? j : 0;
+      if (o.coldiv) cd[b4] = *gptr<T>(o.coldiv + jc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + acc_row<T>(lk, v);
+        const int ic = i < m ? i : 0;
+        if (o.src) src[b4][v] = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
+      }
+    }
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      const int bj = 4 * half + b4;
+      const int j = 16 * bj + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + acc_row<T>(lk, v);
+        cpx<T> r;
         r.x = o.alpha * acc.re[bj][v];
         r.y = o.alpha * acc.im[bj][v];
         if (o.src) {
-          C s = o.src[(int64_t)i * o.srs + (int64_t)j * o.scs];
-          r.x += o.beta * s.x;
-          r.y += o.beta * s.y;
+          r.x += o.beta * src[b4][v].x;
+          r.y += o.beta * src[b4][v].y;
         }
-        if (o.rowdiv) r = cdiv(r, o.rowdiv[i]);
-        if (o.coldiv) r = cdiv(r, o.coldiv[j]);
-        o.dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+        if (o.rowdiv) r = cpx_div(r, rd[v]);
+        if (o.coldiv) r = cpx_div(r, cd[b4]);
+        if (i < m && j < n) dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
       }
     }
   }

@@ -558,46 +558,56 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       }
     }
   }
-  for (int I = nb - 1; I >= 0; --I) {
-    const Panel& P = p.panels[I];
-    std::vector<int32_t> bpred;
-    if (P.npb > 1) {
-      for (int c = 0; c < P.nt; ++c) {
-        const Tile& T = p.tiles[P.tile0 + c];
-        Task t{};
-        t.kind = TK_BUPD;
-        t.panel = I;
-        t.m = T.sz;
-        t.k = P.H - P.n;
-        t.lda = P.H;
-        t.aux = P.tile0 + c;
-        t.c_off = P.prow0 + T.r0;
-        std::vector<int32_t> pr{fdiag[I]};
-        std::vector<Access> ac{{kWKey | (P.tile0 + c), true}};
-        for (int b = 1; b < P.npb; ++b) {
-          int J = p.pblocks[P.pb0 + b].J;
-          pr.push_back(bdiag[J]);
-          for (int cc = 0; cc < p.panels[J].nt; ++cc)
-            ac.push_back({kWKey | (p.panels[J].tile0 + cc), false});
-        }
-        double byt = 16.0 * T.sz * (P.H - P.n), fl = 8.0 * T.sz * (P.H - P.n);
-        int id = sg.add(t, pr, w_stream(byt, fl));
-        bpred.push_back(id);
-        sacc.push_back(ac);
-      }
-    } else {
-      bpred.push_back(fdiag[I]);
+  // backward: x_J once its tiles have received every push, then push
+  // z_c(I) -= L_Jc^T x_J into each panel I that holds J as a row block
+  std::vector<std::vector<std::pair<int, int>>> holders(nb);  // J -> (panel I, row offset of J in I)
+  for (int I = 0; I < nb; ++I)
+    for (int b = 1; b < p.panels[I].npb; ++b) {
+      const PBlock& B = p.pblocks[p.panels[I].pb0 + b];
+      holders[B.J].push_back({I, B.prow});
     }
+  for (int J = nb - 1; J >= 0; --J) {
+    const Panel& PJ = p.panels[J];
     Task t{};
     t.kind = TK_BDIAG;
-    t.panel = I;
-    t.m = P.n;
-    t.lda = P.H;
+    t.panel = J;
+    t.m = PJ.n;
+    t.lda = PJ.H;
+    std::vector<int32_t> pr{fdiag[J]};
     std::vector<Access> ac;
-    for (int c = 0; c < P.nt; ++c) ac.push_back({kWKey | (P.tile0 + c), true});
-    double fl = 4.0 * (double)P.n * P.n;
-    bdiag[I] = sg.add(t, bpred, w_stream(8.0 * P.n * P.n, fl) + 2.0 * P.nt);
+    for (int c = 0; c < PJ.nt; ++c) {
+      pr.push_back(lastb[PJ.tile0 + c]);
+      ac.push_back({kWKey | (PJ.tile0 + c), true});
+    }
+    double fl = 4.0 * (double)PJ.n * PJ.n;
+    int bid = sg.add(t, pr, w_stream(8.0 * PJ.n * PJ.n, fl) + 2.0 * PJ.nt);
+    bdiag[J] = bid;
+    for (int c = 0; c < PJ.nt; ++c) lastb[PJ.tile0 + c] = bid;
     sacc.push_back(ac);
+    for (auto& h : holders[J]) {
+      const int I = h.first;
+      const Panel& P = p.panels[I];
+      for (int c = 0; c < P.nt; ++c) {
+        const Tile& T = p.tiles[P.tile0 + c];
+        Task u{};
+        u.kind = TK_BUPD;
+        u.panel = I;
+        u.m = T.sz;
+        u.k = PJ.n;
+        u.lda = P.H;
+        u.aux = P.tile0 + c;
+        u.a_off = P.off + h.second + (int64_t)T.r0 * P.H;
+        u.b_off = PJ.prow0;
+        u.c_off = P.prow0 + T.r0;
+        std::vector<int32_t> pr2{bid, lastb[P.tile0 + c]};
+        std::vector<Access> ac2{{kWKey | (P.tile0 + c), true}};
+        for (int cc = 0; cc < PJ.nt; ++cc) ac2.push_back({kWKey | (PJ.tile0 + cc), false});
+        double byt = 16.0 * T.sz * PJ.n, fl2 = 8.0 * T.sz * PJ.n;
+        int uid = sg.add(u, pr2, w_stream(byt, fl2));
+        lastb[P.tile0 + c] = uid;
+        sacc.push_back(ac2);
+      }
+    }
   }
   finalize(sg, p.nworkers, sched, p.sdag);
   if (sg.t.size() <= 40000) p.sacc = std::move(sacc);
