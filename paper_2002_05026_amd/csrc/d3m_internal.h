@@ -12,9 +12,9 @@ constexpr int kThreads = 512;   // threads per workgroup of every MFMA kernel (8
 // factorization, dense triangular solves and dense updates), and of the
 // block forward/backward solve DAG.
 enum TaskKind : int32_t {
-  TK_DIAGF = 1,   // LDL^T of the dense diagonal block of one interface
-  TK_PSTRIP = 2,  // TRSM + D-scale of one row tile below the diagonal block
-  TK_XUPD = 3,    // Schur update of one tile: A_rs -= L_rI D_I L_sI^T
+  TK_XUPD = 3,    // Schur update of one tile: A_rs -= L_rq D_q L_sq^T (q: a tile or a panel)
+  TK_FACT = 4,    // LDL^T of one diagonal tile, its D and the inverse of its unit lower factor
+  TK_TRSM = 5,    // one tile of the panel: L_rc = A_rc Linv_c^T D_c^-1
   TK_FDIAG = 10,  // forward solve with the diagonal block: z_I = D^-1 L_II^-1 b_I
   TK_FUPD = 11,   // forward update of one row tile: b_r -= L_rI D_I z_I
   TK_BUPD = 12,   // backward push into one column tile: z_c(I) -= L_Jc^T x_J

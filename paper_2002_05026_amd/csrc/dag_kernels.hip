@@ -18,107 +18,9 @@
 #include "d3m_internal.h"
 #include "gemm_engine.h"
 #include "launch.h"
+#include "tile_ldlt.h"
 
 namespace d3m {
-
-// ---------------------------------------------------------------- tile LDL^T
-// In-place LDL^T (no pivoting, transposes only) of the m x m tile at `a`
-// (column-major, leading dimension lda, lower triangle read), m <= 128, held
-// packed in LDS.  Writes L strictly below the diagonal and D on it back to
-// `a`, D to dout[0..m), and the full m x m inverse of the unit lower factor
-// to linv (column-major, ld m).  Records the first bad pivot (zero or not
-// finite) as internal row index row0 + k in status[0].
-template <typename T> constexpr int fact_lds_bytes() {
-  return (kTileMax * (kTileMax + 1) / 2 + 2 * kTileMax) * (int)sizeof(typename Cplx<T>::type);
-}
-
-template <typename T>
-__device__ __noinline__ void fact_tile(typename Cplx<T>::type* a_, int64_t lda, int m, typename Cplx<T>::type* dout_,
-                                       typename Cplx<T>::type* linv_, int row0, int32_t* status, float* gmin_d,
-                                       float* gmax_l, lds_char* lds) {
-  D3M_LDS cpx<T>* L = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
-  D3M_LDS cpx<T>* U = L + kTileMax * (kTileMax + 1) / 2;
-  D3M_GLB cpx<T>* a = gptr_mut<T>(a_);
-  D3M_GLB cpx<T>* dout = gptr_mut<T>(dout_);
-  D3M_GLB cpx<T>* linv = gptr_mut<T>(linv_);
-  const int tid = threadIdx.x;
-  auto idx = [m](int i, int j) { return j * (2 * m - j + 1) / 2 + (i - j); };
-  wg_sync_global();
-  for (int e = tid; e < m * m; e += kThreads) {
-    int i = e % m, j = e / m;
-    if (i >= j) L[idx(i, j)] = a[i + (int64_t)j * lda];
-  }
-  __syncthreads();
-  // right-looking elimination: u = L(:,k)/d, trailing lower part -= u L(:,k)^T
-  for (int k = 0; k < m; ++k) {
-    const cpx<T> d = L[idx(k, k)];
-    if (tid == 0) {
-      T ad = sqrt(d.x * d.x + d.y * d.y);
-      bool bad = !(ad > (T)0) || !isfinite(d.x) || !isfinite(d.y);
-      if (bad) {
-        atomicMin(&status[0], row0 + k);
-        atomicAdd(&status[1], 1);
-      }
-      if (gmin_d) atomicMin(reinterpret_cast<int*>(gmin_d), __float_as_int((float)ad));
-    }
-    for (int i = k + 1 + tid; i < m; i += kThreads) U[i] = cpx_div(L[idx(i, k)], d);
-    __syncthreads();
-    const int R = m - k - 1;
-    for (int e = tid; e < R * R; e += kThreads) {
-      int ii = e % R, jj = e / R;
-      if (ii >= jj) {
-        int i = k + 1 + ii, j = k + 1 + jj;
-        const cpx<T> u = U[i], l = L[idx(j, k)];
-        cpx<T> t = L[idx(i, j)];
-        t.x -= u.x * l.x - u.y * l.y;
-        t.y -= u.x * l.y + u.y * l.x;
-        L[idx(i, j)] = t;
-      }
-    }
-    __syncthreads();
-    for (int i = k + 1 + tid; i < m; i += kThreads) L[idx(i, k)] = U[i];
-    __syncthreads();
-  }
-  // L and D back to global; D also to dout
-  float lmax = 0.f;
-  for (int e = tid; e < m * m; e += kThreads) {
-    int i = e % m, j = e / m;
-    if (i >= j) {
-      const cpx<T> v = L[idx(i, j)];
-      a[i + (int64_t)j * lda] = v;
-      if (i == j) dout[i] = v;
-      else lmax = fmaxf(lmax, (float)sqrt(v.x * v.x + v.y * v.y));
-    }
-  }
-  if (gmax_l) atomicMax(reinterpret_cast<int*>(gmax_l), __float_as_int(lmax));
-  __syncthreads();
-  // invert the unit lower factor in place: for j = m-2 .. 0,
-  // Linv(i, j) = -(v_i + sum_{j<q<i} Linv(i, q) v_q), v = L(:, j)
-  for (int j = m - 2; j >= 0; --j) {
-    for (int i = j + 1 + tid; i < m; i += kThreads) U[i] = L[idx(i, j)];
-    __syncthreads();
-    for (int i = j + 1 + tid; i < m; i += kThreads) {
-      cpx<T> s = U[i];
-      for (int q = j + 1; q < i; ++q) {
-        const cpx<T> x = L[idx(i, q)], v = U[q];
-        s.x += x.x * v.x - x.y * v.y;
-        s.y += x.x * v.y + x.y * v.x;
-      }
-      s.x = -s.x;
-      s.y = -s.y;
-      L[idx(i, j)] = s;
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < m * m; e += kThreads) {
-    int i = e % m, j = e / m;
-    cpx<T> v;
-    if (i > j) v = L[idx(i, j)];
-    else { v.x = (i == j) ? (T)1 : (T)0; v.y = 0; }
-    linv[e] = v;
-  }
-  wg_sync_global();
-}
 
 // ---------------------------------------------------------------- task bodies
 template <typename T> struct Ctx {
@@ -158,57 +60,24 @@ __device__ __forceinline__ Out<T> outp(typename Cplx<T>::type* dst, int64_t rs, 
   return o;
 }
 
-// One row strip (rows of a tile, all columns of panel I) through
-// L_rc = (A_rc - sum_{p<c} L_rp D_p L_cp^T) Linv_c^T D_c^-1 for the column
-// tiles c < ncol of I (left-looking inside the strip).
+// LDL^T of diagonal tile c of panel I (TK_FACT)
 template <typename T>
-__device__ void strip_solve(const Ctx<T>& cx, const Panel& P, typename Cplx<T>::type* strip, int m, int ncol) {
-  typedef typename Cplx<T>::type C;
-  for (int c = 0; c < ncol; ++c) {
-    const Tile tc = cx.iv->tiles[P.tile0 + c];
-    C* tile = strip + (int64_t)tc.r0 * P.H;
-    Acc<T> acc;
-    if (tc.r0 > 0) {
-      acc.zero();
-      gemm_acc<T>(acc, m, tc.sz, tc.r0, opn<T>(strip, P.H), cx.D + P.prow0,
-                  opn<T>(cx.L + P.off + tc.r0, P.H), cx.lds);
-      gemm_store<T>(acc, m, tc.sz, outp<T>(tile, 1, P.H, (T)-1, (T)1));
-    }
-    acc.zero();
-    gemm_acc<T>(acc, m, tc.sz, tc.sz, opn<T>(tile, P.H), nullptr, opn<T>(cx.Li + tc.linv_off, tc.sz),
-                cx.lds);
-    Out<T> o = outp<T>(tile, 1, P.H, (T)1, (T)0);
-    o.coldiv = cx.D + P.prow0 + tc.r0;
-    gemm_store<T>(acc, m, tc.sz, o);
-  }
-}
-
-template <typename T>
-__device__ __noinline__ void task_diagf(const Ctx<T>& cx, const Task& t) {
-  typedef typename Cplx<T>::type C;
-  const Panel P = cx.iv->panels[t.panel];
+__device__ __noinline__ void task_fact(const Ctx<T>& cx, const Task& t) {
+  const Tile tc = cx.iv->tiles[t.aux];
   float* gr = cx.iv->growth ? cx.iv->growth + 2 * t.panel : nullptr;
-  for (int r = 0; r < P.nt; ++r) {
-    const Tile tr = cx.iv->tiles[P.tile0 + r];
-    C* strip = cx.L + P.off + tr.r0;
-    strip_solve<T>(cx, P, strip, tr.sz, r);
-    C* diag = strip + (int64_t)tr.r0 * P.H;
-    if (tr.r0 > 0) {
-      Acc<T> acc;
-      acc.zero();
-      gemm_acc<T>(acc, tr.sz, tr.sz, tr.r0, opn<T>(strip, P.H), cx.D + P.prow0, opn<T>(strip, P.H),
-                  cx.lds);
-      gemm_store<T>(acc, tr.sz, tr.sz, outp<T>(diag, 1, P.H, (T)-1, (T)1));
-    }
-    fact_tile<T>(diag, P.H, tr.sz, cx.D + P.prow0 + tr.r0, cx.Li + tr.linv_off, P.prow0 + tr.r0,
-                 cx.iv->status, gr ? gr : nullptr, gr ? gr + 1 : nullptr, cx.lds);
-  }
+  tile_ldlt<T>(cx.L + t.a_off, t.lda, t.m, cx.D + t.dofs, cx.Li + tc.linv_off, t.dofs, cx.iv->status,
+               gr ? gr : nullptr, gr ? gr + 1 : nullptr, cx.lds);
 }
 
+// L_rc = A_rc Linv_c^T D_c^-1, in place (TK_TRSM)
 template <typename T>
-__device__ __noinline__ void task_pstrip(const Ctx<T>& cx, const Task& t) {
-  const Panel P = cx.iv->panels[t.panel];
-  strip_solve<T>(cx, P, cx.L + t.a_off, t.m, P.nt);
+__device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
+  Acc<T> acc;
+  acc.zero();
+  gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr, opn<T>(cx.Li + t.b_off, t.n), cx.lds);
+  Out<T> o = outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0);
+  o.coldiv = cx.D + t.dofs;
+  gemm_store<T>(acc, t.m, t.n, o);
 }
 
 template <typename T>
@@ -303,8 +172,8 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
   cx.lds = lds;
   cx.nrhs = nrhs > 0 ? nrhs : cx.iv->nrhs;
   switch (t.kind) {
-    case TK_DIAGF: task_diagf<T>(cx, t); break;
-    case TK_PSTRIP: task_pstrip<T>(cx, t); break;
+    case TK_FACT: task_fact<T>(cx, t); break;
+    case TK_TRSM: task_trsm<T>(cx, t); break;
     case TK_XUPD: task_xupd<T>(cx, t); break;
     case TK_FDIAG: task_fdiag<T>(cx, t); break;
     case TK_FUPD: task_fupd<T>(cx, t); break;
@@ -315,7 +184,7 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
 }
 
 template <typename T> constexpr int dag_lds_bytes() {
-  return fact_lds_bytes<T>() > ge_lds_bytes<T>() ? fact_lds_bytes<T>() : ge_lds_bytes<T>();
+  return tile_ldlt_lds_bytes<T>() > ge_lds_bytes<T>() ? tile_ldlt_lds_bytes<T>() : ge_lds_bytes<T>();
 }
 
 // ---------------------------------------------------------------- the executor

@@ -197,7 +197,7 @@ void finalize(GenDag& g, int P, int sched, TaskDag& out) {
 
 // crude per-workgroup rates used only to weight the schedule (microseconds)
 double w_gemm(double flops) { return 2.0 + flops / 1.5e5; }      // ~150 GFLOP/s per CU
-double w_diag(double n) { return 5.0 + 4.0 / 3.0 * n * n * n / 4e4 + 2 * n; }
+double w_fact(double n) { return 10.0 + 4.0 / 3.0 * n * n * n / 3e4; }
 double w_stream(double bytes, double flops) { return 1.5 + std::max(bytes / 2.5e4, flops / 1.5e5); }
 
 int64_t key3(int64_t panel, int64_t g, int64_t c) { return (panel << 40) | (g << 12) | c; }
@@ -394,74 +394,93 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   }
 
   // ---- factor DAG (symbolic simulation of the sequential elimination)
-  const bool want_acc = true;
+  // Per panel I, a tiled right-looking LDL^T: FACT of each diagonal tile,
+  // TRSM of every row tile below it inside the panel, IUPD of the panel's
+  // remaining columns; then XUPD of every tile of the blocks (J, K), J, K in
+  // S_I, with the whole panel width as inner dimension.
   GenDag g;
   std::vector<std::vector<Access>> facc;
   std::unordered_map<int64_t, int> lastw;  // storage tile -> last writer
   auto lw = [&](int64_t k) { auto it = lastw.find(k); return it == lastw.end() ? -1 : it->second; };
   const int64_t kLinvKey = 1LL << 62, kDKey = 1LL << 61;
-  std::vector<int> strip_task(p.tiles.size(), -1);  // current panel: row tile -> PSTRIP id
+  const bool want_acc = true;
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
     const int nI = P.n;
-    // DIAGF(I)
-    {
-      Task t{};
-      t.kind = TK_DIAGF;
-      t.panel = I;
-      t.m = t.n = t.k = nI;
-      t.lda = P.H;
-      t.dofs = P.prow0;
-      std::vector<int32_t> pr;
-      std::vector<Access> ac;
-      for (int r = 0; r < P.nt; ++r)
-        for (int c = 0; c <= r; ++c) {
-          int64_t k = key3(I, P.tile0 + r, c);
-          pr.push_back(lw(k));
-          ac.push_back({k, true});
-        }
-      ac.push_back({kLinvKey | I, true});
-      ac.push_back({kDKey | I, true});
-      int id = g.add(t, pr, w_diag(nI));
-      for (int r = 0; r < P.nt; ++r)
-        for (int c = 0; c <= r; ++c) lastw[key3(I, P.tile0 + r, c)] = id;
-      if (want_acc) facc.push_back(ac);
-      // PSTRIP for every row tile below the diagonal block
-      for (int b = 1; b < P.npb; ++b) {
-        const PBlock& B = p.pblocks[P.pb0 + b];
-        const Panel& PJ = p.panels[B.J];
-        for (int r = 0; r < PJ.nt; ++r) {
-          const Tile& T = p.tiles[PJ.tile0 + r];
-          Task s{};
-          s.kind = TK_PSTRIP;
-          s.panel = I;
-          s.m = T.sz;
-          s.n = nI;
-          s.k = nI;
-          s.lda = P.H;
-          s.dofs = P.prow0;
-          s.aux = PJ.tile0 + r;
-          s.a_off = P.off + B.prow + T.r0;
-          std::vector<int32_t> pr2{id};
-          std::vector<Access> ac2;
-          for (int c = 0; c < P.nt; ++c) {
-            int64_t k = key3(I, PJ.tile0 + r, c);
-            pr2.push_back(lw(k));
-            ac2.push_back({k, true});
-          }
-          for (int rr = 0; rr < P.nt; ++rr)
-            for (int c = 0; c <= rr; ++c) ac2.push_back({key3(I, P.tile0 + rr, c), false});
-          ac2.push_back({kLinvKey | I, false});
-          ac2.push_back({kDKey | I, false});
-          double fl = 4.0 * T.sz * (double)nI * nI;
-          int sid = g.add(s, pr2, w_gemm(fl) + 2.0 * P.nt);
-          for (int c = 0; c < P.nt; ++c) lastw[key3(I, PJ.tile0 + r, c)] = sid;
-          strip_task[PJ.tile0 + r] = sid;
-          if (want_acc) facc.push_back(ac2);
+    // row tiles of the panel: (global tile index, row offset in panel)
+    std::vector<std::pair<int, int>> rows;
+    for (int b = 0; b < P.npb; ++b) {
+      const PBlock& B = p.pblocks[P.pb0 + b];
+      const Panel& PJ = p.panels[B.J];
+      for (int r = 0; r < PJ.nt; ++r) rows.push_back({PJ.tile0 + r, B.prow + p.tiles[PJ.tile0 + r].r0});
+    }
+    std::vector<int> trsm_last(rows.size(), -1);  // last TRSM of each row tile
+    for (int c = 0; c < P.nt; ++c) {
+      const Tile& TC = p.tiles[P.tile0 + c];
+      // FACT(I, c)
+      Task f{};
+      f.kind = TK_FACT;
+      f.panel = I;
+      f.m = f.n = f.k = TC.sz;
+      f.lda = P.H;
+      f.aux = P.tile0 + c;
+      f.dofs = P.prow0 + TC.r0;
+      f.a_off = P.off + TC.r0 + (int64_t)TC.r0 * P.H;
+      const int64_t kcc = key3(I, P.tile0 + c, c);
+      int fid = g.add(f, {lw(kcc)}, w_fact(TC.sz));
+      lastw[kcc] = fid;
+      if (want_acc) facc.push_back({{kcc, true}, {kLinvKey | (P.tile0 + c), true}, {kDKey | (P.tile0 + c), true}});
+      // TRSM(I, r, c) for every row tile after c
+      std::vector<int> trsm(rows.size(), -1);
+      for (size_t r = c + 1; r < rows.size(); ++r) {
+        const Tile& TR = p.tiles[rows[r].first];
+        Task t{};
+        t.kind = TK_TRSM;
+        t.panel = I;
+        t.m = TR.sz;
+        t.n = t.k = TC.sz;
+        t.lda = P.H;
+        t.aux = P.tile0 + c;
+        t.dofs = P.prow0 + TC.r0;
+        t.a_off = P.off + rows[r].second + (int64_t)TC.r0 * P.H;
+        t.b_off = TC.linv_off;
+        const int64_t krc = key3(I, rows[r].first, c);
+        int tid = g.add(t, {fid, lw(krc)}, w_gemm(8.0 * TR.sz * (double)TC.sz * TC.sz));
+        lastw[krc] = tid;
+        trsm[r] = tid;
+        trsm_last[r] = tid;
+        if (want_acc)
+          facc.push_back({{krc, true}, {kLinvKey | (P.tile0 + c), false}, {kDKey | (P.tile0 + c), false}});
+      }
+      // IUPD(I, r, s, c): A_rs -= L_rc D_c L_sc^T, s a later tile of I, r >= s
+      for (int s2 = c + 1; s2 < P.nt; ++s2) {
+        const Tile& TS = p.tiles[P.tile0 + s2];
+        for (size_t r = s2; r < rows.size(); ++r) {
+          const Tile& TR = p.tiles[rows[r].first];
+          Task u{};
+          u.kind = TK_XUPD;
+          u.panel = I;
+          u.m = TR.sz;
+          u.n = TS.sz;
+          u.k = TC.sz;
+          u.lda = P.H;
+          u.ldc = P.H;
+          u.dofs = P.prow0 + TC.r0;
+          u.aux = ((int)r == s2) ? 1 : 0;
+          u.a_off = P.off + rows[r].second + (int64_t)TC.r0 * P.H;
+          u.b_off = P.off + rows[s2].second + (int64_t)TC.r0 * P.H;
+          u.c_off = P.off + rows[r].second + (int64_t)TS.r0 * P.H;
+          const int64_t krs = key3(I, rows[r].first, s2);
+          int uid = g.add(u, {trsm[r], trsm[s2], lw(krs)}, w_gemm(8.0 * TR.sz * (double)TS.sz * TC.sz));
+          lastw[krs] = uid;
+          if (want_acc)
+            facc.push_back({{krs, true}, {key3(I, rows[r].first, c), false}, {key3(I, rows[s2].first, c), false},
+                            {kDKey | (P.tile0 + c), false}});
         }
       }
     }
     // XUPD: A_JK -= L_JI D_I L_KI^T, tile by tile, J >= K in S_I
+    const int own = P.nt;
     for (int u = 1; u < P.npb; ++u) {
       const PBlock& BJ = p.pblocks[P.pb0 + u];
       const Panel& PJ = p.panels[BJ.J];
@@ -470,10 +489,16 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         const Panel& PK = p.panels[BK.J];
         const int rowJinK = prow_in[BK.J][BJ.J];
         for (int r = 0; r < PJ.nt; ++r)
-          for (int s = 0; s < PK.nt; ++s) {
-            if (u == v && r < s) continue;
+          for (int s2 = 0; s2 < PK.nt; ++s2) {
+            if (u == v && r < s2) continue;
             const Tile& TR = p.tiles[PJ.tile0 + r];
-            const Tile& TS = p.tiles[PK.tile0 + s];
+            const Tile& TS = p.tiles[PK.tile0 + s2];
+            // index of the row tiles in this panel's row list
+            int ri = -1, si = -1;
+            for (size_t q = own; q < rows.size(); ++q) {
+              if (rows[q].first == PJ.tile0 + r) ri = (int)q;
+              if (rows[q].first == PK.tile0 + s2) si = (int)q;
+            }
             Task t{};
             t.kind = TK_XUPD;
             t.panel = I;
@@ -483,20 +508,21 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
             t.lda = P.H;
             t.ldc = PK.H;
             t.dofs = P.prow0;
-            t.aux = (u == v && r == s) ? 1 : 0;
+            t.aux = (u == v && r == s2) ? 1 : 0;
             t.a_off = P.off + BJ.prow + TR.r0;
             t.b_off = P.off + BK.prow + TS.r0;
             t.c_off = PK.off + rowJinK + TR.r0 + (int64_t)TS.r0 * PK.H;
-            int64_t tk = key3(BK.J, PJ.tile0 + r, s);
-            std::vector<int32_t> pr{strip_task[PJ.tile0 + r], strip_task[PK.tile0 + s], lw(tk)};
+            int64_t tk = key3(BK.J, PJ.tile0 + r, s2);
+            std::vector<int32_t> pr{trsm_last[ri], trsm_last[si], lw(tk)};
             double fl = 8.0 * TR.sz * (double)TS.sz * nI;
             int id = g.add(t, pr, w_gemm(fl));
             lastw[tk] = id;
             if (want_acc) {
-              std::vector<Access> ac{{tk, true}, {kDKey | I, false}};
+              std::vector<Access> ac{{tk, true}};
               for (int c = 0; c < P.nt; ++c) {
                 ac.push_back({key3(I, PJ.tile0 + r, c), false});
-                ac.push_back({key3(I, PK.tile0 + s, c), false});
+                ac.push_back({key3(I, PK.tile0 + s2, c), false});
+                ac.push_back({kDKey | (P.tile0 + c), false});
               }
               facc.push_back(ac);
             }
