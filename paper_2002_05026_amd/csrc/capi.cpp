@@ -26,7 +26,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout of one factor.
 struct Layout {
-  size_t L, D, Linv, W, X64, R64, norms, ctrl, status, growth, counters, flags;
+  size_t L, D, Linv, W, Z, X64, R64, norms, ctrl, status, growth, counters, flags;
   size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, iv;
   size_t kp, fills, rt, rptr, rblk, nI, row0, prow0, perm, dkt;
   size_t total;
@@ -84,6 +84,7 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.D = take(p.N * es);
   l.Linv = take(p.Linv_elems * es);
   l.W = take((size_t)p.N * nrhs_max * es);
+  l.Z = take((size_t)p.N * nrhs_max * es);
   l.X64 = take((size_t)p.N * nrhs_max * 16);
   l.R64 = take((size_t)p.N * nrhs_max * 16);
   l.norms = take(3 * 128 * sizeof(double));
@@ -359,6 +360,7 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
   iv.D = f->ws + f->lay.D;
   iv.Linv = f->ws + f->lay.Linv;
   iv.W = f->ws + f->lay.W;
+  iv.Z = f->ws + f->lay.Z;
   iv.panels = f->at<Panel>(f->lay.panels);
   iv.pblocks = f->at<PBlock>(f->lay.pblocks);
   iv.tiles = f->at<Tile>(f->lay.tiles);

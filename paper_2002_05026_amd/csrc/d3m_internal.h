@@ -15,10 +15,11 @@ enum TaskKind : int32_t {
   TK_XUPD = 3,    // Schur update of one tile: A_rs -= L_rq D_q L_sq^T (q: a tile or a panel)
   TK_FACT = 4,    // LDL^T of one diagonal tile, its D and the inverse of its unit lower factor
   TK_TRSM = 5,    // one tile of the panel: L_rc = A_rc Linv_c^T D_c^-1
-  TK_FDIAG = 10,  // forward solve with the diagonal block: z_I = D^-1 L_II^-1 b_I
+  TK_INV = 6,     // one tile of the inverse of a panel's unit lower diagonal block
   TK_FUPD = 11,   // forward update of one row tile: b_r -= L_rI D_I z_I
   TK_BUPD = 12,   // backward push into one column tile: z_c(I) -= L_Jc^T x_J
-  TK_BDIAG = 13,  // backward solve with the diagonal block: x_I = L_II^-T t_I
+  TK_FTILE = 14,  // forward, one tile of a diagonal block: z_c = D_c^-1 (L_II^-1 b_I)_c
+  TK_BTILE = 15,  // backward, one tile of a diagonal block: x_c = (L_II^-T t_I)_c
 };
 
 // One task, in ticket order.  Offsets are in complex elements, relative to
@@ -42,6 +43,7 @@ static_assert(sizeof(Task) == 80, "Task layout");
 // leading dimension H = n_I + sum_J n_J.
 struct Panel {
   int64_t off;       // element offset of the panel in L storage
+  int64_t ioff;      // element offset of the inverse of its unit lower diagonal block (n x n)
   int32_t H, n;      // rows, cols
   int32_t prow0;     // internal (elimination-order) first row of I
   int32_t tile0;     // first tile index of I in the tile table
@@ -62,7 +64,7 @@ struct PBlock {
 // A tile of an interface: rows [r0, r0+sz) of interface I.
 struct Tile {
   int32_t panel, r0, sz, pad;
-  int64_t linv_off;  // element offset of its inverted unit-lower diagonal tile
+  int64_t linv_off;  // element offset of its diagonal tile inside the panel's inverse block (ld n)
 };
 
 // Per-instance device view.  The element type of L, D, Linv and W is the
@@ -70,8 +72,9 @@ struct Tile {
 struct InstView {
   void* L;           // panel storage
   void* D;           // N diagonal pivots, internal order
-  void* Linv;        // inverted unit-lower diagonal tiles
-  void* W;           // solve vectors, internal order, RHS fastest: W[row * nrhs + j]
+  void* Linv;        // per panel: inverse of the unit lower diagonal block
+  void* W;           // solve vectors, internal order, RHS fastest: W[row * nrhs + j] (b, then x)
+  void* Z;           // second solve vector, same layout (z = D^-1 L^-1 b, then t)
   const Panel* panels;
   const PBlock* pblocks;
   const Tile* tiles;

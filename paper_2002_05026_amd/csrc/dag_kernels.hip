@@ -29,6 +29,7 @@ template <typename T> struct Ctx {
   C* D;
   C* Li;
   C* W;
+  C* Z;
   const InstView* iv;
   lds_char* lds;
   int nrhs;
@@ -65,7 +66,8 @@ template <typename T>
 __device__ __noinline__ void task_fact(const Ctx<T>& cx, const Task& t) {
   const Tile tc = cx.iv->tiles[t.aux];
   float* gr = cx.iv->growth ? cx.iv->growth + 2 * t.panel : nullptr;
-  tile_ldlt<T>(cx.L + t.a_off, t.lda, t.m, cx.D + t.dofs, cx.Li + tc.linv_off, t.dofs, cx.iv->status,
+  const Panel P = cx.iv->panels[t.panel];
+  tile_ldlt<T>(cx.L + t.a_off, t.lda, t.m, cx.D + t.dofs, cx.Li + tc.linv_off, P.n, t.dofs, cx.iv->status,
                gr ? gr : nullptr, gr ? gr + 1 : nullptr, cx.lds);
 }
 
@@ -74,7 +76,7 @@ template <typename T>
 __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr, opn<T>(cx.Li + t.b_off, t.n), cx.lds);
+  gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr, opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
   Out<T> o = outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0);
   o.coldiv = cx.D + t.dofs;
   gemm_store<T>(acc, t.m, t.n, o);
@@ -89,28 +91,39 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
   gemm_store<T>(acc, t.m, t.n, outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1));
 }
 
-// forward: z_c = D_c^-1 Linv_c (b_c - sum_{p<c} L_cp D_p z_p), tile by tile
+// tile (r, c) of the inverse of panel I's unit lower diagonal block:
+// Y^T = (sum_{c <= q < r} L_rq Linv_qc)^T into the unused upper tile (c, r),
+// then Linv_rc = -Linv_rr Y (TK_INV)
 template <typename T>
-__device__ __noinline__ void task_fdiag(const Ctx<T>& cx, const Task& t) {
-  typedef typename Cplx<T>::type C;
+__device__ __noinline__ void task_inv(const Ctx<T>& cx, const Task& t) {
   const Panel P = cx.iv->panels[t.panel];
+  const Tile tr = cx.iv->tiles[t.aux], tc = cx.iv->tiles[t.dofs];
+  typedef typename Cplx<T>::type C;
+  C* Lb = cx.Li + P.ioff;
+  const int n = P.n;
+  Acc<T> acc;
+  acc.zero();
+  gemm_acc<T>(acc, tc.sz, tr.sz, tr.r0 - tc.r0, opn<T>(Lb + tc.r0 + (int64_t)tc.r0 * n, n, OP_T), nullptr,
+              opn<T>(cx.L + P.off + tr.r0 + (int64_t)tc.r0 * P.H, P.H), cx.lds);
+  C* stage = Lb + tc.r0 + (int64_t)tr.r0 * n;
+  gemm_store<T>(acc, tc.sz, tr.sz, outp<T>(stage, 1, n, (T)1, (T)0));
+  acc.zero();
+  gemm_acc<T>(acc, tr.sz, tc.sz, tr.sz, opn<T>(Lb + tr.r0 + (int64_t)tr.r0 * n, n), nullptr, opn<T>(stage, n),
+              cx.lds);
+  gemm_store<T>(acc, tr.sz, tc.sz, outp<T>(Lb + tr.r0 + (int64_t)tc.r0 * n, 1, n, (T)-1, (T)0));
+}
+
+// forward, one tile: z_c = D_c^-1 sum_{p < r0_c + sz_c} Linv_II(c, p) b_p
+template <typename T>
+__device__ __noinline__ void task_ftile(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
-  for (int c = 0; c < P.nt; ++c) {
-    const Tile tc = cx.iv->tiles[P.tile0 + c];
-    C* wc = cx.W + (int64_t)(P.prow0 + tc.r0) * nr;
-    Acc<T> acc;
-    if (tc.r0 > 0) {
-      acc.zero();
-      gemm_acc<T>(acc, tc.sz, nr, tc.r0, opn<T>(cx.L + P.off + tc.r0, P.H), cx.D + P.prow0,
-                  opn<T>(cx.W + (int64_t)P.prow0 * nr, nr), cx.lds);
-      gemm_store<T>(acc, tc.sz, nr, outp<T>(wc, nr, 1, (T)-1, (T)1));
-    }
-    acc.zero();
-    gemm_acc<T>(acc, tc.sz, nr, tc.sz, opn<T>(cx.Li + tc.linv_off, tc.sz), nullptr, opn<T>(wc, nr), cx.lds);
-    Out<T> o = outp<T>(wc, nr, 1, (T)1, (T)0);
-    o.rowdiv = cx.D + P.prow0 + tc.r0;
-    gemm_store<T>(acc, tc.sz, nr, o);
-  }
+  Acc<T> acc;
+  acc.zero();
+  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda), nullptr, opn<T>(cx.W + t.b_off * nr, nr),
+              cx.lds);
+  Out<T> o = outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)1, (T)0);
+  o.rowdiv = cx.D + t.dofs;
+  gemm_store<T>(acc, t.m, nr, o);
 }
 
 // forward update: b_r -= L_rI D_I z_I
@@ -120,11 +133,11 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
   gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.L + t.a_off, t.lda), cx.D + t.dofs,
-              opn<T>(cx.W + t.b_off * nr, nr), cx.lds);
+              opn<T>(cx.Z + t.b_off * nr, nr), cx.lds);
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
 
-// backward push: z_c(I) -= L_Jc^T x_J for one row block J of panel I
+// backward push: t_c(I) -= L_Jc^T x_J for one row block J of panel I
 template <typename T>
 __device__ __noinline__ void task_bupd(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
@@ -132,32 +145,18 @@ __device__ __noinline__ void task_bupd(const Ctx<T>& cx, const Task& t) {
   acc.zero();
   gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T), nullptr, opn<T>(cx.W + t.b_off * nr, nr),
               cx.lds);
-  gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
+  gemm_store<T>(acc, t.m, nr, outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
 
-// backward: x_c = Linv_c^T (t_c - sum_{p>c} L_pc^T x_p), last tile first
+// backward, one tile: x_c = sum_{p >= r0_c} Linv_II(p, c) t_p
 template <typename T>
-__device__ __noinline__ void task_bdiag(const Ctx<T>& cx, const Task& t) {
-  typedef typename Cplx<T>::type C;
-  const Panel P = cx.iv->panels[t.panel];
+__device__ __noinline__ void task_btile(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
-  for (int c = P.nt - 1; c >= 0; --c) {
-    const Tile tc = cx.iv->tiles[P.tile0 + c];
-    C* wc = cx.W + (int64_t)(P.prow0 + tc.r0) * nr;
-    const int below = tc.r0 + tc.sz;
-    Acc<T> acc;
-    if (below < P.n) {
-      acc.zero();
-      gemm_acc<T>(acc, tc.sz, nr, P.n - below,
-                  opn<T>(cx.L + P.off + below + (int64_t)tc.r0 * P.H, P.H, OP_T), nullptr,
-                  opn<T>(cx.W + (int64_t)(P.prow0 + below) * nr, nr), cx.lds);
-      gemm_store<T>(acc, tc.sz, nr, outp<T>(wc, nr, 1, (T)-1, (T)1));
-    }
-    acc.zero();
-    gemm_acc<T>(acc, tc.sz, nr, tc.sz, opn<T>(cx.Li + tc.linv_off, tc.sz, OP_T), nullptr, opn<T>(wc, nr),
-                cx.lds);
-    gemm_store<T>(acc, tc.sz, nr, outp<T>(wc, nr, 1, (T)1, (T)0));
-  }
+  Acc<T> acc;
+  acc.zero();
+  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda, OP_T), nullptr, opn<T>(cx.Z + t.b_off * nr, nr),
+              cx.lds);
+  gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)1, (T)0));
 }
 
 template <typename T>
@@ -169,16 +168,18 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
   cx.D = reinterpret_cast<C*>(cx.iv->D);
   cx.Li = reinterpret_cast<C*>(cx.iv->Linv);
   cx.W = reinterpret_cast<C*>(cx.iv->W);
+  cx.Z = reinterpret_cast<C*>(cx.iv->Z);
   cx.lds = lds;
   cx.nrhs = nrhs > 0 ? nrhs : cx.iv->nrhs;
   switch (t.kind) {
     case TK_FACT: task_fact<T>(cx, t); break;
     case TK_TRSM: task_trsm<T>(cx, t); break;
     case TK_XUPD: task_xupd<T>(cx, t); break;
-    case TK_FDIAG: task_fdiag<T>(cx, t); break;
+    case TK_INV: task_inv<T>(cx, t); break;
+    case TK_FTILE: task_ftile<T>(cx, t); break;
     case TK_FUPD: task_fupd<T>(cx, t); break;
     case TK_BUPD: task_bupd<T>(cx, t); break;
-    case TK_BDIAG: task_bdiag<T>(cx, t); break;
+    case TK_BTILE: task_btile<T>(cx, t); break;
     default: break;
   }
 }

@@ -129,8 +129,9 @@ template <typename T> struct Acc {
 };
 
 // LDS bytes the engine needs.
+// Two slab buffers (double buffering), each holding the A and B slabs.
 template <typename T> constexpr int ge_lds_bytes() {
-  return 2 * GeKB<T>::KB * GE_LDP * (int)sizeof(typename Cplx<T>::type);
+  return 2 * 2 * GeKB<T>::KB * GE_LDP * (int)sizeof(typename Cplx<T>::type);
 }
 
 // Address of A(i, p) for the operand mode (i, p inside the operand).
@@ -244,9 +245,9 @@ __device__ __forceinline__ void ge_mma(Acc<T>& acc, const D3M_LDS cpx<T>* ap, co
 template <typename T>
 __device__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
-  D3M_LDS cpx<T>* As = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   constexpr int KB = GeKB<T>::KB;
-  D3M_LDS cpx<T>* Bs = As + KB * GE_LDP;
+  D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
+  D3M_LDS cpx<T>* buf1 = buf0 + 2 * KB * GE_LDP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const bool rowok = 16 * w < m;
@@ -255,23 +256,32 @@ __device__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
   const bool scaled = dA != nullptr;
   wg_sync_global();
   if (k <= 0 || m <= 0 || n <= 0) return;
+  // slab s lives in buffer s & 1: while slab s is multiplied, slab s+1 is
+  // written to the other buffer and slab s+2 is loaded into registers; one
+  // barrier per slab
   ge_fetch<T>(sl, A, dA, B, m, n, k, 0);
-  for (int p0 = 0; p0 < k; p0 += KB) {
-    __syncthreads();
-    ge_stash<T>(sl, A.mode, scaled, As, Bs);
-    __syncthreads();
-    if (p0 + KB < k) ge_fetch<T>(sl, A, dA, B, m, n, k, p0 + KB);
+  ge_stash<T>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+  if (KB < k) ge_fetch<T>(sl, A, dA, B, m, n, k, KB);
+  __syncthreads();
+  int s = 0;
+  for (int p0 = 0; p0 < k; p0 += KB, ++s) {
+    D3M_LDS cpx<T>* cur = (s & 1) ? buf1 : buf0;
+    D3M_LDS cpx<T>* nxt = (s & 1) ? buf0 : buf1;
     if (rowok) {
-      const D3M_LDS cpx<T>* ap = As + lk * GE_LDP + 16 * w + lr;
-      const D3M_LDS cpx<T>* bp = Bs + lk * GE_LDP + lr;
+      const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
+      const D3M_LDS cpx<T>* bp = cur + KB * GE_LDP + lk * GE_LDP + lr;
       // three widths only (more variants make the allocator copy the
       // accumulator); LDS columns beyond n hold zeros
       if (nbj > 4) ge_mma<T, 8>(acc, ap, bp);
       else if (nbj > 1) ge_mma<T, 4>(acc, ap, bp);
       else ge_mma<T, 1>(acc, ap, bp);
     }
+    if (p0 + KB < k) {
+      ge_stash<T>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
+      if (p0 + 2 * KB < k) ge_fetch<T>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 template <typename T> __device__ __forceinline__ cpx<T> cpx_div(cpx<T> a, cpx<T> b) {

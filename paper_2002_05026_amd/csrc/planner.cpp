@@ -329,6 +329,8 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
     P.H = h;
     P.off = loff;
     loff += (int64_t)h * nI;
+    P.ioff = linv;
+    linv += (int64_t)nI * nI;
     // tiles: nt = ceil(n/T), near-equal sizes rounded up to 16
     int nt = (nI + tile - 1) / tile;
     int base = (nI + nt - 1) / nt;
@@ -342,8 +344,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       t.r0 = c * base;
       t.sz = (c == nt - 1) ? nI - c * base : base;
       t.pad = 0;
-      t.linv_off = linv;
-      linv += (int64_t)t.sz * t.sz;
+      t.linv_off = P.ioff + t.r0 + (int64_t)t.r0 * nI;
       p.tiles.push_back(t);
     }
     prow0 += nI;
@@ -402,7 +403,8 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   std::vector<std::vector<Access>> facc;
   std::unordered_map<int64_t, int> lastw;  // storage tile -> last writer
   auto lw = [&](int64_t k) { auto it = lastw.find(k); return it == lastw.end() ? -1 : it->second; };
-  const int64_t kLinvKey = 1LL << 62, kDKey = 1LL << 61;
+  const int64_t kDKey = 1LL << 61;
+  auto inv_key = [](int64_t a, int64_t b) { return (1LL << 59) | (a << 20) | b; };
   const bool want_acc = true;
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
@@ -429,7 +431,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       const int64_t kcc = key3(I, P.tile0 + c, c);
       int fid = g.add(f, {lw(kcc)}, w_fact(TC.sz));
       lastw[kcc] = fid;
-      if (want_acc) facc.push_back({{kcc, true}, {kLinvKey | (P.tile0 + c), true}, {kDKey | (P.tile0 + c), true}});
+      if (want_acc) facc.push_back({{kcc, true}, {inv_key(P.tile0 + c, P.tile0 + c), true}, {kDKey | (P.tile0 + c), true}});
       // TRSM(I, r, c) for every row tile after c
       std::vector<int> trsm(rows.size(), -1);
       for (size_t r = c + 1; r < rows.size(); ++r) {
@@ -444,13 +446,14 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         t.dofs = P.prow0 + TC.r0;
         t.a_off = P.off + rows[r].second + (int64_t)TC.r0 * P.H;
         t.b_off = TC.linv_off;
+        t.ldc = nI;  // leading dimension of the inverse block
         const int64_t krc = key3(I, rows[r].first, c);
         int tid = g.add(t, {fid, lw(krc)}, w_gemm(8.0 * TR.sz * (double)TC.sz * TC.sz));
         lastw[krc] = tid;
         trsm[r] = tid;
         trsm_last[r] = tid;
         if (want_acc)
-          facc.push_back({{krc, true}, {kLinvKey | (P.tile0 + c), false}, {kDKey | (P.tile0 + c), false}});
+          facc.push_back({{krc, true}, {inv_key(P.tile0 + c, P.tile0 + c), false}, {kDKey | (P.tile0 + c), false}});
       }
       // IUPD(I, r, s, c): A_rs -= L_rc D_c L_sc^T, s a later tile of I, r >= s
       for (int s2 = c + 1; s2 < P.nt; ++s2) {
@@ -476,6 +479,42 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
           if (want_acc)
             facc.push_back({{krs, true}, {key3(I, rows[r].first, c), false}, {key3(I, rows[s2].first, c), false},
                             {kDKey | (P.tile0 + c), false}});
+        }
+      }
+    }
+    // INV(I, r, c): tile (r, c) of the inverse of the unit lower diagonal
+    // block, Linv_rc = -Linv_rr sum_{c <= q < r} L_rq Linv_qc; only the
+    // solve needs it, so nothing in the factor waits for it
+    {
+      std::vector<int> fact_of(P.nt);
+      for (int c = 0; c < P.nt; ++c) fact_of[c] = lw(key3(I, P.tile0 + c, c));
+      for (int c = 0; c < P.nt; ++c) {
+        const Tile& TC = p.tiles[P.tile0 + c];
+        int prev = -1;
+        for (int r = c + 1; r < P.nt; ++r) {
+          const Tile& TR = p.tiles[P.tile0 + r];
+          Task v{};
+          v.kind = TK_INV;
+          v.panel = I;
+          v.m = TR.sz;
+          v.n = TC.sz;
+          v.k = TR.r0 - TC.r0;
+          v.aux = P.tile0 + r;
+          v.dofs = P.tile0 + c;
+          std::vector<int32_t> pr{fact_of[r], fact_of[c], prev};
+          double fl = 8.0 * TC.sz * (double)TR.sz * (TR.r0 - TC.r0) + 8.0 * TR.sz * (double)TC.sz * TR.sz;
+          int vid = g.add(v, pr, w_gemm(fl));
+          prev = vid;
+          if (want_acc) {
+            std::vector<Access> ac{{inv_key(P.tile0 + r, P.tile0 + c), true},
+                                   {inv_key(P.tile0 + c, P.tile0 + r), true},
+                                   {inv_key(P.tile0 + r, P.tile0 + r), false}};
+            for (int q = c; q < r; ++q) {
+              ac.push_back({key3(I, P.tile0 + r, q), false});
+              ac.push_back({inv_key(P.tile0 + q, P.tile0 + c), false});
+            }
+            facc.push_back(ac);
+          }
         }
       }
     }
@@ -533,31 +572,39 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   finalize(g, p.nworkers, sched, p.fdag);
   if (g.t.size() <= 40000) p.facc = std::move(facc);
 
-  // ---- solve DAG: forward (elimination order), then backward (reverse)
+  // ---- solve DAG: forward (elimination order), then backward (reverse).
+  // W holds b (then x), Z holds z = D^-1 L^-1 b (then t); the diagonal
+  // blocks are applied through their precomputed inverses, one tile each.
   GenDag sg;
   std::vector<std::vector<Access>> sacc;
-  std::vector<int> lastb(p.tiles.size(), -1);
-  std::vector<int> fdiag(nb, -1), bdiag(nb, -1);
-  const int64_t kWKey = 1LL << 60;
+  std::vector<int> lastb(p.tiles.size(), -1), lastz(p.tiles.size(), -1);
+  std::vector<std::vector<int>> ftile(nb), btile(nb);
+  const int64_t kWKey = 1LL << 60, kZKey = 1LL << 58;
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
-    Task t{};
-    t.kind = TK_FDIAG;
-    t.panel = I;
-    t.m = P.n;
-    t.lda = P.H;
-    t.dofs = P.prow0;
-    std::vector<int32_t> pr;
-    std::vector<Access> ac;
+    std::vector<int32_t> inpr;
+    for (int c = 0; c < P.nt; ++c) inpr.push_back(lastb[P.tile0 + c]);
     for (int c = 0; c < P.nt; ++c) {
-      pr.push_back(lastb[P.tile0 + c]);
-      ac.push_back({kWKey | (P.tile0 + c), true});
+      const Tile& T = p.tiles[P.tile0 + c];
+      Task t{};
+      t.kind = TK_FTILE;
+      t.panel = I;
+      t.m = T.sz;
+      t.k = T.r0 + T.sz;
+      t.lda = P.n;
+      t.aux = P.tile0 + c;
+      t.a_off = P.ioff + T.r0;
+      t.b_off = P.prow0;
+      t.c_off = P.prow0 + T.r0;
+      t.dofs = P.prow0 + T.r0;
+      std::vector<Access> ac{{kZKey | (P.tile0 + c), true}};
+      for (int q = 0; q < P.nt; ++q) ac.push_back({kWKey | (P.tile0 + q), false});
+      double fl = 8.0 * T.sz * (double)(T.r0 + T.sz);
+      int id = sg.add(t, inpr, w_stream(8.0 * T.sz * (T.r0 + T.sz), fl));
+      ftile[I].push_back(id);
+      lastz[P.tile0 + c] = id;
+      sacc.push_back(ac);
     }
-    double fl = 4.0 * (double)P.n * P.n;
-    int id = sg.add(t, pr, w_stream(8.0 * P.n * P.n, fl) + 2.0 * P.nt);
-    fdiag[I] = id;
-    for (int c = 0; c < P.nt; ++c) lastb[P.tile0 + c] = id;
-    sacc.push_back(ac);
     for (int b = 1; b < P.npb; ++b) {
       const PBlock& B = p.pblocks[P.pb0 + b];
       const Panel& PJ = p.panels[B.J];
@@ -572,11 +619,12 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         u.dofs = P.prow0;
         u.aux = PJ.tile0 + r;
         u.a_off = P.off + B.prow + T.r0;
-        u.b_off = P.prow0;               // rows of z_I in W
+        u.b_off = P.prow0;               // rows of z_I in Z
         u.c_off = PJ.prow0 + T.r0;       // rows of b_r in W
-        std::vector<int32_t> pr2{id, lastb[PJ.tile0 + r]};
+        std::vector<int32_t> pr2(ftile[I]);
+        pr2.push_back(lastb[PJ.tile0 + r]);
         std::vector<Access> ac2{{kWKey | (PJ.tile0 + r), true}};
-        for (int c = 0; c < P.nt; ++c) ac2.push_back({kWKey | (P.tile0 + c), false});
+        for (int c = 0; c < P.nt; ++c) ac2.push_back({kZKey | (P.tile0 + c), false});
         double byt = 16.0 * T.sz * P.n, fl2 = 8.0 * T.sz * P.n;
         int uid = sg.add(u, pr2, w_stream(byt, fl2));
         lastb[PJ.tile0 + r] = uid;
@@ -584,8 +632,6 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       }
     }
   }
-  // backward: x_J once its tiles have received every push, then push
-  // z_c(I) -= L_Jc^T x_J into each panel I that holds J as a row block
   std::vector<std::vector<std::pair<int, int>>> holders(nb);  // J -> (panel I, row offset of J in I)
   for (int I = 0; I < nb; ++I)
     for (int b = 1; b < p.panels[I].npb; ++b) {
@@ -594,22 +640,28 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
     }
   for (int J = nb - 1; J >= 0; --J) {
     const Panel& PJ = p.panels[J];
-    Task t{};
-    t.kind = TK_BDIAG;
-    t.panel = J;
-    t.m = PJ.n;
-    t.lda = PJ.H;
-    std::vector<int32_t> pr{fdiag[J]};
-    std::vector<Access> ac;
+    std::vector<int32_t> zpr;
+    for (int c = 0; c < PJ.nt; ++c) zpr.push_back(lastz[PJ.tile0 + c]);
     for (int c = 0; c < PJ.nt; ++c) {
-      pr.push_back(lastb[PJ.tile0 + c]);
-      ac.push_back({kWKey | (PJ.tile0 + c), true});
+      const Tile& T = p.tiles[PJ.tile0 + c];
+      Task t{};
+      t.kind = TK_BTILE;
+      t.panel = J;
+      t.m = T.sz;
+      t.k = PJ.n - T.r0;
+      t.lda = PJ.n;
+      t.aux = PJ.tile0 + c;
+      t.a_off = PJ.ioff + T.r0 + (int64_t)T.r0 * PJ.n;
+      t.b_off = PJ.prow0 + T.r0;
+      t.c_off = PJ.prow0 + T.r0;
+      std::vector<Access> ac{{kWKey | (PJ.tile0 + c), true}};
+      for (int q = 0; q < PJ.nt; ++q) ac.push_back({kZKey | (PJ.tile0 + q), false});
+      double fl = 8.0 * T.sz * (double)(PJ.n - T.r0);
+      int id = sg.add(t, zpr, w_stream(8.0 * T.sz * (PJ.n - T.r0), fl));
+      btile[J].push_back(id);
+      lastb[PJ.tile0 + c] = id;
+      sacc.push_back(ac);
     }
-    double fl = 4.0 * (double)PJ.n * PJ.n;
-    int bid = sg.add(t, pr, w_stream(8.0 * PJ.n * PJ.n, fl) + 2.0 * PJ.nt);
-    bdiag[J] = bid;
-    for (int c = 0; c < PJ.nt; ++c) lastb[PJ.tile0 + c] = bid;
-    sacc.push_back(ac);
     for (auto& h : holders[J]) {
       const int I = h.first;
       const Panel& P = p.panels[I];
@@ -623,14 +675,15 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         u.lda = P.H;
         u.aux = P.tile0 + c;
         u.a_off = P.off + h.second + (int64_t)T.r0 * P.H;
-        u.b_off = PJ.prow0;
-        u.c_off = P.prow0 + T.r0;
-        std::vector<int32_t> pr2{bid, lastb[P.tile0 + c]};
-        std::vector<Access> ac2{{kWKey | (P.tile0 + c), true}};
+        u.b_off = PJ.prow0;              // rows of x_J in W
+        u.c_off = P.prow0 + T.r0;        // rows of t_c in Z
+        std::vector<int32_t> pr2(btile[J]);
+        pr2.push_back(lastz[P.tile0 + c]);
+        std::vector<Access> ac2{{kZKey | (P.tile0 + c), true}};
         for (int cc = 0; cc < PJ.nt; ++cc) ac2.push_back({kWKey | (PJ.tile0 + cc), false});
         double byt = 16.0 * T.sz * PJ.n, fl2 = 8.0 * T.sz * PJ.n;
         int uid = sg.add(u, pr2, w_stream(byt, fl2));
-        lastb[P.tile0 + c] = uid;
+        lastz[P.tile0 + c] = uid;
         sacc.push_back(ac2);
       }
     }

@@ -12,8 +12,9 @@
 //             complex product per block pair on the matrix cores)
 //
 // then L (strictly below the diagonal) and D (on it) go back to the tile in
-// global memory, and the full inverse Linv = L^-1 (m x m, column-major,
-// zeros above the diagonal) is assembled by block diagonals:
+// global memory, and the full inverse Linv = L^-1 (m x m, column-major with
+// leading dimension ldl, zeros above the diagonal) is assembled by block
+// diagonals:
 //   Linv_ij = -X_i sum_{j <= q < i} L_iq Linv_qj.
 // Rows/columns beyond m are padded with the identity.
 #pragma once
@@ -51,8 +52,8 @@ __device__ __forceinline__ cpx<T> tl_x(const D3M_LDS cpx<T>* S, int b, int i, in
 
 template <typename T>
 __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typename Cplx<T>::type* dout_,
-                          typename Cplx<T>::type* linv_, int row0, int32_t* status, float* gmin_d, float* gmax_l,
-                          lds_char* lds) {
+                          typename Cplx<T>::type* linv_, int64_t ldl, int row0, int32_t* status, float* gmin_d,
+                          float* gmax_l, lds_char* lds) {
   typedef typename V4<T>::type v4;
   D3M_LDS cpx<T>* S = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   D3M_LDS cpx<T>* dv = S + TL_NBLK * 256;
@@ -216,7 +217,7 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
     cpx<T> v;
     if ((i >> 4) == (j >> 4)) v = tl_x(S, i >> 4, i & 15, j & 15);
     else { v.x = 0; v.y = 0; }
-    linv[e] = v;
+    linv[i + (int64_t)j * ldl] = v;
   }
   // block diagonals d = 1.. of Linv: T = sum_q L_iq Linv_qj, Linv_ij = -X_i T
   const int lr = lane & 15, lk = lane >> 4;
@@ -235,7 +236,7 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
           if (q == bj) bv = tl_x(S, bj, kq, lr);
           else {
             const int gr = 16 * q + kq, gc = 16 * bj + lr;
-            if (gr < m && gc < m) bv = linv[gr + (int64_t)gc * m];
+            if (gr < m && gc < m) bv = linv[gr + (int64_t)gc * ldl];
             else { bv.x = (gr == gc) ? (T)1 : (T)0; bv.y = 0; }
           }
           re = mfma16(av.x, bv.x, re);
@@ -253,7 +254,7 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
           cpx<T> t;
           t.x = re[v];
           t.y = im[v];
-          linv[gr + (int64_t)gc * m] = t;
+          linv[gr + (int64_t)gc * ldl] = t;
         }
       }
       __builtin_amdgcn_s_waitcnt(0);
@@ -265,7 +266,7 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
         const cpx<T> av = tl_x(S, bi, lr, kq);  // X_i(lr, kq)
         cpx<T> bv;                             // T(kq, lr)
         const int gr = 16 * bi + kq;
-        if (gr < m && gc < m) bv = linv[gr + (int64_t)gc * m];
+        if (gr < m && gc < m) bv = linv[gr + (int64_t)gc * ldl];
         else { bv.x = 0; bv.y = 0; }
         re2 = mfma16(av.x, bv.x, re2);
         re2 = mfma16(-av.y, bv.y, re2);
@@ -281,7 +282,7 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
           cpx<T> t;
           t.x = -re2[v];
           t.y = -im2[v];
-          linv[gr + (int64_t)gc * m] = t;
+          linv[gr + (int64_t)gc * ldl] = t;
         }
       }
     }
