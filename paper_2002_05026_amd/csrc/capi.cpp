@@ -196,7 +196,7 @@ d3m_status run_dag(d3m_factor_s* f, bool solve, int nrhs, const int32_t* skip, h
   const int w = solve ? 1 : 0;
   const bool timed = f->opt.timing && !skip && f->nev[w] < d3m_factor_s::kRing;
   if (timed) HIPCHK(hipEventRecord(f->ev[w][2 * f->nev[w]], s));
-  HIPCHK(launch_dag(a, f->prec, f->nworkers, s));
+  HIPCHK(launch_dag(a, f->prec, f->nworkers, solve, s));
   if (timed) {
     HIPCHK(hipEventRecord(f->ev[w][2 * f->nev[w] + 1], s));
     f->nev[w]++;
@@ -700,7 +700,7 @@ d3m_status batch_dag(d3m_batch_s* b, bool solve, const int32_t* skip, hipStream_
   a.trace = nullptr;
   HIPCHK(launch_reset(a.counters, b->at<int32_t>(solve ? b->lay.scnt : b->lay.fcnt), a.ntask, a.head, a.abort_flag,
                       skip, s));
-  HIPCHK(launch_dag(a, b->prec, b->nworkers, s));
+  HIPCHK(launch_dag(a, b->prec, b->nworkers, solve, s));
   return D3M_OK;
 }
 }  // namespace

@@ -189,7 +189,9 @@ template <typename T> constexpr int dag_lds_bytes() {
 }
 
 // ---------------------------------------------------------------- the executor
-template <typename T>
+// PHASE only names the launch (0: factor DAG, 1: solve DAG) so that
+// profilers report the two separately.
+template <typename T, int PHASE>
 __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[dag_lds_bytes<T>()];
   __shared__ int s_ticket;
@@ -264,10 +266,15 @@ __global__ void k_reset(int32_t* counters, const int32_t* init, int n, int32_t* 
   }
 }
 
-hipError_t launch_dag(const DagArgs& a, int prec, int nworkers, hipStream_t s) {
+hipError_t launch_dag(const DagArgs& a, int prec, int nworkers, bool solve, hipStream_t s) {
   if (a.ntask == 0) return hipSuccess;
-  if (prec == 0) hipLaunchKernelGGL(k_dag<double>, dim3(nworkers), dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL(k_dag<float>, dim3(nworkers), dim3(kThreads), 0, s, a);
+  if (prec == 0) {
+    if (solve) hipLaunchKernelGGL((k_dag<double, 1>), dim3(nworkers), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_dag<double, 0>), dim3(nworkers), dim3(kThreads), 0, s, a);
+  } else {
+    if (solve) hipLaunchKernelGGL((k_dag<float, 1>), dim3(nworkers), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_dag<float, 0>), dim3(nworkers), dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

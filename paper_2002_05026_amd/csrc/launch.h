@@ -55,7 +55,7 @@ struct IrCtrl {
   double eta_hist[32];
 };
 
-hipError_t launch_dag(const DagArgs& a, int prec, int nworkers, hipStream_t s);
+hipError_t launch_dag(const DagArgs& a, int prec, int nworkers, bool solve, hipStream_t s);
 hipError_t launch_level(const Task* tasks, int begin, int end, const InstView* iv, int prec, hipStream_t s);
 hipError_t launch_reset(int32_t* counters, const int32_t* init, int n, int32_t* head, int32_t* abort_flag,
                         const int32_t* skip, hipStream_t s);

@@ -1,0 +1,188 @@
+"""GPU: differentiation (torch wrapper against torch's dense autograd;
+directional central differences per the stated protocol), hipGraph capture
+of factor + solve and of a batch (every replay against eager), the tuner."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_05026_amd import instances as gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _d3m():
+    import paper_2002_05026_amd as d3m
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return d3m
+
+
+def test_autograd_matches_dense_torch_autograd():
+    d3m = _d3m()
+    from paper_2002_05026_amd.autograd import solve
+    from tests.test_autograd_convention import _dense_torch
+    inst = gen.make_instance((2, 2, 2), (6, 20), gen.COEF_PLAIN, 2, 808, with_c=True)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=16)
+    # reference on the CPU in complex128
+    Kc = torch.tensor(inst.K, requires_grad=True)
+    Bc = torch.tensor(inst.B, requires_grad=True)
+    Xc = torch.linalg.solve(_dense_torch(inst.sizes, inst.pairs, Kc), Bc.t()).t()
+    torch.real((torch.tensor(inst.C) * Xc).sum()).backward()
+    for prec, tol in ((d3m.C128, 1e-10), (d3m.C64_IR, 1e-7)):
+        K = torch.tensor(inst.K, device="cuda", requires_grad=True)
+        B = torch.tensor(inst.B, device="cuda", requires_grad=True)
+        X = solve(K, B, plan, prec)
+        torch.real((torch.tensor(inst.C, device="cuda") * X).sum()).backward()
+        assert np.abs(B.grad.cpu().numpy() - Bc.grad.numpy()).max() <= tol * np.abs(Bc.grad.numpy()).max()
+        assert np.abs(K.grad.cpu().numpy() - Kc.grad.numpy()).max() <= tol * np.abs(Kc.grad.numpy()).max()
+
+
+def test_directional_finite_differences():
+    # J = sum_k Re(c_k^T x_k); h = 1e-6 relative; FD evaluations solved in FP64
+    # (eta <= 1e-13); adjoint from the mixed path; relative error <= 1e-5
+    d3m = _d3m()
+    inst = gen.make_instance((2, 2, 2), (30, 80), gen.COEF_PLAIN, 3, 909, with_c=True)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=32)
+    K = torch.tensor(inst.K, device="cuda")
+    B = torch.tensor(inst.B, device="cuda")
+    C = torch.tensor(inst.C, device="cuda")
+    fm = d3m.Factor(plan, d3m.C64_IR, nrhs_max=3)
+    fm.factorize(K)
+    X = fm.solve(B)
+    Lam, dK = fm.adjoint(X, C)
+    assert fm.status()["status"] == 0
+    f64 = d3m.Factor(plan, d3m.C128, nrhs_max=3)
+
+    def J(Kt, Bt):
+        f64.factorize(Kt)
+        Xt = f64.solve(Bt)
+        st = f64.status()
+        assert st["status"] == 0 and st["eta"] <= 1e-13
+        return float(torch.real((C * Xt).sum()))
+
+    rng = np.random.default_rng(1)
+    dKs = dK.cpu().numpy()
+    Lams = Lam.cpu().numpy()
+    off = inst.offsets
+    for trial in range(4):
+        # b-direction
+        E = (rng.standard_normal(inst.B.shape) + 1j * rng.standard_normal(inst.B.shape))
+        h = 1e-6 * np.linalg.norm(inst.B) / np.linalg.norm(E)
+        Et = torch.tensor(E, device="cuda")
+        fd = (J(K, B + h * Et) - J(K, B - h * Et)) / (2 * h)
+        ad = np.real(np.sum(Lams * E))
+        assert abs(fd - ad) <= 1e-5 * abs(ad)
+        # symmetric pattern direction on the stored entries (diagonal blocks
+        # read from their lower triangle)
+        EK = (rng.standard_normal(inst.K.shape) + 1j * rng.standard_normal(inst.K.shape))
+        hK = 1e-6 * np.linalg.norm(inst.K) / np.linalg.norm(EK)
+        EKt = torch.tensor(EK, device="cuda")
+        fdK = (J(K + hK * EKt, B) - J(K - hK * EKt, B)) / (2 * hK)
+        adK = 0.0
+        for I in range(inst.nb):
+            n = int(inst.sizes[I])
+            e = EK[off[I]:off[I + 1]].reshape(n, n, order="F")
+            e = np.tril(e) + np.tril(e, -1).T
+            g = dKs[off[I]:off[I + 1]].reshape(n, n, order="F")
+            adK += np.real(np.sum(g * e))
+        adK += 2 * np.real(np.sum(dKs[off[inst.nb]:] * EK[off[inst.nb]:]))
+        assert abs(fdK - adK) <= 1e-5 * abs(adK)
+
+
+def test_graph_capture_factor_solve_replays():
+    d3m = _d3m()
+    inst = gen.make_instance((3, 3, 2), (40, 120), gen.COEF_PRECISION, 4, 1001)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=64)
+    K = torch.tensor(inst.K, device="cuda")
+    B = torch.tensor(inst.B, device="cuda")
+    f = d3m.Factor(plan, d3m.C64_IR, nrhs_max=4)
+    f.factorize(K)
+    Xe = f.solve(B).clone()
+    ref = Xe.cpu().numpy()
+    X = torch.zeros_like(B)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        f.factorize(K)
+        f.solve(B, X)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        f.factorize(K)
+        f.solve(B, X)
+    for rep in range(3):
+        X.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(X.cpu().numpy(), ref), rep
+        assert f.status()["status"] == 0
+        _ = (B * 2).sum().item()  # eager work between replays
+    eta = oracle.backward_error(inst.sizes, inst.pairs, inst.K, ref, inst.B)
+    assert eta.max() <= 1e-10
+
+
+def test_graph_capture_batch_replays():
+    d3m = _d3m()
+    insts = gen.config_batch(count=3, nrhs=2, size_range=(30, 80))
+    fs, Ks, Bs, Xs = [], [], [], []
+    for inst in insts:
+        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=32)
+        fs.append(d3m.Factor(plan, d3m.C64_IR, nrhs_max=2))
+        Ks.append(torch.tensor(inst.K, device="cuda"))
+        Bs.append(torch.tensor(inst.B, device="cuda"))
+        Xs.append(torch.zeros_like(Bs[-1]))
+    b = d3m.Batch(fs)
+    b.run(Ks, Bs, Xs)
+    torch.cuda.synchronize()
+    refs = [x.cpu().numpy().copy() for x in Xs]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(Ks, Bs, Xs)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        b.run(Ks, Bs, Xs)
+    for rep in range(3):
+        for x in Xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for x, r in zip(Xs, refs):
+            assert np.array_equal(x.cpu().numpy(), r), rep
+    for inst, x, f in zip(insts, refs, fs):
+        assert f.status()["status"] == 0
+        assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, x, inst.B).max() <= 1e-10
+
+
+def test_batch_instance_equals_single_run_bitwise():
+    d3m = _d3m()
+    insts = gen.config_batch(count=3, nrhs=2, size_range=(30, 80))
+    fs, Ks, Bs, Xs = [], [], [], []
+    for inst in insts:
+        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=32)
+        fs.append(d3m.Factor(plan, d3m.C64_IR, nrhs_max=2))
+        Ks.append(torch.tensor(inst.K, device="cuda"))
+        Bs.append(torch.tensor(inst.B, device="cuda"))
+        Xs.append(torch.zeros_like(Bs[-1]))
+    d3m.Batch(fs).run(Ks, Bs, Xs)
+    torch.cuda.synchronize()
+    for f, K, B, X in zip(fs, Ks, Bs, Xs):
+        f.factorize(K)
+        Xs1 = f.solve(B)
+        assert np.array_equal(Xs1.cpu().numpy(), X.cpu().numpy())
+
+
+def test_tuner_picks_a_candidate(tmp_path, monkeypatch):
+    d3m = _d3m()
+    from paper_2002_05026_amd import tune
+    monkeypatch.setenv("D3M_TUNE_CACHE", str(tmp_path / "tune.json"))
+    inst = gen.make_instance((2, 2, 2), (100, 300), gen.COEF_PLAIN, 1, 4)
+    res = tune.tune(inst, d3m.C64_IR, candidates=(64, 128), reps=2)
+    assert res["tile"] in (64, 128) and all(v > 0 for v in res["ms"].values())
+    assert tune.lookup(d3m.C64_IR, float(inst.sizes.mean())) == res["tile"]
