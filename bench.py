@@ -25,6 +25,20 @@ sys.path.insert(0, ROOT)
 METRIC = "block-LDLᵀ TFLOP/s + time-to-solve at 1e-10 residual, mixed+IR vs FP64"
 PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
+# HBM bytes per complex64 factor-DAG launch on this workload, from the two
+# rocprofv3 --pmc runs (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after the plain-copy
+# calibration) recorded in profiles/k_dag_factor_c64_precision_4x4x4.md, valid
+# only for the kernel sources they were taken with.
+TRAFFIC_BYTES = 272.30e9
+TRAFFIC_SRC_HASH = "afa160bed18893d5"
+KERNEL_SOURCES = ("paper_2002_05026_amd/csrc/dag_kernels.hip", "paper_2002_05026_amd/csrc/gemm_engine.h",
+                  "paper_2002_05026_amd/csrc/tile_ldlt.h")
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha1(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()[:16]
+    return TRAFFIC_BYTES if h == TRAFFIC_SRC_HASH else None
 
 
 def cpu_baseline(inst):
@@ -58,12 +72,23 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy (for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
               "(see DESIGN.md) and is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30}))
+        return
     import paper_2002_05026_amd as d3m
     from paper_2002_05026_amd import instances as gen
 
@@ -146,7 +171,7 @@ def main():
         "fp64": fp64,
         "roofline": {"kernel": "k_dag<float> (complex64 factor DAG)", "bound": "mfma", "achieved": achieved,
                      "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
-                     "traffic": None},
+                     "traffic": measured_traffic()},
         "cpu_baseline": {k: v for k, v in cpu.items() if k != "factor_s"} if cpu else None,
     }
     print(json.dumps(out), flush=True)
