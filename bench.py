@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--workload", default="precision", choices=["precision", "fp64", "batch", "diff"],
+                    help="precision (default): the metric's workload; the others measure the remaining "
+                         "configurations and print their own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy (for scaling HBM byte counters) and exit")
     args = ap.parse_args()
@@ -88,6 +91,11 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 1 << 30}))
+        return
+    if args.workload != "precision":
+        from paper_2002_05026_amd import extra_workloads
+        out = getattr(extra_workloads, args.workload)(args)
+        print(json.dumps(out), flush=True)
         return
     import paper_2002_05026_amd as d3m
     from paper_2002_05026_amd import instances as gen

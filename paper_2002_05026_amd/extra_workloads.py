@@ -1,0 +1,216 @@
+"""Measurements of the configurations other than the benchmark's default
+(bench.py --workload fp64|batch|diff).  Each returns one JSON-able dict.
+
+* fp64:  8x8x1 grid, 112 interfaces, n~U{200..400}, complex128 factor and
+         solve, 1 and 16 right-hand sides (the plain method).
+* batch: a frequency sweep of 32 instances (grids 2x2x2 / 3x3x2 / 4x4x2,
+         n~U{100..500}, f in [0.5, 2]), 16 RHS each, complex64 + FP64
+         refinement, one persistent launch per phase, captured in a hipGraph
+         and replayed; tiles from the tuner.
+* diff:  6x6x6 grid, 540 interfaces, n~U{300..700} (about 270k unknowns),
+         128 RHS, complex64 + FP64 refinement, then the adjoint (lambda and
+         dK on K's pattern) with the same factors.
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+PEAK_FP32_MFMA = 157.3
+PEAK_FP64_MFMA = 78.6
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def fp64(args):
+    import torch
+
+    import paper_2002_05026_amd as d3m
+    from paper_2002_05026_amd import instances as gen
+    res = {"metric": "block-LDLT TFLOP/s + time-to-solve, FP64 plain method", "unit": "TFLOP/s",
+           "data": "synthetic", "dtype": "c128", "n_gpus": 1,
+           "config": {"workload": "fp64: 8x8x1 domain grid, 112 interfaces, n~U{200..400}, complex128"}}
+    runs = {}
+    for nrhs in (1, 16):
+        inst = gen.config_fp64(nrhs=nrhs)
+        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid)
+        flops = plan.info["flops_factor"]
+        K = torch.from_numpy(inst.K).cuda()
+        B = torch.from_numpy(inst.B).cuda()
+        X = torch.empty_like(B)
+        f = d3m.Factor(plan, d3m.C128, nrhs_max=nrhs, timing=True)
+        for _ in range(max(1, args.warmup)):
+            f.factorize(K)
+            f.solve(B, X)
+        torch.cuda.synchronize()
+        f.status()
+        e0, e1 = _events()
+        e0.record()
+        for _ in range(args.steps):
+            f.factorize(K)
+            f.solve(B, X)
+        e1.record()
+        torch.cuda.synchronize()
+        st = f.status()
+        ms = e0.elapsed_time(e1) / args.steps
+        dag = st["t_factor_dag_ms"] / st["n_factor_dag"]
+        sdag = st["t_solve_dag_ms"] / st["n_solve_dag"]
+        solve_bytes = 2.0 * plan.info["nnz_L"] * 16
+        runs[nrhs] = {"N": inst.N, "time_to_solve_ms": ms, "factor_dag_ms": dag, "factor_tflops": flops / dag / 1e9,
+                      "frac_fp64_peak": flops / dag / 1e9 / PEAK_FP64_MFMA, "solve_dag_ms": sdag,
+                      "solve_GBps_factor_bytes": solve_bytes / sdag / 1e6, "eta": st["eta"],
+                      "factor_gflop": flops / 1e9}
+        _log(f"fp64 nrhs={nrhs}: {runs[nrhs]}")
+    res["runs"] = runs
+    res["value"] = runs[1]["factor_tflops"]
+    return res
+
+
+def batch(args):
+    import torch
+
+    import paper_2002_05026_amd as d3m
+    from paper_2002_05026_amd import instances as gen
+    from paper_2002_05026_amd import tune
+    insts = gen.config_batch(count=32, nrhs=16)
+    _log(f"batch: {len(insts)} instances, N = {[i.N for i in insts][:8]}...")
+    # tile edge from the tuner (timed on one instance of the largest grid)
+    probe = max(insts, key=lambda i: i.N)
+    tuned = tune.tune(probe, d3m.C64_IR, reps=2)
+    tile = tuned["tile"]
+    _log(f"tuned tile {tuned}")
+    fs, Ks, Bs, Xs, flops = [], [], [], [], 0.0
+    for inst in insts:
+        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=tile)
+        flops += plan.info["flops_factor"]
+        fs.append(d3m.Factor(plan, d3m.C64_IR, nrhs_max=16))
+        Ks.append(torch.from_numpy(inst.K).cuda())
+        Bs.append(torch.from_numpy(inst.B).cuda())
+        Xs.append(torch.zeros_like(Bs[-1]))
+    b = d3m.Batch(fs)
+    b.run(Ks, Bs, Xs)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(Ks, Bs, Xs)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run(Ks, Bs, Xs)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for _ in range(args.steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    sts = [f.status() for f in fs]
+    etas = [st["eta"] for st in sts]
+    iters = [st["ir_iters"] for st in sts]
+    ok = all(st["status"] == 0 for st in sts)
+    # the same instances one after another (each its own launches), for comparison
+    e0, e1 = _events()
+    e0.record()
+    for f, K, B, X in zip(fs, Ks, Bs, Xs):
+        f.factorize(K)
+        f.solve(B, X)
+    e1.record()
+    torch.cuda.synchronize()
+    seq = e0.elapsed_time(e1)
+    return {"metric": "batched frequency sweep: aggregate factor TFLOP/s and time for all instances",
+            "value": flops / ms / 1e9, "unit": "TFLOP/s", "ms_per_sweep": ms, "sequential_ms": seq,
+            "n_instances": len(insts), "status_ok": ok, "max_eta": max(etas), "ir_iters": sorted(set(iters)),
+            "tile": tile, "tuner_ms": tuned["ms"], "factor_gflop_total": flops / 1e9, "dtype": "c64+c128",
+            "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": "batch: 32-instance sweep, grids {2x2x2,3x3x2,4x4x2}, n~U{100..500}, "
+                                   "f_k = 0.5 + 1.5k/31, 16 RHS each, hipGraph replay"}}
+
+
+def diff(args):
+    import torch
+
+    import paper_2002_05026_amd as d3m
+    from paper_2002_05026_amd import instances as gen
+    t0 = time.perf_counter()
+    inst = gen.config_diff(nrhs=128)
+    _log(f"diff: N={inst.N}, K {inst.K.nbytes / 1e9:.1f} GB generated in {time.perf_counter() - t0:.0f}s")
+    sub = gen.subinstance(inst, gen.box_interfaces(inst, (0, 0, 0), (2, 2, 2)))
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid)
+    flops = plan.info["flops_factor"]
+    _log(f"plan: {plan.info['ntask_factor']} factor tasks, {flops / 1e12:.1f} TFLOP")
+    K = torch.from_numpy(inst.K).cuda()
+    B = torch.from_numpy(inst.B).cuda()
+    C = torch.from_numpy(inst.C).cuda()
+    del inst.K
+    X = torch.empty_like(B)
+    f = d3m.Factor(plan, d3m.C64_IR, nrhs_max=128, timing=True)
+    f.factorize(K)
+    f.solve(B, X)
+    torch.cuda.synchronize()
+    st0 = f.status()
+    _log(f"warm run status {st0['status']} eta {st0['eta_hist']}")
+    e0, e1 = _events()
+    e2, e3 = _events()
+    e0.record()
+    f.factorize(K)
+    f.solve(B, X)
+    e1.record()
+    e2.record()
+    Lam, dK = f.adjoint(X, C)
+    e3.record()
+    torch.cuda.synchronize()
+    st = f.status()
+    ms = e0.elapsed_time(e1)
+    adj = e2.elapsed_time(e3)
+    dag = st["t_factor_dag_ms"] / max(1, st["n_factor_dag"])
+    J = float(torch.real((C * X).sum()))
+    Jl = float(torch.real((Lam * B).sum()))
+    subcheck = _sub_gradient_check(sub)
+    return {"sub_instance_check": subcheck,"metric": "differentiation at scale: c64+IR time-to-solve, adjoint time, factor TFLOP/s",
+            "value": flops / dag / 1e9, "unit": "TFLOP/s", "N": plan.N, "nrhs": 128,
+            "time_to_solve_ms": ms, "adjoint_ms": adj, "factor_dag_ms": dag,
+            "frac_fp32_peak": flops / dag / 1e9 / PEAK_FP32_MFMA, "status": st["status"],
+            "eta_hist": st["eta_hist"], "J": J, "identity_rel_err": abs(J - Jl) / abs(J),
+            "factor_gflop": flops / 1e9, "dtype": "c64+c128", "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": "diff: 6x6x6 domain grid, 540 interfaces, n~U{300..700}, 128 RHS, "
+                                   "complex64 factor + FP64 refinement + adjoint"}}
+
+
+def _sub_gradient_check(sub):
+    """The 2x2x2 sub-instance (principal submatrix of K on the 12 interfaces
+    inside the domain box [0,2)^3) through the same GPU path (complex64 +
+    FP64 refinement, adjoint), against the CPU FP64 oracle's gradient."""
+    import torch
+
+    import oracle
+    import paper_2002_05026_amd as d3m
+    order = oracle.nd_order((2, 2, 2))
+    p = oracle.OraclePlan(sub.sizes, sub.pairs, order)
+    assert p.factor(sub.K) == -1
+    Xo = p.solve(sub.B)
+    Lo = p.solve(sub.C)
+    dKo = oracle.grad_K(sub.sizes, sub.pairs, Lo, Xo, sub.K.shape[0])
+    plan = d3m.Plan(sub.sizes, sub.pairs, grid=(2, 2, 2))
+    K = torch.from_numpy(sub.K).cuda()
+    f = d3m.Factor(plan, d3m.C64_IR, nrhs_max=sub.B.shape[0])
+    f.factorize(K)
+    X = f.solve(torch.from_numpy(sub.B).cuda())
+    Lam, dK = f.adjoint(X, torch.from_numpy(sub.C).cuda())
+    st = f.status()
+    rel_lam = float(np.linalg.norm(Lam.cpu().numpy() - Lo) / np.linalg.norm(Lo))
+    rel_dk = float(np.linalg.norm(dK.cpu().numpy() - dKo) / np.linalg.norm(dKo))
+    return {"N": int(sub.N), "status": st["status"], "rel_err_lambda": rel_lam, "rel_err_dK": rel_dk,
+            "pass_1e-5": bool(rel_lam <= 1e-5 and rel_dk <= 1e-5)}
