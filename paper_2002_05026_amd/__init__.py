@@ -207,7 +207,8 @@ class Factor:
     """A numeric factor bound to a torch-owned device workspace."""
 
     def __init__(self, plan: Plan, precision: int = C128, nrhs_max: int = 1, tol: float = 1e-10,
-                 max_iter: int = 10, ir_host_sync: bool = False, timing: bool = False, device=None):
+                 max_iter: int = 10, ir_host_sync: bool = False, timing: bool = False, growth_dmin: float = 0.0,
+                 growth_lmax: float = 0.0, fallback: bool = True, device=None):
         import torch
         self.plan = plan
         self.precision = int(precision)
@@ -217,7 +218,8 @@ class Factor:
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
         self._off = (-base) % 256
-        opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), 0.0, 0.0, 0, int(bool(timing)))
+        opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), float(growth_dmin), float(growth_lmax),
+                       0 if fallback else -1, int(bool(timing)))
         h = _vp()
         _check(lib().d3m_factor_bind(plan._h, self.precision, ctypes.c_void_p(base + self._off), nbytes,
                                      self.nrhs_max, ctypes.byref(opts), ctypes.byref(h)), "d3m_factor_bind")

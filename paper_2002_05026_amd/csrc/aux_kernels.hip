@@ -17,6 +17,7 @@ __global__ void k_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ct
   if (i == 0) {
     status[0] = 0x7fffffff;
     status[1] = 0;
+    status[2] = 0;
     if (ctrl) {
       ctrl->stop = 0;
       ctrl->iters = 0;

@@ -369,6 +369,9 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
   iv.nrhs = nrhs_max;
   iv.npanel = p.nb;
   iv.N = p.N;
+  iv.gdmin = (float)f->opt.growth_dmin;
+  iv.glmax = (float)f->opt.growth_lmax;
+  iv.fallback = f->opt.fallback < 0 ? 0 : 1;
   bool ok = up(f->lay.ftasks, p.fdag.tasks.data(), p.fdag.tasks.size() * sizeof(Task)) &&
             up(f->lay.fsucc, p.fdag.succ.data(), p.fdag.succ.size() * 4) &&
             up(f->lay.fcnt, p.fdag.npred.data(), p.fdag.npred.size() * 4) &&
@@ -506,10 +509,10 @@ d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
   if (!f || !out) return D3M_ERR_ARG;
   HIPCHK(hipStreamSynchronize(f->last));
   std::memset(out, 0, sizeof(*out));
-  int32_t st[2];
+  int32_t st[3];
   IrCtrl c;
   int32_t flags[2];
-  HIPCHK(hipMemcpy(st, f->at<int32_t>(f->lay.status), 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(st, f->at<int32_t>(f->lay.status), 12, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(&c, f->ctrl(), sizeof(c), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(flags, f->at<int32_t>(f->lay.flags), 8, hipMemcpyDeviceToHost));
   out->pivot_row = -1;
@@ -519,6 +522,7 @@ d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
     out->status = D3M_ZERO_PIVOT;
   }
   out->ir_iters = c.iters;
+  out->fallbacks = st[2];
   out->eta = -1;
   for (int k = 0; k < 32; ++k) {
     out->eta_hist[k] = c.eta_hist[k];

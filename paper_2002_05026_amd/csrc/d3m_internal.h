@@ -78,11 +78,14 @@ struct InstView {
   const Panel* panels;
   const PBlock* pblocks;
   const Tile* tiles;
-  int32_t* status;   // [0] first bad pivot (internal row, INT_MAX if none), [1] count
-  float* growth;     // per panel: [2*I] min |d| / max |A_II|, [2*I+1] max |L|
+  int32_t* status;   // [0] first bad pivot (internal row, INT_MAX if none), [1] count, [2] FP64 re-factors
+  float* growth;     // per panel: [2*I] min |d|, [2*I+1] max |L|
   int32_t nrhs;
   int32_t npanel;
   int64_t N;
+  float gdmin, glmax;  // fallback trigger (complex64 factor): |d| < gdmin max|A|, |l| > glmax
+  int32_t fallback;    // 1: re-factor tripped diagonal tiles in FP64
+  int32_t pad;
 };
 
 // Arguments of one persistent DAG launch.

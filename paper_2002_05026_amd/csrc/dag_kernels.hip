@@ -62,13 +62,26 @@ __device__ __forceinline__ Out<T> outp(typename Cplx<T>::type* dst, int64_t rs, 
 }
 
 // LDL^T of diagonal tile c of panel I (TK_FACT)
+// In the complex64 factor a tile whose growth check trips is factored again
+// in FP64 from the same (Schur-complemented) tile and stored rounded to
+// complex64.
 template <typename T>
 __device__ __noinline__ void task_fact(const Ctx<T>& cx, const Task& t) {
   const Tile tc = cx.iv->tiles[t.aux];
   float* gr = cx.iv->growth ? cx.iv->growth + 2 * t.panel : nullptr;
   const Panel P = cx.iv->panels[t.panel];
-  tile_ldlt<T>(cx.L + t.a_off, t.lda, t.m, cx.D + t.dofs, cx.Li + tc.linv_off, P.n, t.dofs, cx.iv->status,
-               gr ? gr : nullptr, gr ? gr + 1 : nullptr, cx.lds);
+  GrowthCheck gc;
+  gc.on = sizeof(T) == 4 && cx.iv->fallback != 0;
+  gc.dmin = cx.iv->gdmin;
+  gc.lmax = cx.iv->glmax;
+  const bool tripped = tile_ldlt<T, T>(cx.L + t.a_off, t.lda, t.m, cx.D + t.dofs, cx.Li + tc.linv_off, P.n, t.dofs,
+                                       cx.iv->status, gr, gr ? gr + 1 : nullptr, gc, cx.lds);
+  if (sizeof(T) == 4 && tripped) {
+    if (threadIdx.x == 0) atomicAdd(&cx.iv->status[2], 1);
+    gc.on = false;
+    tile_ldlt<double, T>(cx.L + t.a_off, t.lda, t.m, cx.D + t.dofs, cx.Li + tc.linv_off, P.n, t.dofs,
+                         cx.iv->status, gr, gr ? gr + 1 : nullptr, gc, cx.lds);
+  }
 }
 
 // L_rc = A_rc Linv_c^T D_c^-1, in place (TK_TRSM)
@@ -184,8 +197,9 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
   }
 }
 
+// the complex64 kernel also holds the FP64 re-factor of a tile
 template <typename T> constexpr int dag_lds_bytes() {
-  return tile_ldlt_lds_bytes<T>() > ge_lds_bytes<T>() ? tile_ldlt_lds_bytes<T>() : ge_lds_bytes<T>();
+  return tile_ldlt_lds_bytes<double>() > ge_lds_bytes<T>() ? tile_ldlt_lds_bytes<double>() : ge_lds_bytes<T>();
 }
 
 // ---------------------------------------------------------------- the executor

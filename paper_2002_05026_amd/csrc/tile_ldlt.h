@@ -26,7 +26,7 @@ constexpr int TL_NB = kTileMax / 16;                       // 16-blocks per tile
 constexpr int TL_NBLK = TL_NB * (TL_NB + 1) / 2;          // lower block triangle
 
 template <typename T> constexpr int tile_ldlt_lds_bytes() {
-  return (TL_NBLK * 256 + kTileMax) * (int)sizeof(cpx<T>);
+  return (TL_NBLK * 256 + kTileMax) * (int)sizeof(cpx<T>) + 16;
 }
 
 __device__ __forceinline__ int tl_blk(int bi, int bj) { return (bi * (bi + 1) / 2 + bj) * 256; }
@@ -50,34 +50,59 @@ __device__ __forceinline__ cpx<T> tl_x(const D3M_LDS cpx<T>* S, int b, int i, in
   return v;
 }
 
-template <typename T>
-__device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typename Cplx<T>::type* dout_,
-                          typename Cplx<T>::type* linv_, int64_t ldl, int row0, int32_t* status, float* gmin_d,
-                          float* gmax_l, lds_char* lds) {
+// Growth test of a factorization attempt (the fallback trigger): a pivot
+// with |d| < dmin * max|A|, an entry of L with |l| > lmax, or any value that
+// is not finite.
+struct GrowthCheck {
+  bool on;
+  float dmin, lmax;
+};
+
+template <typename T, typename S> __device__ __forceinline__ cpx<T> cvt_cpx(cpx<S> v) {
+  cpx<T> r;
+  r.x = (T)v.x;
+  r.y = (T)v.y;
+  return r;
+}
+
+// T: arithmetic precision; TS: storage precision of the tile, D and Linv.
+// Returns true (and writes nothing back) when the growth check is on and
+// trips; bad pivots are only recorded when the check is off.
+template <typename T, typename TS>
+__device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typename Cplx<TS>::type* dout_,
+                          typename Cplx<TS>::type* linv_, int64_t ldl, int row0, int32_t* status, float* gmin_d,
+                          float* gmax_l, GrowthCheck gc, lds_char* lds) {
   typedef typename V4<T>::type v4;
   D3M_LDS cpx<T>* S = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   D3M_LDS cpx<T>* dv = S + TL_NBLK * 256;
-  D3M_GLB cpx<T>* a = gptr_mut<T>(a_);
-  D3M_GLB cpx<T>* dout = gptr_mut<T>(dout_);
-  D3M_GLB cpx<T>* linv = gptr_mut<T>(linv_);
+  D3M_LDS int* flags = reinterpret_cast<D3M_LDS int*>(dv + kTileMax);  // [0] max|A| bits, [1] min|d| bits, [2] max|L| bits, [3] bad
+  D3M_GLB cpx<TS>* a = gptr_mut<TS>(a_);
+  D3M_GLB cpx<TS>* dout = gptr_mut<TS>(dout_);
+  D3M_GLB cpx<TS>* linv = gptr_mut<TS>(linv_);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nb = (m + 15) >> 4;
   const int M = nb * 16;
   wg_sync_global();
+  if (tid < 4) flags[tid] = (tid == 1) ? 0x7f800000 : 0;
+  __syncthreads();
   // lower block triangle from the tile's lower triangle; identity padding
+  float amax = 0.f;
   for (int e = tid; e < M * M; e += kThreads) {
     const int i = e % M, j = e / M;
     if ((i >> 4) < (j >> 4)) continue;
     cpx<T> v;
     if (i < m && j < m) {
-      if (i >= j) v = a[i + (int64_t)j * lda];
-      else { v.x = 0; v.y = 0; }  // upper part of a diagonal block: scratch
+      if (i >= j) {
+        v = cvt_cpx<T>(a[i + (int64_t)j * lda]);
+        amax = fmaxf(amax, (float)sqrt(v.x * v.x + v.y * v.y));
+      } else { v.x = 0; v.y = 0; }  // upper part of a diagonal block: scratch
     } else {
       v.x = (i == j) ? (T)1 : (T)0;
       v.y = 0;
     }
     S[tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15)] = v;
   }
+  if (gc.on) atomicMax((int*)(flags), __float_as_int(amax));
   __syncthreads();
   for (int kb = 0; kb < nb; ++kb) {
     const int bkk = tl_blk(kb, kb);
@@ -87,11 +112,17 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
         const cpx<T> d = S[bkk + k * 16 + k];
         if (lane == 0 && kb * 16 + k < m) {
           const T ad = sqrt(d.x * d.x + d.y * d.y);
-          if (!(ad > (T)0) || !isfinite(d.x) || !isfinite(d.y)) {
-            atomicMin(&status[0], row0 + kb * 16 + k);
-            atomicAdd(&status[1], 1);
+          const bool bad = !(ad > (T)0) || !isfinite(d.x) || !isfinite(d.y);
+          if (gc.on) {
+            if (bad) flags[3] = 1;
+            else atomicMin((int*)(flags + 1), __float_as_int((float)ad));
+          } else {
+            if (bad) {
+              atomicMin(&status[0], row0 + kb * 16 + k);
+              atomicAdd(&status[1], 1);
+            }
+            if (gmin_d) atomicMin(reinterpret_cast<int*>(gmin_d), __float_as_int((float)ad));
           }
-          if (gmin_d) atomicMin(reinterpret_cast<int*>(gmin_d), __float_as_int((float)ad));
         }
         const T den = d.x * d.x + d.y * d.y;
         cpx<T> dinv;
@@ -199,14 +230,34 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
     }
     __syncthreads();
   }
+  if (gc.on) {
+    float lm = 0.f;
+    bool nf = false;
+    for (int e = tid; e < m * m; e += kThreads) {
+      const int i = e % m, j = e / m;
+      if (i <= j) continue;
+      const cpx<T> v = S[tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15)];
+      const float av = (float)sqrt(v.x * v.x + v.y * v.y);
+      if (!(av <= 3.0e38f)) nf = true;
+      else lm = fmaxf(lm, av);
+    }
+    atomicMax((int*)(flags + 2), __float_as_int(lm));
+    if (nf) flags[3] = 1;
+    __syncthreads();
+    const float fa = __int_as_float(flags[0]), fd = __int_as_float(flags[1]), fl = __int_as_float(flags[2]);
+    const bool trip = flags[3] != 0 || fd < gc.dmin * fa || fl > gc.lmax;
+    __syncthreads();
+    if (trip) return true;
+    if (tid == 0 && gmin_d) atomicMin(reinterpret_cast<int*>(gmin_d), __float_as_int(fd));
+  }
   // L and D back to the tile; D to dout
   float lmax = 0.f;
   for (int e = tid; e < m * m; e += kThreads) {
     const int i = e % m, j = e / m;
     if (i < j) continue;
     const cpx<T> v = S[tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15)];
-    a[i + (int64_t)j * lda] = v;
-    if (i == j) dout[i] = v;
+    a[i + (int64_t)j * lda] = cvt_cpx<TS>(v);
+    if (i == j) dout[i] = cvt_cpx<TS>(v);
     else lmax = fmaxf(lmax, (float)sqrt(v.x * v.x + v.y * v.y));
   }
   if (gmax_l) atomicMax(reinterpret_cast<int*>(gmax_l), __float_as_int(lmax));
@@ -217,7 +268,7 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
     cpx<T> v;
     if ((i >> 4) == (j >> 4)) v = tl_x(S, i >> 4, i & 15, j & 15);
     else { v.x = 0; v.y = 0; }
-    linv[i + (int64_t)j * ldl] = v;
+    linv[i + (int64_t)j * ldl] = cvt_cpx<TS>(v);
   }
   // block diagonals d = 1.. of Linv: T = sum_q L_iq Linv_qj, Linv_ij = -X_i T
   const int lr = lane & 15, lk = lane >> 4;
@@ -235,9 +286,9 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
           cpx<T> bv;                               // Linv(q,bj)(kq, lr)
           if (q == bj) bv = tl_x(S, bj, kq, lr);
           else {
-            const int gr = 16 * q + kq, gc = 16 * bj + lr;
-            if (gr < m && gc < m) bv = linv[gr + (int64_t)gc * ldl];
-            else { bv.x = (gr == gc) ? (T)1 : (T)0; bv.y = 0; }
+            const int gr = 16 * q + kq, gcl = 16 * bj + lr;
+            if (gr < m && gcl < m) bv = cvt_cpx<T>(linv[gr + (int64_t)gcl * ldl]);
+            else { bv.x = (gr == gcl) ? (T)1 : (T)0; bv.y = 0; }
           }
           re = mfma16(av.x, bv.x, re);
           re = mfma16(-av.y, bv.y, re);
@@ -246,15 +297,15 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
         }
       }
       // T goes through the output block of Linv to change register layout
-      const int gc = 16 * bj + lr;
+      const int gcl = 16 * bj + lr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gr = 16 * bi + acc_row<T>(lk, v);
-        if (gr < m && gc < m) {
+        if (gr < m && gcl < m) {
           cpx<T> t;
           t.x = re[v];
           t.y = im[v];
-          linv[gr + (int64_t)gc * ldl] = t;
+          linv[gr + (int64_t)gcl * ldl] = cvt_cpx<TS>(t);
         }
       }
       __builtin_amdgcn_s_waitcnt(0);
@@ -266,7 +317,7 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
         const cpx<T> av = tl_x(S, bi, lr, kq);  // X_i(lr, kq)
         cpx<T> bv;                             // T(kq, lr)
         const int gr = 16 * bi + kq;
-        if (gr < m && gc < m) bv = linv[gr + (int64_t)gc * ldl];
+        if (gr < m && gcl < m) bv = cvt_cpx<T>(linv[gr + (int64_t)gcl * ldl]);
         else { bv.x = 0; bv.y = 0; }
         re2 = mfma16(av.x, bv.x, re2);
         re2 = mfma16(-av.y, bv.y, re2);
@@ -278,16 +329,17 @@ __device__ void tile_ldlt(typename Cplx<T>::type* a_, int64_t lda, int m, typena
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gr = 16 * bi + acc_row<T>(lk, v);
-        if (gr < m && gc < m) {
+        if (gr < m && gcl < m) {
           cpx<T> t;
           t.x = -re2[v];
           t.y = -im2[v];
-          linv[gr + (int64_t)gc * ldl] = t;
+          linv[gr + (int64_t)gcl * ldl] = cvt_cpx<TS>(t);
         }
       }
     }
   }
   wg_sync_global();
+  return false;
 }
 
 }  // namespace d3m

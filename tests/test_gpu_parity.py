@@ -200,3 +200,31 @@ def test_batch_matches_single_runs():
         assert st["status"] == 0, st
         eta = oracle.backward_error(inst.sizes, inst.pairs, inst.K, X.cpu().numpy(), inst.B)
         assert eta.max() <= 1e-10
+
+
+def test_forced_fp64_fallback_of_diagonal_tiles():
+    # a growth threshold that every tile trips: each diagonal tile of the
+    # complex64 factor is re-factored in FP64; refinement still certifies
+    d3m = _d3m()
+    inst = gen.make_instance((2, 2, 2), (40, 150), gen.COEF_PRECISION, 3, 1111)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=32)
+    K = torch.from_numpy(inst.K).cuda()
+    B = torch.from_numpy(inst.B).cuda()
+    f = d3m.Factor(plan, 1, nrhs_max=3, growth_dmin=1e30)
+    f.factorize(K)
+    X = f.solve(B).cpu().numpy()
+    st = f.status()
+    assert st["status"] == 0 and st["fallbacks"] == plan.info["ntiles"], st
+    assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, inst.B).max() <= 1e-10
+    # the FP64 tiles make x0 at least as good as the plain complex64 factor
+    g = d3m.Factor(plan, 1, nrhs_max=3)
+    g.factorize(K)
+    g.solve(B)
+    sg = g.status()
+    assert sg["fallbacks"] == 0
+    assert st["eta_hist"][0] <= 2 * sg["eta_hist"][0]
+    # with the fallback switched off nothing is re-factored
+    h = d3m.Factor(plan, 1, nrhs_max=3, growth_dmin=1e30, fallback=False)
+    h.factorize(K)
+    h.solve(B)
+    assert h.status()["fallbacks"] == 0
