@@ -95,7 +95,6 @@ constexpr int GE_THREADS = 512;  // 8 waves
 template <typename T> struct GeKB;
 template <> struct GeKB<float> { static constexpr int KB = 16, LOG = 4; };
 template <> struct GeKB<double> { static constexpr int KB = 8, LOG = 3; };
-constexpr int GE_KBMAX = 16;
 
 enum OpMode : int { OP_N = 0, OP_T = 1, OP_SYM = 2 };
 
@@ -117,6 +116,12 @@ template <typename T> struct Out {
   const typename Cplx<T>::type* coldiv;     // divide column j by coldiv[j], or null
 };
 
+// Accumulator of one wave: 8 column blocks of 16x16.  complex128 keeps the
+// real and imaginary parts.  complex64 uses three real products per complex
+// product (Gauss): P1 = sum ar*br, P2 = sum ai*bi, P3 = sum (ar+ai)(br+bi),
+// so re = P1 - P2 and im = P3 - P1 - P2; this takes 3 instead of 4 MFMAs per
+// block and k-step.  The parts stay separate until read with acc_val, so
+// several gemm_acc calls may add into one accumulator.
 template <typename T> struct Acc {
   typename V4<T>::type re[8], im[8];
   __device__ __forceinline__ void zero() {
@@ -127,6 +132,32 @@ template <typename T> struct Acc {
     }
   }
 };
+template <> struct Acc<float> {
+  v4f p1[8], p2[8], p3[8];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      p1[b] = v4f{0, 0, 0, 0};
+      p2[b] = v4f{0, 0, 0, 0};
+      p3[b] = v4f{0, 0, 0, 0};
+    }
+  }
+};
+
+// Complex value of accumulator item v of column block bj.
+__device__ __forceinline__ cpx<double> acc_val(const Acc<double>& a, int bj, int v) {
+  cpx<double> r;
+  r.x = a.re[bj][v];
+  r.y = a.im[bj][v];
+  return r;
+}
+__device__ __forceinline__ cpx<float> acc_val(const Acc<float>& a, int bj, int v) {
+  cpx<float> r;
+  const float x = a.p1[bj][v], y = a.p2[bj][v];
+  r.x = x - y;
+  r.y = a.p3[bj][v] - x - y;
+  return r;
+}
 
 // LDS bytes the engine needs.
 // Two slab buffers (double buffering), each holding the A and B slabs.
@@ -218,24 +249,44 @@ __device__ __forceinline__ void ge_stash(const Slab<T>& sl, int amode, bool scal
 }
 
 // One LDS slab into the accumulator: NBJ column blocks (compile time, so the
-// fragment reads of a k-step are issued together ahead of its MFMAs).
-template <typename T, int NBJ>
-__device__ __forceinline__ void ge_mma(Acc<T>& acc, const D3M_LDS cpx<T>* ap, const D3M_LDS cpx<T>* bp) {
+// fragment reads of a k-step are issued together ahead of its MFMAs), k-steps
+// below kend (the slab's columns beyond k hold zeros and are skipped).
+template <int NBJ>
+__device__ __forceinline__ void ge_mma(Acc<double>& acc, const D3M_LDS cpx<double>* ap,
+                                       const D3M_LDS cpx<double>* bp, int kend) {
   // one k-step at a time keeps the fragment registers few (the other wave
   // on the SIMD covers the LDS latency)
 #pragma unroll 1
-  for (int kk = 0; kk < GeKB<T>::KB; kk += 4) {
-    const cpx<T> a0 = ap[kk * GE_LDP];
-    cpx<T> b[NBJ];
+  for (int kk = 0; kk < kend; kk += 4) {
+    const cpx<double> a0 = ap[kk * GE_LDP];
+    cpx<double> b[NBJ];
 #pragma unroll
     for (int bj = 0; bj < NBJ; ++bj) b[bj] = bp[kk * GE_LDP + 16 * bj];
-    const T nai = -a0.y;
+    const double nai = -a0.y;
 #pragma unroll
     for (int bj = 0; bj < NBJ; ++bj) {
       acc.re[bj] = mfma16(a0.x, b[bj].x, acc.re[bj]);
       acc.re[bj] = mfma16(nai, b[bj].y, acc.re[bj]);
       acc.im[bj] = mfma16(a0.x, b[bj].y, acc.im[bj]);
       acc.im[bj] = mfma16(a0.y, b[bj].x, acc.im[bj]);
+    }
+  }
+}
+template <int NBJ>
+__device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>* ap,
+                                       const D3M_LDS cpx<float>* bp, int kend) {
+#pragma unroll 1
+  for (int kk = 0; kk < kend; kk += 4) {
+    const cpx<float> a0 = ap[kk * GE_LDP];
+    cpx<float> b[NBJ];
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj) b[bj] = bp[kk * GE_LDP + 16 * bj];
+    const float as = a0.x + a0.y;
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj) {
+      acc.p1[bj] = mfma16(a0.x, b[bj].x, acc.p1[bj]);
+      acc.p2[bj] = mfma16(a0.y, b[bj].y, acc.p2[bj]);
+      acc.p3[bj] = mfma16(as, b[bj].x + b[bj].y, acc.p3[bj]);
     }
   }
 }
@@ -272,9 +323,10 @@ __device__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
       const D3M_LDS cpx<T>* bp = cur + KB * GE_LDP + lk * GE_LDP + lr;
       // three widths only (more variants make the allocator copy the
       // accumulator); LDS columns beyond n hold zeros
-      if (nbj > 4) ge_mma<T, 8>(acc, ap, bp);
-      else if (nbj > 1) ge_mma<T, 4>(acc, ap, bp);
-      else ge_mma<T, 1>(acc, ap, bp);
+      const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KB ? k - p0 : KB);
+      if (nbj > 4) ge_mma<8>(acc, ap, bp, kend);
+      else if (nbj > 1) ge_mma<4>(acc, ap, bp, kend);
+      else ge_mma<1>(acc, ap, bp, kend);
     }
     if (p0 + KB < k) {
       ge_stash<T>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
@@ -333,9 +385,9 @@ __device__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * w + acc_row<T>(lk, v);
-        cpx<T> r;
-        r.x = o.alpha * acc.re[bj][v];
-        r.y = o.alpha * acc.im[bj][v];
+        cpx<T> r = acc_val(acc, bj, v);
+        r.x *= o.alpha;
+        r.y *= o.alpha;
         if (o.src) {
           r.x += o.beta * src[b4][v].x;
           r.y += o.beta * src[b4][v].y;
