@@ -166,16 +166,22 @@ __device__ __forceinline__ void atomic_max_pos(double* p, double v) {
 }
 
 // R(internal rows of the tile) = B - K X; X, R internal, RHS fastest; B user
-// layout.  Column maxima of |r| go to colmax.
+// layout.  Column maxima of |r| go to colmax.  Workgroup (x, y) takes row
+// tile x and right-hand sides [64y, 64y + 64), so each wave holds four
+// 16-column FP64 accumulator blocks (no register spills at any nrhs).
+constexpr int kResCols = 64;
 __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const double2* B, int64_t ld,
                                                   const double2* X, double2* R, double* colmax, UserView uv,
                                                   const RTaskDev* rt, int nrhs, const int32_t* skip) {
+  constexpr int NB = kResCols / 16;
   __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double>()];
-  __shared__ unsigned long long cmax[GE_TN];
+  __shared__ unsigned long long cmax[kResCols];
   if (skip && *skip) return;
   const RTaskDev t = rt[blockIdx.x];
   const int I = t.I;
   const int nI = uv.n[I];
+  const int j0 = kResCols * blockIdx.y;
+  const int nr = nrhs - j0 < kResCols ? nrhs - j0 : kResCols;
   Acc<double> acc;
   acc.zero();
   for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
@@ -187,28 +193,28 @@ __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const d
     else if (b.mode == 1) { A.p = K + b.koff + t.r0; A.ld = nI; A.mode = OP_N; }
     else { A.p = K + b.koff + (int64_t)t.r0 * nJ; A.ld = nJ; A.mode = OP_T; }
     Opnd<double> Bo;
-    Bo.p = X + uv.prow0[b.J] * nrhs;
+    Bo.p = X + uv.prow0[b.J] * nrhs + j0;
     Bo.ld = nrhs;
     Bo.mode = OP_N;
     Bo.i0 = 0;
-    gemm_acc<double>(acc, t.sz, nrhs, nJ, A, nullptr, Bo, (lds_char*)lds);
+    gemm_acc<double, NB>(acc, t.sz, nr, nJ, A, nullptr, Bo, (lds_char*)lds);
   }
-  if (threadIdx.x < GE_TN) cmax[threadIdx.x] = 0ull;
+  if (threadIdx.x < kResCols) cmax[threadIdx.x] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const double2* src = B + uv.row0[I] + t.r0;
-  double2* dst = R + (uv.prow0[I] + t.r0) * nrhs;
+  const double2* src = B + uv.row0[I] + t.r0 + (int64_t)j0 * ld;
+  double2* dst = R + (uv.prow0[I] + t.r0) * nrhs + j0;
   if (16 * w < t.sz) {
 #pragma unroll
-    for (int bj = 0; bj < 8; ++bj) {
+    for (int bj = 0; bj < NB; ++bj) {
       const int j = 16 * bj + lr;
-      if (16 * bj >= nrhs) continue;
+      if (16 * bj >= nr) continue;
       double mx = 0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * w + acc_row<double>(lk, v);
-        if (i < t.sz && j < nrhs) {
+        if (i < t.sz && j < nr) {
           double2 s = src[i + (int64_t)j * ld];
           double2 r;
           r.x = s.x - acc.re[bj][v];
@@ -219,17 +225,19 @@ __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const d
           mx = fmax(mx, a);
         }
       }
-      if (j < nrhs) atomicMax(&cmax[j], (unsigned long long)__double_as_longlong(mx));
+      if (j < nr) atomicMax(&cmax[j], (unsigned long long)__double_as_longlong(mx));
     }
   }
   __syncthreads();
-  if (threadIdx.x < nrhs) atomic_max_pos(colmax + threadIdx.x, __longlong_as_double((long long)cmax[threadIdx.x]));
+  if (threadIdx.x < nr)
+    atomic_max_pos(colmax + j0 + threadIdx.x, __longlong_as_double((long long)cmax[threadIdx.x]));
 }
 
 hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64,
                            double* colmax, const UserView& uv, const RTaskDev* rt, int nrt, int nrhs,
                            const int32_t* skip, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(nrt), dim3(kThreads), 0, s, (const double2*)K, (const double2*)B, ld,
+  const int ny = (nrhs + kResCols - 1) / kResCols;
+  hipLaunchKernelGGL(k_residual, dim3(nrt, ny), dim3(kThreads), 0, s, (const double2*)K, (const double2*)B, ld,
                      (const double2*)X64, (double2*)R64, colmax, uv, rt, nrhs, skip);
   return hipGetLastError();
 }

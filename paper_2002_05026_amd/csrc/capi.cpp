@@ -59,13 +59,20 @@ void make_tables(const PlanImpl& p, Tables& t) {
     for (auto& b : p.rrow[i]) t.rblk.push_back({b.koff, b.J, b.mode});
     t.rptr[i + 1] = (int32_t)t.rblk.size();
   }
+  // residual / norm row tiles, largest work (rows x row length of K) first,
+  // so that the hardware's in-order dispatch balances the tail
+  std::vector<std::pair<int64_t, RTaskDev>> rts;
   for (int i = 0; i < p.nb; ++i) {
+    int64_t len = 0;
+    for (auto& b : p.rrow[i]) len += p.n[b.J];
     const Panel& P = p.panels[p.pos[i]];
     for (int c = 0; c < P.nt; ++c) {
       const Tile& T = p.tiles[P.tile0 + c];
-      t.rt.push_back({i, T.r0, T.sz, 0});
+      rts.push_back({(int64_t)T.sz * len, RTaskDev{i, T.r0, T.sz, 0}});
     }
   }
+  std::stable_sort(rts.begin(), rts.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  for (auto& r : rts) t.rt.push_back(r.second);
   auto add_dk = [&](int64_t koff, int I, int J) {
     for (int r0 = 0; r0 < p.n[I]; r0 += kTileMax)
       for (int c0 = 0; c0 < p.n[J]; c0 += kTileMax)

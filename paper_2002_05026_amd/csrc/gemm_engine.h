@@ -293,7 +293,9 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
 
 // acc += A * diag(dA) * B^T over k columns.  Starts and ends with a barrier,
 // so callers may overwrite the operands (or LDS) right after it returns.
-template <typename T>
+// NBMAX (8, 4 or 1) bounds n by 16 * NBMAX at compile time; callers whose n
+// is known to be small pass it so that only the narrow accumulators stay live.
+template <typename T, int NBMAX = 8>
 __device__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
   constexpr int KB = GeKB<T>::KB;
@@ -324,8 +326,8 @@ __device__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
       // three widths only (more variants make the allocator copy the
       // accumulator); LDS columns beyond n hold zeros
       const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KB ? k - p0 : KB);
-      if (nbj > 4) ge_mma<8>(acc, ap, bp, kend);
-      else if (nbj > 1) ge_mma<4>(acc, ap, bp, kend);
+      if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
+      else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
       else ge_mma<1>(acc, ap, bp, kend);
     }
     if (p0 + KB < k) {

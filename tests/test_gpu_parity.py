@@ -106,6 +106,22 @@ def test_small_mixed_ir_parity(grid, lo, hi, tile):
     assert _fwd_err(X, Xo) <= 1e-8
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wide_rhs_parity(precision):
+    # 100 right-hand sides: the FP64 residual runs in chunks of 64 columns
+    # (one full, one ragged); every column must be certified
+    inst = gen.make_instance((2, 2, 2), (40, 120), gen.COEF_PRECISION, 100, 505)
+    plan, f, Kt, Bt, X, st = _run(inst, precision, tile=32, tol=1e-10, max_iter=10)
+    assert st["status"] == 0, st
+    eta = oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, inst.B)
+    bound = 1e-12 if precision == 0 else 1e-10
+    assert eta.max() <= bound
+    assert 0 <= st["eta"] <= bound
+    order = oracle.nd_order(inst.grid)
+    p, Xo = _oracle_solution(inst, order, inst.B)
+    assert _fwd_err(X, Xo) <= (1e-10 if precision == 0 else 1e-8)
+
+
 def test_host_sync_refinement_matches_device_flag():
     inst = gen.make_instance((2, 2, 2), (30, 60), gen.COEF_PLAIN, 2, 303)
     _, _, _, _, X1, s1 = _run(inst, 1, tile=32)
