@@ -574,60 +574,81 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
 
   // ---- solve DAG: forward (elimination order), then backward (reverse).
   // W holds b (then x), Z holds z = D^-1 L^-1 b (then t); the diagonal
-  // blocks are applied through their precomputed inverses, one tile each.
+  // blocks are applied through their precomputed inverses.  The solve cuts
+  // each factor tile into row tiles of at most kSolveTile rows: a solve task
+  // has only nrhs columns, and a 64-row task keeps one wave per SIMD busy in
+  // about half the time of a 128-row one, which shortens the chains of
+  // updates into one tile that bound the solve.  Solve tiles never cross a
+  // factor tile: the tile rows of Linv_II are only valid left of the end of
+  // their factor tile (the upper tiles serve the INV tasks as staging).
+  constexpr int kSolveTile = 64;
+  std::vector<int> st0(nb + 1, 0);  // solve tiles of panel I: st0[I] .. st0[I+1]-1
+  std::vector<std::pair<int, int>> stl;  // (r0, sz)
+  for (int I = 0; I < nb; ++I) {
+    const Panel& P = p.panels[I];
+    for (int c = 0; c < P.nt; ++c) {
+      const Tile& T = p.tiles[P.tile0 + c];
+      const int nt = (T.sz + kSolveTile - 1) / kSolveTile;
+      for (int q = 0; q < nt; ++q) {
+        const int r0 = T.sz * q / nt, r1 = T.sz * (q + 1) / nt;
+        stl.push_back({T.r0 + r0, r1 - r0});
+      }
+    }
+    st0[I + 1] = (int)stl.size();
+  }
   GenDag sg;
   std::vector<std::vector<Access>> sacc;
-  std::vector<int> lastb(p.tiles.size(), -1), lastz(p.tiles.size(), -1);
+  std::vector<int> lastb(stl.size(), -1), lastz(stl.size(), -1);
   std::vector<std::vector<int>> ftile(nb), btile(nb);
   const int64_t kWKey = 1LL << 60, kZKey = 1LL << 58;
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
     std::vector<int32_t> inpr;
-    for (int c = 0; c < P.nt; ++c) inpr.push_back(lastb[P.tile0 + c]);
-    for (int c = 0; c < P.nt; ++c) {
-      const Tile& T = p.tiles[P.tile0 + c];
+    for (int c = st0[I]; c < st0[I + 1]; ++c) inpr.push_back(lastb[c]);
+    for (int c = st0[I]; c < st0[I + 1]; ++c) {
+      const int r0 = stl[c].first, sz = stl[c].second;
       Task t{};
       t.kind = TK_FTILE;
       t.panel = I;
-      t.m = T.sz;
-      t.k = T.r0 + T.sz;
+      t.m = sz;
+      t.k = r0 + sz;
       t.lda = P.n;
-      t.aux = P.tile0 + c;
-      t.a_off = P.ioff + T.r0;
+      t.aux = c;
+      t.a_off = P.ioff + r0;
       t.b_off = P.prow0;
-      t.c_off = P.prow0 + T.r0;
-      t.dofs = P.prow0 + T.r0;
-      std::vector<Access> ac{{kZKey | (P.tile0 + c), true}};
-      for (int q = 0; q < P.nt; ++q) ac.push_back({kWKey | (P.tile0 + q), false});
-      double fl = 8.0 * T.sz * (double)(T.r0 + T.sz);
-      int id = sg.add(t, inpr, w_stream(8.0 * T.sz * (T.r0 + T.sz), fl));
+      t.c_off = P.prow0 + r0;
+      t.dofs = P.prow0 + r0;
+      std::vector<Access> ac{{kZKey | c, true}};
+      for (int q = st0[I]; q < st0[I + 1]; ++q) ac.push_back({kWKey | q, false});
+      double fl = 8.0 * sz * (double)(r0 + sz);
+      int id = sg.add(t, inpr, w_stream(8.0 * sz * (r0 + sz), fl));
       ftile[I].push_back(id);
-      lastz[P.tile0 + c] = id;
+      lastz[c] = id;
       sacc.push_back(ac);
     }
     for (int b = 1; b < P.npb; ++b) {
       const PBlock& B = p.pblocks[P.pb0 + b];
       const Panel& PJ = p.panels[B.J];
-      for (int r = 0; r < PJ.nt; ++r) {
-        const Tile& T = p.tiles[PJ.tile0 + r];
+      for (int r = st0[B.J]; r < st0[B.J + 1]; ++r) {
+        const int r0 = stl[r].first, sz = stl[r].second;
         Task u{};
         u.kind = TK_FUPD;
         u.panel = I;
-        u.m = T.sz;
+        u.m = sz;
         u.k = P.n;
         u.lda = P.H;
         u.dofs = P.prow0;
-        u.aux = PJ.tile0 + r;
-        u.a_off = P.off + B.prow + T.r0;
+        u.aux = r;
+        u.a_off = P.off + B.prow + r0;
         u.b_off = P.prow0;               // rows of z_I in Z
-        u.c_off = PJ.prow0 + T.r0;       // rows of b_r in W
+        u.c_off = PJ.prow0 + r0;         // rows of b_r in W
         std::vector<int32_t> pr2(ftile[I]);
-        pr2.push_back(lastb[PJ.tile0 + r]);
-        std::vector<Access> ac2{{kWKey | (PJ.tile0 + r), true}};
-        for (int c = 0; c < P.nt; ++c) ac2.push_back({kZKey | (P.tile0 + c), false});
-        double byt = 16.0 * T.sz * P.n, fl2 = 8.0 * T.sz * P.n;
+        pr2.push_back(lastb[r]);
+        std::vector<Access> ac2{{kWKey | r, true}};
+        for (int c = st0[I]; c < st0[I + 1]; ++c) ac2.push_back({kZKey | c, false});
+        double byt = 16.0 * sz * P.n, fl2 = 8.0 * sz * P.n;
         int uid = sg.add(u, pr2, w_stream(byt, fl2));
-        lastb[PJ.tile0 + r] = uid;
+        lastb[r] = uid;
         sacc.push_back(ac2);
       }
     }
@@ -641,49 +662,49 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   for (int J = nb - 1; J >= 0; --J) {
     const Panel& PJ = p.panels[J];
     std::vector<int32_t> zpr;
-    for (int c = 0; c < PJ.nt; ++c) zpr.push_back(lastz[PJ.tile0 + c]);
-    for (int c = 0; c < PJ.nt; ++c) {
-      const Tile& T = p.tiles[PJ.tile0 + c];
+    for (int c = st0[J]; c < st0[J + 1]; ++c) zpr.push_back(lastz[c]);
+    for (int c = st0[J]; c < st0[J + 1]; ++c) {
+      const int r0 = stl[c].first, sz = stl[c].second;
       Task t{};
       t.kind = TK_BTILE;
       t.panel = J;
-      t.m = T.sz;
-      t.k = PJ.n - T.r0;
+      t.m = sz;
+      t.k = PJ.n - r0;
       t.lda = PJ.n;
-      t.aux = PJ.tile0 + c;
-      t.a_off = PJ.ioff + T.r0 + (int64_t)T.r0 * PJ.n;
-      t.b_off = PJ.prow0 + T.r0;
-      t.c_off = PJ.prow0 + T.r0;
-      std::vector<Access> ac{{kWKey | (PJ.tile0 + c), true}};
-      for (int q = 0; q < PJ.nt; ++q) ac.push_back({kZKey | (PJ.tile0 + q), false});
-      double fl = 8.0 * T.sz * (double)(PJ.n - T.r0);
-      int id = sg.add(t, zpr, w_stream(8.0 * T.sz * (PJ.n - T.r0), fl));
+      t.aux = c;
+      t.a_off = PJ.ioff + r0 + (int64_t)r0 * PJ.n;
+      t.b_off = PJ.prow0 + r0;
+      t.c_off = PJ.prow0 + r0;
+      std::vector<Access> ac{{kWKey | c, true}};
+      for (int q = st0[J]; q < st0[J + 1]; ++q) ac.push_back({kZKey | q, false});
+      double fl = 8.0 * sz * (double)(PJ.n - r0);
+      int id = sg.add(t, zpr, w_stream(8.0 * sz * (PJ.n - r0), fl));
       btile[J].push_back(id);
-      lastb[PJ.tile0 + c] = id;
+      lastb[c] = id;
       sacc.push_back(ac);
     }
     for (auto& h : holders[J]) {
       const int I = h.first;
       const Panel& P = p.panels[I];
-      for (int c = 0; c < P.nt; ++c) {
-        const Tile& T = p.tiles[P.tile0 + c];
+      for (int c = st0[I]; c < st0[I + 1]; ++c) {
+        const int r0 = stl[c].first, sz = stl[c].second;
         Task u{};
         u.kind = TK_BUPD;
         u.panel = I;
-        u.m = T.sz;
+        u.m = sz;
         u.k = PJ.n;
         u.lda = P.H;
-        u.aux = P.tile0 + c;
-        u.a_off = P.off + h.second + (int64_t)T.r0 * P.H;
+        u.aux = c;
+        u.a_off = P.off + h.second + (int64_t)r0 * P.H;
         u.b_off = PJ.prow0;              // rows of x_J in W
-        u.c_off = P.prow0 + T.r0;        // rows of t_c in Z
+        u.c_off = P.prow0 + r0;          // rows of t_c in Z
         std::vector<int32_t> pr2(btile[J]);
-        pr2.push_back(lastz[P.tile0 + c]);
-        std::vector<Access> ac2{{kZKey | (P.tile0 + c), true}};
-        for (int cc = 0; cc < PJ.nt; ++cc) ac2.push_back({kWKey | (PJ.tile0 + cc), false});
-        double byt = 16.0 * T.sz * PJ.n, fl2 = 8.0 * T.sz * PJ.n;
+        pr2.push_back(lastz[c]);
+        std::vector<Access> ac2{{kZKey | c, true}};
+        for (int cc = st0[J]; cc < st0[J + 1]; ++cc) ac2.push_back({kWKey | cc, false});
+        double byt = 16.0 * sz * PJ.n, fl2 = 8.0 * sz * PJ.n;
         int uid = sg.add(u, pr2, w_stream(byt, fl2));
-        lastz[P.tile0 + c] = uid;
+        lastz[c] = uid;
         sacc.push_back(ac2);
       }
     }
