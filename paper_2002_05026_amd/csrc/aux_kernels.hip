@@ -439,6 +439,7 @@ __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const doubl
   o.alpha = -0.5;
   o.beta = 0;
   o.rowdiv = o.coldiv = nullptr;
+  o.dst2 = nullptr;
   gemm_store<double>(acc, t.m, t.n, o);
 }
 
@@ -502,6 +503,7 @@ __global__ __launch_bounds__(kThreads) void k_debug_gemm(int m, int n, int k, in
   o.alpha = alpha;
   o.beta = beta;
   o.rowdiv = o.coldiv = nullptr;
+  o.dst2 = nullptr;
   gemm_store<T>(acc, m, n, o);
 }
 
@@ -546,6 +548,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type*
     o.alpha = -1;
     o.beta = 1;
     o.rowdiv = o.coldiv = nullptr;
+    o.dst2 = nullptr;
     gemm_store<T>(acc, 128, 128, o);
   }
 }

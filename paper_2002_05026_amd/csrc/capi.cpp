@@ -26,7 +26,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout of one factor.
 struct Layout {
-  size_t L, D, Linv, W, Z, X64, R64, norms, ctrl, status, growth, counters, flags;
+  size_t L, LD, D, Linv, W, Z, X64, R64, norms, ctrl, status, growth, counters, flags;
   size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, iv;
   size_t kp, fills, rt, rptr, rblk, nI, row0, prow0, perm, dkt;
   size_t total;
@@ -88,6 +88,7 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
   l.L = take(p.L_elems * es);
+  l.LD = take(p.L_elems * es);
   l.D = take(p.N * es);
   l.Linv = take(p.Linv_elems * es);
   l.W = take((size_t)p.N * nrhs_max * es);
@@ -364,6 +365,7 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
   };
   InstView iv{};
   iv.L = f->ws + f->lay.L;
+  iv.LD = f->ws + f->lay.LD;
   iv.D = f->ws + f->lay.D;
   iv.Linv = f->ws + f->lay.Linv;
   iv.W = f->ws + f->lay.W;

@@ -71,6 +71,7 @@ struct Tile {
 // factor precision (complex64 or complex128).
 struct InstView {
   void* L;           // panel storage
+  void* LD;          // same layout: L_rc D_c below each diagonal tile (the scaled update operand)
   void* D;           // N diagonal pivots, internal order
   void* Linv;        // per panel: inverse of the unit lower diagonal block
   void* W;           // solve vectors, internal order, RHS fastest: W[row * nrhs + j] (b, then x)

@@ -26,6 +26,7 @@ namespace d3m {
 template <typename T> struct Ctx {
   typedef typename Cplx<T>::type C;
   C* L;
+  C* LD;  // L_rc D_c (written by the TRSM tasks)
   C* D;
   C* Li;
   C* W;
@@ -56,6 +57,7 @@ __device__ __forceinline__ Out<T> outp(typename Cplx<T>::type* dst, int64_t rs, 
   o.scs = cs;
   o.alpha = alpha;
   o.beta = beta;
+  o.dst2 = nullptr;
   o.rowdiv = nullptr;
   o.coldiv = nullptr;
   return o;
@@ -84,23 +86,25 @@ __device__ __noinline__ void task_fact(const Ctx<T>& cx, const Task& t) {
   }
 }
 
-// L_rc = A_rc Linv_c^T D_c^-1, in place (TK_TRSM)
+// L_rc = A_rc Linv_c^T D_c^-1, in place, and L_rc D_c = A_rc Linv_c^T into
+// LD at the same place (TK_TRSM)
 template <typename T>
 __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
   gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr, opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
   Out<T> o = outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0);
+  o.dst2 = cx.LD + t.a_off;
   o.coldiv = cx.D + t.dofs;
   gemm_store<T>(acc, t.m, t.n, o);
 }
 
+// C -= (L D) L^T on one tile pair (TK_XUPD)
 template <typename T>
 __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), cx.D + t.dofs,
-              opn<T>(cx.L + t.b_off, t.lda), cx.lds);
+  gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.LD + t.a_off, t.lda), nullptr, opn<T>(cx.L + t.b_off, t.lda), cx.lds);
   gemm_store<T>(acc, t.m, t.n, outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1));
 }
 
@@ -139,14 +143,13 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx, const Task& t) {
   gemm_store<T>(acc, t.m, nr, o);
 }
 
-// forward update: b_r -= L_rI D_I z_I
+// forward update: b_r -= (L_rI D_I) z_I
 template <typename T>
 __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.L + t.a_off, t.lda), cx.D + t.dofs,
-              opn<T>(cx.Z + t.b_off * nr, nr), cx.lds);
+  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.LD + t.a_off, t.lda), nullptr, opn<T>(cx.Z + t.b_off * nr, nr), cx.lds);
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
 
@@ -178,6 +181,7 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
   Ctx<T> cx;
   cx.iv = ivs + t.inst;
   cx.L = reinterpret_cast<C*>(cx.iv->L);
+  cx.LD = reinterpret_cast<C*>(cx.iv->LD);
   cx.D = reinterpret_cast<C*>(cx.iv->D);
   cx.Li = reinterpret_cast<C*>(cx.iv->Linv);
   cx.W = reinterpret_cast<C*>(cx.iv->W);

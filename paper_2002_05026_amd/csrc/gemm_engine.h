@@ -109,6 +109,7 @@ template <typename T> struct Opnd {
 template <typename T> struct Out {
   typename Cplx<T>::type* dst;
   int64_t rs, cs;                           // dst(i,j) = dst[i*rs + j*cs]
+  typename Cplx<T>::type* dst2;             // if non-null: also gets the value before the divisions
   const typename Cplx<T>::type* src;        // beta term (may alias dst), or null
   int64_t srs, scs;
   T alpha, beta;
@@ -296,7 +297,7 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
 // NBMAX (8, 4 or 1) bounds n by 16 * NBMAX at compile time; callers whose n
 // is known to be small pass it so that only the narrow accumulators stay live.
 template <typename T, int NBMAX = 8>
-__device__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
+__device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
   constexpr int KB = GeKB<T>::KB;
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
@@ -346,11 +347,18 @@ template <typename T> __device__ __forceinline__ cpx<T> cpx_div(cpx<T> a, cpx<T>
   return r;
 }
 
-// Write the accumulator through the store descriptor.  All loads (beta
-// term, divisors) are issued first from clamped addresses, then the results
-// are formed and stored.
+// Column blocks whose beta-term loads the store issues before its first
+// wait: all 8 for complex64, 4 at a time for complex128 (registers).
+template <typename T> struct GeStoreBatch;
+template <> struct GeStoreBatch<float> { static constexpr int NB = 8; };
+template <> struct GeStoreBatch<double> { static constexpr int NB = 4; };
+
+// Write the accumulator through the store descriptor.  All loads of a batch
+// of column blocks (beta term, divisors) are issued first from clamped
+// addresses, then the results are formed and stored.
 template <typename T>
-__device__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
+__device__ __forceinline__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
+  constexpr int NBB = GeStoreBatch<T>::NB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   if (16 * w >= m) return;
@@ -364,12 +372,12 @@ __device__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
     }
   }
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    if (64 * half >= n) break;
-    cpx<T> src[4][4], cd[4];
+  for (int bt = 0; bt < 8 / NBB; ++bt) {
+    if (16 * NBB * bt >= n) break;
+    cpx<T> src[NBB][4], cd[NBB];
 #pragma unroll
-    for (int b4 = 0; b4 < 4; ++b4) {
-      const int bj = 4 * half + b4;
+    for (int b4 = 0; b4 < NBB; ++b4) {
+      const int bj = NBB * bt + b4;
       const int j = 16 * bj + lr;
       const int jc = j < n ? j : 0;
       if (o.coldiv) cd[b4] = *gptr<T>(o.coldiv + jc);
@@ -381,9 +389,10 @@ __device__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
       }
     }
 #pragma unroll
-    for (int b4 = 0; b4 < 4; ++b4) {
-      const int bj = 4 * half + b4;
+    for (int b4 = 0; b4 < NBB; ++b4) {
+      const int bj = NBB * bt + b4;
       const int j = 16 * bj + lr;
+      if (16 * bj >= n) break;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * w + acc_row<T>(lk, v);
@@ -394,6 +403,7 @@ __device__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
           r.x += o.beta * src[b4][v].x;
           r.y += o.beta * src[b4][v].y;
         }
+        if (o.dst2 && i < m && j < n) gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
         if (o.rowdiv) r = cpx_div(r, rd[v]);
         if (o.coldiv) r = cpx_div(r, cd[b4]);
         if (i < m && j < n) dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
