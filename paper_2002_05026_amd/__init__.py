@@ -289,12 +289,13 @@ class Factor:
                 "n_factor_dag": int(ri.n_factor_dag), "n_solve_dag": int(ri.n_solve_dag)}
 
     def set_trace(self, buf=None):
-        """Record per-task timestamps of later DAG launches into the uint8
-        CUDA tensor buf (None stops)."""
+        """Record per-task timestamps of later DAG launches into the CUDA
+        tensor buf (any dtype; its size in bytes is what counts; None stops)."""
         if buf is None:
             _check(lib().d3m_factor_set_trace(self._h, None, 0), "d3m_factor_set_trace")
         else:
-            _check(lib().d3m_factor_set_trace(self._h, _ptr(buf), buf.numel()), "d3m_factor_set_trace")
+            _check(lib().d3m_factor_set_trace(self._h, _ptr(buf), buf.numel() * buf.element_size()),
+                   "d3m_factor_set_trace")
         self._trace = buf
 
     def tasks(self, solve: bool = False) -> dict:

@@ -195,10 +195,23 @@ void finalize(GenDag& g, int P, int sched, TaskDag& out) {
   out.makespan_us = makespan;
 }
 
-// crude per-workgroup rates used only to weight the schedule (microseconds)
-double w_gemm(double flops) { return 2.0 + flops / 1.5e5; }      // ~150 GFLOP/s per CU
-double w_fact(double n) { return 10.0 + 4.0 / 3.0 * n * n * n / 3e4; }
-double w_stream(double bytes, double flops) { return 1.5 + std::max(bytes / 2.5e4, flops / 1.5e5); }
+// Task durations (microseconds) used only to weight the list schedule,
+// fitted to traces of the complex64 tasks on MI355X.  A tile product costs a
+// fixed part (task start, first slab, store) plus its executed MFMA work:
+// rows count as 64 up to 64 rows and as 128 above (waves per SIMD), columns
+// as 16, 64 or 128 (the accumulator widths).
+double tile_work(double m, double n, double k) {
+  const double me = m > 64 ? 128 : 64, ne = n > 64 ? 128 : (n > 16 ? 64 : 16);
+  return 8.0 * me * ne * k;
+}
+double w_gemm(double m, double n, double k) { return 22.0 + tile_work(m, n, k) / 5.5e5; }
+double w_trsm(double m, double n, double k) { return 23.0 + tile_work(m, n, k) / 4.2e5; }
+double w_fact(double n) {
+  const double r = n / 128.0;
+  return 46.0 + 93.0 * r * r * r + 128.0 * r;
+}
+// solve tasks: weighted for 64 right-hand sides
+double w_solve(double m, double k) { return 22.0 + tile_work(m, 64, k) / 5.5e5; }
 
 int64_t key3(int64_t panel, int64_t g, int64_t c) { return (panel << 40) | (g << 12) | c; }
 
@@ -448,7 +461,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         t.b_off = TC.linv_off;
         t.ldc = nI;  // leading dimension of the inverse block
         const int64_t krc = key3(I, rows[r].first, c);
-        int tid = g.add(t, {fid, lw(krc)}, w_gemm(8.0 * TR.sz * (double)TC.sz * TC.sz));
+        int tid = g.add(t, {fid, lw(krc)}, w_trsm(TR.sz, TC.sz, TC.sz));
         lastw[krc] = tid;
         trsm[r] = tid;
         trsm_last[r] = tid;
@@ -474,7 +487,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
           u.b_off = P.off + rows[s2].second + (int64_t)TC.r0 * P.H;
           u.c_off = P.off + rows[r].second + (int64_t)TS.r0 * P.H;
           const int64_t krs = key3(I, rows[r].first, s2);
-          int uid = g.add(u, {trsm[r], trsm[s2], lw(krs)}, w_gemm(8.0 * TR.sz * (double)TS.sz * TC.sz));
+          int uid = g.add(u, {trsm[r], trsm[s2], lw(krs)}, w_gemm(TR.sz, TS.sz, TC.sz));
           lastw[krs] = uid;
           if (want_acc)
             facc.push_back({{krs, true}, {key3(I, rows[r].first, c), false}, {key3(I, rows[s2].first, c), false},
@@ -502,8 +515,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
           v.aux = P.tile0 + r;
           v.dofs = P.tile0 + c;
           std::vector<int32_t> pr{fact_of[r], fact_of[c], prev};
-          double fl = 8.0 * TC.sz * (double)TR.sz * (TR.r0 - TC.r0) + 8.0 * TR.sz * (double)TC.sz * TR.sz;
-          int vid = g.add(v, pr, w_gemm(fl));
+          int vid = g.add(v, pr, w_gemm(TC.sz, TR.sz, TR.r0 - TC.r0) + w_gemm(TR.sz, TC.sz, TR.sz));
           prev = vid;
           if (want_acc) {
             std::vector<Access> ac{{inv_key(P.tile0 + r, P.tile0 + c), true},
@@ -553,8 +565,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
             t.c_off = PK.off + rowJinK + TR.r0 + (int64_t)TS.r0 * PK.H;
             int64_t tk = key3(BK.J, PJ.tile0 + r, s2);
             std::vector<int32_t> pr{trsm_last[ri], trsm_last[si], lw(tk)};
-            double fl = 8.0 * TR.sz * (double)TS.sz * nI;
-            int id = g.add(t, pr, w_gemm(fl));
+            int id = g.add(t, pr, w_gemm(TR.sz, TS.sz, nI));
             lastw[tk] = id;
             if (want_acc) {
               std::vector<Access> ac{{tk, true}};
@@ -620,8 +631,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       t.dofs = P.prow0 + r0;
       std::vector<Access> ac{{kZKey | c, true}};
       for (int q = st0[I]; q < st0[I + 1]; ++q) ac.push_back({kWKey | q, false});
-      double fl = 8.0 * sz * (double)(r0 + sz);
-      int id = sg.add(t, inpr, w_stream(8.0 * sz * (r0 + sz), fl));
+      int id = sg.add(t, inpr, w_solve(sz, r0 + sz));
       ftile[I].push_back(id);
       lastz[c] = id;
       sacc.push_back(ac);
@@ -646,8 +656,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         pr2.push_back(lastb[r]);
         std::vector<Access> ac2{{kWKey | r, true}};
         for (int c = st0[I]; c < st0[I + 1]; ++c) ac2.push_back({kZKey | c, false});
-        double byt = 16.0 * sz * P.n, fl2 = 8.0 * sz * P.n;
-        int uid = sg.add(u, pr2, w_stream(byt, fl2));
+        int uid = sg.add(u, pr2, w_solve(sz, P.n));
         lastb[r] = uid;
         sacc.push_back(ac2);
       }
@@ -677,8 +686,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       t.c_off = PJ.prow0 + r0;
       std::vector<Access> ac{{kWKey | c, true}};
       for (int q = st0[J]; q < st0[J + 1]; ++q) ac.push_back({kZKey | q, false});
-      double fl = 8.0 * sz * (double)(PJ.n - r0);
-      int id = sg.add(t, zpr, w_stream(8.0 * sz * (PJ.n - r0), fl));
+      int id = sg.add(t, zpr, w_solve(sz, PJ.n - r0));
       btile[J].push_back(id);
       lastb[c] = id;
       sacc.push_back(ac);
@@ -702,8 +710,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         pr2.push_back(lastz[c]);
         std::vector<Access> ac2{{kZKey | c, true}};
         for (int cc = st0[J]; cc < st0[J + 1]; ++cc) ac2.push_back({kWKey | cc, false});
-        double byt = 16.0 * sz * PJ.n, fl2 = 8.0 * sz * PJ.n;
-        int uid = sg.add(u, pr2, w_stream(byt, fl2));
+        int uid = sg.add(u, pr2, w_solve(sz, PJ.n));
         lastz[c] = uid;
         sacc.push_back(ac2);
       }
