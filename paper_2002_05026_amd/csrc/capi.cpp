@@ -91,7 +91,7 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.LD = take(p.L_elems * es);
   l.D = take(p.N * es);
   l.Linv = take(p.Linv_elems * es);
-  l.W = take((size_t)p.N * nrhs_max * es);
+  l.W = take((size_t)p.N * nrhs_max * es * (1 + kSolveSlots));  // b and its extra accumulators
   l.Z = take((size_t)p.N * nrhs_max * es);
   l.X64 = take((size_t)p.N * nrhs_max * 16);
   l.R64 = take((size_t)p.N * nrhs_max * 16);

@@ -20,7 +20,13 @@ enum TaskKind : int32_t {
   TK_BUPD = 12,   // backward push into one column tile: z_c(I) -= L_Jc^T x_J
   TK_FTILE = 14,  // forward, one tile of a diagonal block: z_c = D_c^-1 (L_II^-1 b_I)_c
   TK_BTILE = 15,  // backward, one tile of a diagonal block: x_c = (L_II^-T t_I)_c
+  TK_RED = 16,    // forward: b_r += the extra accumulators of tile r
 };
+
+// Extra accumulators of the forward solve: the updates into one row tile of
+// b go round-robin to b itself and kSolveSlots more copies of b (stored after
+// it, N rows each), which a TK_RED task adds into b before the tile is used.
+constexpr int kSolveSlots = 3;
 
 // One task, in ticket order.  Offsets are in complex elements, relative to
 // the instance's base pointers (panel storage L, solve vector W).

@@ -150,7 +150,27 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
   gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.LD + t.a_off, t.lda), nullptr, opn<T>(cx.Z + t.b_off * nr, nr), cx.lds);
-  gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
+  // the first update into an extra accumulator overwrites it (two stores with
+  // a constant beta each, so neither has a per-element branch)
+  if (t.pad0) gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)0));
+  else gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
+}
+
+// b_r += the t.k extra accumulators of tile r (N rows apart) (TK_RED)
+template <typename T>
+__device__ __noinline__ void task_red(const Ctx<T>& cx, const Task& t) {
+  const int64_t nr = cx.nrhs, stride = cx.iv->N * nr;
+  D3M_GLB cpx<T>* w = gptr_mut<T>(cx.W + t.c_off * nr);
+  const int64_t tot = (int64_t)t.m * nr;
+  for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+    cpx<T> v = w[e];
+    for (int q = 1; q <= t.k; ++q) {
+      const cpx<T> u = w[q * stride + e];
+      v.x += u.x;
+      v.y += u.y;
+    }
+    w[e] = v;
+  }
 }
 
 // backward push: t_c(I) -= L_Jc^T x_J for one row block J of panel I
@@ -197,6 +217,7 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
     case TK_FUPD: task_fupd<T>(cx, t); break;
     case TK_BUPD: task_bupd<T>(cx, t); break;
     case TK_BTILE: task_btile<T>(cx, t); break;
+    case TK_RED: task_red<T>(cx, t); break;
     default: break;
   }
 }

@@ -612,8 +612,33 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   std::vector<int> lastb(stl.size(), -1), lastz(stl.size(), -1);
   std::vector<std::vector<int>> ftile(nb), btile(nb);
   const int64_t kWKey = 1LL << 60, kZKey = 1LL << 58;
+  auto wkey = [&](int slot, int r) { return kWKey | ((int64_t)slot << 40) | r; };
+  // forward updates into tile r: count so far, and the last one per extra slot
+  std::vector<int> nupd(stl.size(), 0);
+  std::vector<std::array<int, kSolveSlots + 1>> lastx(stl.size());
+  for (auto& a : lastx) a.fill(-1);
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
+    // sum the extra accumulators of I's tiles into b_I
+    for (int c = st0[I]; c < st0[I + 1]; ++c) {
+      const int used = std::min(nupd[c], kSolveSlots + 1) - 1;
+      if (used <= 0) continue;
+      Task t{};
+      t.kind = TK_RED;
+      t.panel = I;
+      t.m = stl[c].second;
+      t.k = used;
+      t.aux = c;
+      t.c_off = P.prow0 + stl[c].first;
+      std::vector<int32_t> pr{lastb[c]};
+      std::vector<Access> ac{{wkey(0, c), true}};
+      for (int q = 1; q <= used; ++q) {
+        pr.push_back(lastx[c][q]);
+        ac.push_back({wkey(q, c), false});
+      }
+      lastb[c] = sg.add(t, pr, 10.0);
+      sacc.push_back(ac);
+    }
     std::vector<int32_t> inpr;
     for (int c = st0[I]; c < st0[I + 1]; ++c) inpr.push_back(lastb[c]);
     for (int c = st0[I]; c < st0[I + 1]; ++c) {
@@ -630,7 +655,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       t.c_off = P.prow0 + r0;
       t.dofs = P.prow0 + r0;
       std::vector<Access> ac{{kZKey | c, true}};
-      for (int q = st0[I]; q < st0[I + 1]; ++q) ac.push_back({kWKey | q, false});
+      for (int q = st0[I]; q < st0[I + 1]; ++q) ac.push_back({wkey(0, q), false});
       int id = sg.add(t, inpr, w_solve(sz, r0 + sz));
       ftile[I].push_back(id);
       lastz[c] = id;
@@ -641,6 +666,8 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       const Panel& PJ = p.panels[B.J];
       for (int r = st0[B.J]; r < st0[B.J + 1]; ++r) {
         const int r0 = stl[r].first, sz = stl[r].second;
+        // slot of this update: b itself (0) or an extra accumulator
+        const int slot = nupd[r]++ % (kSolveSlots + 1);
         Task u{};
         u.kind = TK_FUPD;
         u.panel = I;
@@ -650,14 +677,16 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         u.dofs = P.prow0;
         u.aux = r;
         u.a_off = P.off + B.prow + r0;
-        u.b_off = P.prow0;               // rows of z_I in Z
-        u.c_off = PJ.prow0 + r0;         // rows of b_r in W
+        u.b_off = P.prow0;                                // rows of z_I in Z
+        u.c_off = slot * p.N + PJ.prow0 + r0;             // rows of b_r (or a copy) in W
+        u.pad0 = (slot > 0 && lastx[r][slot] < 0) ? 1 : 0;  // first into a copy: overwrite
         std::vector<int32_t> pr2(ftile[I]);
-        pr2.push_back(lastb[r]);
-        std::vector<Access> ac2{{kWKey | r, true}};
+        pr2.push_back(slot == 0 ? lastb[r] : lastx[r][slot]);
+        std::vector<Access> ac2{{wkey(slot, r), true}};
         for (int c = st0[I]; c < st0[I + 1]; ++c) ac2.push_back({kZKey | c, false});
         int uid = sg.add(u, pr2, w_solve(sz, P.n));
-        lastb[r] = uid;
+        if (slot == 0) lastb[r] = uid;
+        else lastx[r][slot] = uid;
         sacc.push_back(ac2);
       }
     }
@@ -684,7 +713,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       t.a_off = PJ.ioff + r0 + (int64_t)r0 * PJ.n;
       t.b_off = PJ.prow0 + r0;
       t.c_off = PJ.prow0 + r0;
-      std::vector<Access> ac{{kWKey | c, true}};
+      std::vector<Access> ac{{wkey(0, c), true}};
       for (int q = st0[J]; q < st0[J + 1]; ++q) ac.push_back({kZKey | q, false});
       int id = sg.add(t, zpr, w_solve(sz, PJ.n - r0));
       btile[J].push_back(id);
@@ -709,7 +738,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         std::vector<int32_t> pr2(btile[J]);
         pr2.push_back(lastz[c]);
         std::vector<Access> ac2{{kZKey | c, true}};
-        for (int cc = st0[J]; cc < st0[J + 1]; ++cc) ac2.push_back({kWKey | cc, false});
+        for (int cc = st0[J]; cc < st0[J + 1]; ++cc) ac2.push_back({wkey(0, cc), false});
         int uid = sg.add(u, pr2, w_solve(sz, PJ.n));
         lastz[c] = uid;
         sacc.push_back(ac2);
