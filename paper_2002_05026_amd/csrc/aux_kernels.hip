@@ -165,26 +165,27 @@ __device__ __forceinline__ void atomic_max_pos(double* p, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
 }
 
-// R(internal rows of the tile) = B - K X; X, R internal, RHS fastest; B user
-// layout.  Column maxima of |r| go to colmax.  Workgroup (x, y) takes row
-// tile x and right-hand sides [64y, 64y + 64), so each wave holds four
-// 16-column FP64 accumulator blocks (no register spills at any nrhs).
+// Partial residual products: workgroup (x, y, z) takes row tile x,
+// right-hand sides [64y, 64y + 64) and chunk z of the tile's block row, and
+// writes P_z = sum over the chunk's blocks K_IJ X_J (internal rows, RHS
+// fastest; zeros for an empty chunk).  Four 16-column FP64 accumulator
+// blocks per wave (no register spills at any nrhs), so the registers allow
+// slabs of 16 columns.
 constexpr int kResCols = 64;
-__global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const double2* B, int64_t ld,
-                                                  const double2* X, double2* R, double* colmax, UserView uv,
+__global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const double2* X, double2* P, UserView uv,
                                                   const RTaskDev* rt, int nrhs, const int32_t* skip) {
-  constexpr int NB = kResCols / 16;
-  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double>()];
-  __shared__ unsigned long long cmax[kResCols];
+  constexpr int NB = kResCols / 16, KB = 16;  // 16-column FP64 slabs: more latency cover per slab
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double, KB>()];
   if (skip && *skip) return;
   const RTaskDev t = rt[blockIdx.x];
   const int I = t.I;
   const int nI = uv.n[I];
   const int j0 = kResCols * blockIdx.y;
   const int nr = nrhs - j0 < kResCols ? nrhs - j0 : kResCols;
+  const int e0 = uv.rsplit[I * (kResSplit + 1) + blockIdx.z], e1 = uv.rsplit[I * (kResSplit + 1) + blockIdx.z + 1];
   Acc<double> acc;
   acc.zero();
-  for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
+  for (int e = e0; e < e1; ++e) {
     const RBlkDev b = uv.rblk[e];
     const int nJ = uv.n[b.J];
     Opnd<double> A;
@@ -197,48 +198,68 @@ __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const d
     Bo.ld = nrhs;
     Bo.mode = OP_N;
     Bo.i0 = 0;
-    gemm_acc<double, NB>(acc, t.sz, nr, nJ, A, nullptr, Bo, (lds_char*)lds);
+    gemm_acc<double, NB, KB>(acc, t.sz, nr, nJ, A, nullptr, Bo, (lds_char*)lds);
   }
-  if (threadIdx.x < kResCols) cmax[threadIdx.x] = 0ull;
-  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const double2* src = B + uv.row0[I] + t.r0 + (int64_t)j0 * ld;
-  double2* dst = R + (uv.prow0[I] + t.r0) * nrhs + j0;
+  double2* dst = P + (int64_t)blockIdx.z * uv.N * nrhs + (uv.prow0[I] + t.r0) * nrhs + j0;
   if (16 * w < t.sz) {
 #pragma unroll
     for (int bj = 0; bj < NB; ++bj) {
       const int j = 16 * bj + lr;
-      if (16 * bj >= nr) continue;
-      double mx = 0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * w + acc_row<double>(lk, v);
         if (i < t.sz && j < nr) {
-          double2 s = src[i + (int64_t)j * ld];
           double2 r;
-          r.x = s.x - acc.re[bj][v];
-          r.y = s.y - acc.im[bj][v];
+          r.x = acc.re[bj][v];
+          r.y = acc.im[bj][v];
           dst[(int64_t)i * nrhs + j] = r;
-          double a = sqrt(r.x * r.x + r.y * r.y);
-          if (!(a == a)) a = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> inf
-          mx = fmax(mx, a);
         }
       }
-      if (j < nr) atomicMax(&cmax[j], (unsigned long long)__double_as_longlong(mx));
     }
   }
-  __syncthreads();
-  if (threadIdx.x < nr)
-    atomic_max_pos(colmax + j0 + threadIdx.x, __longlong_as_double((long long)cmax[threadIdx.x]));
 }
 
-hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64,
+// R = B - sum_z P_z (internal rows, RHS fastest; B in user layout) and the
+// column maxima of |R| into colmax.
+__global__ void k_residual_fin(const double2* B, int64_t ld, const double2* P, double2* R, double* colmax,
+                               UserView uv, int nrhs, const int32_t* skip) {
+  if (skip && *skip) return;
+  __shared__ unsigned long long cm[128];
+  if (threadIdx.x < 128) cm[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t tot = uv.N * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = e / nrhs;
+    const int j = (int)(e - q * nrhs);
+    double2 r = B[uv.perm[q] + (int64_t)j * ld];
+#pragma unroll
+    for (int z = 0; z < kResSplit; ++z) {
+      const double2 p = P[z * tot + e];
+      r.x -= p.x;
+      r.y -= p.y;
+    }
+    R[e] = r;
+    double a = sqrt(r.x * r.x + r.y * r.y);
+    if (!(a == a)) a = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> inf
+    atomicMax(&cm[j], (unsigned long long)__double_as_longlong(a));
+  }
+  __syncthreads();
+  if (threadIdx.x < nrhs && cm[threadIdx.x]) atomic_max_pos(colmax + threadIdx.x, __longlong_as_double((long long)cm[threadIdx.x]));
+}
+
+hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64, void* P,
                            double* colmax, const UserView& uv, const RTaskDev* rt, int nrt, int nrhs,
                            const int32_t* skip, hipStream_t s) {
+  if (nrhs > 128) return hipErrorInvalidValue;
   const int ny = (nrhs + kResCols - 1) / kResCols;
-  hipLaunchKernelGGL(k_residual, dim3(nrt, ny), dim3(kThreads), 0, s, (const double2*)K, (const double2*)B, ld,
-                     (const double2*)X64, (double2*)R64, colmax, uv, rt, nrhs, skip);
+  hipLaunchKernelGGL(k_residual, dim3(nrt, ny, kResSplit), dim3(kThreads), 0, s, (const double2*)K,
+                     (const double2*)X64, (double2*)P, uv, rt, nrhs, skip);
+  const int64_t tot = uv.N * nrhs;
+  const int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_residual_fin, dim3(blocks), dim3(256), 0, s, (const double2*)B, ld, (const double2*)P,
+                     (double2*)R64, colmax, uv, nrhs, skip);
   return hipGetLastError();
 }
 

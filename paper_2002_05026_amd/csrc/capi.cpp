@@ -26,9 +26,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout of one factor.
 struct Layout {
-  size_t L, LD, D, Linv, W, Z, X64, R64, norms, ctrl, status, growth, counters, flags;
+  size_t L, LD, D, Linv, W, Z, X64, R64, P64, norms, ctrl, status, growth, counters, flags;
   size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, iv;
-  size_t kp, fills, rt, rptr, rblk, nI, row0, prow0, perm, dkt;
+  size_t kp, fills, rt, rptr, rblk, rsplit, nI, row0, prow0, perm, dkt;
   size_t total;
 };
 
@@ -37,6 +37,7 @@ struct Tables {
   std::vector<RTaskDev> rt;
   std::vector<int32_t> rptr;
   std::vector<RBlkDev> rblk;
+  std::vector<int32_t> rsplit;
   std::vector<int32_t> nI;
   std::vector<int64_t> row0, prow0;
   std::vector<int32_t> perm;
@@ -58,6 +59,23 @@ void make_tables(const PlanImpl& p, Tables& t) {
   for (int i = 0; i < p.nb; ++i) {
     for (auto& b : p.rrow[i]) t.rblk.push_back({b.koff, b.J, b.mode});
     t.rptr[i + 1] = (int32_t)t.rblk.size();
+  }
+  // residual chunks: block z of row i starts at the first block whose
+  // cumulative width reaches z/kResSplit of the row's width
+  t.rsplit.assign((size_t)p.nb * (kResSplit + 1), 0);
+  for (int i = 0; i < p.nb; ++i) {
+    int64_t tot = 0;
+    for (auto& b : p.rrow[i]) tot += p.n[b.J];
+    int32_t* sp = &t.rsplit[(size_t)i * (kResSplit + 1)];
+    int64_t cum = 0;
+    int e = t.rptr[i], z = 1;
+    sp[0] = t.rptr[i];
+    for (auto& b : p.rrow[i]) {
+      cum += p.n[b.J];
+      ++e;
+      while (z < kResSplit && cum * kResSplit >= tot * z) sp[z++] = e;
+    }
+    while (z <= kResSplit) sp[z++] = t.rptr[i + 1];
   }
   // residual / norm row tiles, largest work (rows x row length of K) first,
   // so that the hardware's in-order dispatch balances the tail
@@ -95,6 +113,7 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.Z = take((size_t)p.N * nrhs_max * es);
   l.X64 = take((size_t)p.N * nrhs_max * 16);
   l.R64 = take((size_t)p.N * nrhs_max * 16);
+  l.P64 = take((size_t)kResSplit * p.N * nrhs_max * 16);
   l.norms = take(3 * 128 * sizeof(double));
   l.ctrl = take(sizeof(IrCtrl));
   l.status = take(4 * sizeof(int32_t));
@@ -116,6 +135,7 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.rt = take(t.rt.size() * sizeof(RTaskDev));
   l.rptr = take(t.rptr.size() * sizeof(int32_t));
   l.rblk = take(t.rblk.size() * sizeof(RBlkDev));
+  l.rsplit = take(t.rsplit.size() * sizeof(int32_t));
   l.nI = take(t.nI.size() * sizeof(int32_t));
   l.row0 = take(t.row0.size() * sizeof(int64_t));
   l.prow0 = take(t.prow0.size() * sizeof(int64_t));
@@ -163,6 +183,7 @@ struct d3m_factor_s {
     u.prow0 = at<int64_t>(lay.prow0);
     u.rptr = at<int32_t>(lay.rptr);
     u.rblk = at<RBlkDev>(lay.rblk);
+    u.rsplit = at<int32_t>(lay.rsplit);
     u.perm = at<int32_t>(lay.perm);
     u.N = plan->p.N;
     return u;
@@ -396,6 +417,7 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
             up(f->lay.rt, f->tab.rt.data(), f->tab.rt.size() * sizeof(RTaskDev)) &&
             up(f->lay.rptr, f->tab.rptr.data(), f->tab.rptr.size() * 4) &&
             up(f->lay.rblk, f->tab.rblk.data(), f->tab.rblk.size() * sizeof(RBlkDev)) &&
+            up(f->lay.rsplit, f->tab.rsplit.data(), f->tab.rsplit.size() * 4) &&
             up(f->lay.nI, f->tab.nI.data(), f->tab.nI.size() * 4) &&
             up(f->lay.row0, f->tab.row0.data(), f->tab.row0.size() * 8) &&
             up(f->lay.prow0, f->tab.prow0.data(), f->tab.prow0.size() * 8) &&
@@ -455,7 +477,7 @@ d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int n
     HIPCHK(launch_perm_in(B, ld, W, 0, uv, nrhs, nullptr, s));
     d3m_status st = run_dag(f, true, nrhs, nullptr, s);
     if (st) return st;
-    HIPCHK(launch_residual(K, B, ld, W, R64, f->rmax(), uv, rt, nrt, nrhs, nullptr, s));
+    HIPCHK(launch_residual(K, B, ld, W, R64, f->ws + f->lay.P64, f->rmax(), uv, rt, nrt, nrhs, nullptr, s));
     HIPCHK(launch_colmax(W, N, nrhs, 0, 1, f->xmax(), nullptr, s));
     HIPCHK(launch_ir_check(c, f->rmax(), f->xmax(), f->bmax(), nrhs, 2, s));
     HIPCHK(launch_perm_out(W, X, ld, uv, nrhs, s));
@@ -468,7 +490,7 @@ d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int n
   HIPCHK(launch_cvt_up(W, X64, nel, s));
   const int32_t* stop = f->stop();
   for (int it = 0; it <= f->opt.max_iter; ++it) {
-    HIPCHK(launch_residual(K, B, ld, X64, R64, f->rmax(), uv, rt, nrt, nrhs, stop, s));
+    HIPCHK(launch_residual(K, B, ld, X64, R64, f->ws + f->lay.P64, f->rmax(), uv, rt, nrt, nrhs, stop, s));
     HIPCHK(launch_colmax(X64, N, nrhs, 0, 1, f->xmax(), stop, s));
     HIPCHK(launch_ir_check(c, f->rmax(), f->xmax(), f->bmax(), nrhs, it == f->opt.max_iter ? 1 : 0, s));
     if (f->opt.ir_host_sync) {
@@ -821,7 +843,7 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
       d3m_factor_s* f = b->f[i];
       const int64_t N = f->plan->p.N;
       void* xv = b->prec == 1 ? f->ws + f->lay.X64 : f->ws + f->lay.W;
-      HIPCHK(launch_residual(K[i], B[i], ld[i], xv, f->ws + f->lay.R64, f->rmax(), f->uv(),
+      HIPCHK(launch_residual(K[i], B[i], ld[i], xv, f->ws + f->lay.R64, f->ws + f->lay.P64, f->rmax(), f->uv(),
                              f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), nrhs[i], f->stop(), s));
       HIPCHK(launch_colmax(xv, N, nrhs[i], 0, 1, f->xmax(), f->stop(), s));
       HIPCHK(launch_ir_check(f->ctrl(), f->rmax(), f->xmax(), f->bmax(), nrhs[i],

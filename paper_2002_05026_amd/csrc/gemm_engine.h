@@ -160,11 +160,12 @@ __device__ __forceinline__ cpx<float> acc_val(const Acc<float>& a, int bj, int v
   return r;
 }
 
-// LDS bytes the engine needs.
+// LDS bytes the engine needs for slabs of KB columns.
 // Two slab buffers (double buffering), each holding the A and B slabs.
-template <typename T> constexpr int ge_lds_bytes() {
-  return 2 * 2 * GeKB<T>::KB * GE_LDP * (int)sizeof(typename Cplx<T>::type);
+template <typename T, int KB = GeKB<T>::KB> constexpr int ge_lds_bytes() {
+  return 2 * 2 * KB * GE_LDP * (int)sizeof(typename Cplx<T>::type);
 }
+constexpr int ge_log2(int v) { return v <= 1 ? 0 : 1 + ge_log2(v / 2); }
 
 // Address of A(i, p) for the operand mode (i, p inside the operand).
 template <typename T>
@@ -181,25 +182,25 @@ __device__ __forceinline__ const typename Cplx<T>::type* op_addr(const Opnd<T>& 
 // range elements read the operand's first element) so that they stay in
 // flight while the previous slab is multiplied; masking and the D scaling
 // happen when the slab is written to LDS.
-template <typename T> struct Slab {
-  static constexpr int NE = GeKB<T>::KB * GE_TM / GE_THREADS;  // elements per thread per operand
+template <typename T, int KB = GeKB<T>::KB> struct Slab {
+  static constexpr int NE = KB * GE_TM / GE_THREADS;  // elements per thread per operand
   cpx<T> a[NE], b[NE], d[NE];
   uint32_t amask, bmask;
 };
 
-template <typename T>
-__device__ __forceinline__ void ge_fetch(Slab<T>& sl, const Opnd<T>& A, const typename Cplx<T>::type* dA,
+template <typename T, int KB>
+__device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, const typename Cplx<T>::type* dA,
                                          const Opnd<T>& B, int m, int n, int k, int p0) {
   typedef typename Cplx<T>::type C;
   const int tid = threadIdx.x;
-  constexpr int KB = GeKB<T>::KB, NE = Slab<T>::NE;
+  constexpr int NE = Slab<T, KB>::NE, LOG = ge_log2(KB);
   sl.amask = 0;
   sl.bmask = 0;
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = tid + GE_THREADS * q;
     int i, pp;
-    if (A.mode == OP_T) { pp = e & (KB - 1); i = e >> GeKB<T>::LOG; }
+    if (A.mode == OP_T) { pp = e & (KB - 1); i = e >> LOG; }
     else { i = e & (GE_TM - 1); pp = e >> 7; }
     const int p = p0 + pp;
     const bool ok = (i < m) & (p < k);
@@ -219,16 +220,16 @@ __device__ __forceinline__ void ge_fetch(Slab<T>& sl, const Opnd<T>& A, const ty
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void ge_stash(const Slab<T>& sl, int amode, bool scaled, D3M_LDS cpx<T>* As,
+template <typename T, int KB>
+__device__ __forceinline__ void ge_stash(const Slab<T, KB>& sl, int amode, bool scaled, D3M_LDS cpx<T>* As,
                                          D3M_LDS cpx<T>* Bs) {
   const int tid = threadIdx.x;
-  constexpr int KB = GeKB<T>::KB, NE = Slab<T>::NE;
+  constexpr int NE = Slab<T, KB>::NE, LOG = ge_log2(KB);
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = tid + GE_THREADS * q;
     int i, pp;
-    if (amode == OP_T) { pp = e & (KB - 1); i = e >> GeKB<T>::LOG; }
+    if (amode == OP_T) { pp = e & (KB - 1); i = e >> LOG; }
     else { i = e & (GE_TM - 1); pp = e >> 7; }
     cpx<T> v = sl.a[q];
     if (scaled) {
@@ -296,26 +297,27 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
 // so callers may overwrite the operands (or LDS) right after it returns.
 // NBMAX (8, 4 or 1) bounds n by 16 * NBMAX at compile time; callers whose n
 // is known to be small pass it so that only the narrow accumulators stay live.
-template <typename T, int NBMAX = 8>
+// KB: complex columns per slab (lds holds ge_lds_bytes<T, KB>()); callers
+// with registers to spare take deeper slabs, which cover more load latency.
+template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB>
 __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
-  constexpr int KB = GeKB<T>::KB;
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   D3M_LDS cpx<T>* buf1 = buf0 + 2 * KB * GE_LDP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const bool rowok = 16 * w < m;
   const int nbj = (n + 15) >> 4;
-  Slab<T> sl;
+  Slab<T, KB> sl;
   const bool scaled = dA != nullptr;
   wg_sync_global();
   if (k <= 0 || m <= 0 || n <= 0) return;
   // slab s lives in buffer s & 1: while slab s is multiplied, slab s+1 is
   // written to the other buffer and slab s+2 is loaded into registers; one
   // barrier per slab
-  ge_fetch<T>(sl, A, dA, B, m, n, k, 0);
-  ge_stash<T>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-  if (KB < k) ge_fetch<T>(sl, A, dA, B, m, n, k, KB);
+  ge_fetch<T, KB>(sl, A, dA, B, m, n, k, 0);
+  ge_stash<T, KB>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+  if (KB < k) ge_fetch<T, KB>(sl, A, dA, B, m, n, k, KB);
   __syncthreads();
   int s = 0;
   for (int p0 = 0; p0 < k; p0 += KB, ++s) {
@@ -332,8 +334,8 @@ __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const
       else ge_mma<1>(acc, ap, bp, kend);
     }
     if (p0 + KB < k) {
-      ge_stash<T>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
-      if (p0 + 2 * KB < k) ge_fetch<T>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
+      ge_stash<T, KB>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
+      if (p0 + 2 * KB < k) ge_fetch<T, KB>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
     }
     __syncthreads();
   }

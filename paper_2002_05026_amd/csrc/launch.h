@@ -32,12 +32,17 @@ struct DkTaskDev {
 };
 
 // Per-factor constant tables used by the residual, norm and dK kernels.
+// The residual splits the K blocks of each block row into kResSplit chunks
+// of similar width (one workgroup each, partial products summed afterwards).
+constexpr int kResSplit = 4;
+
 struct UserView {
   const int32_t* n;       // sizes, user numbering
   const int64_t* row0;    // user first row of each interface
   const int64_t* prow0;   // internal first row of each user interface
   const int32_t* rptr;    // block-row CSR over RBlkDev
   const RBlkDev* rblk;
+  const int32_t* rsplit;  // per interface: kResSplit + 1 bounds into rblk
   const int32_t* perm;    // internal row -> user row
   int64_t N;
 };
@@ -68,7 +73,9 @@ hipError_t launch_knorm(const void* K, const UserView& uv, const RTaskDev* rt, i
 hipError_t launch_perm_in(const void* B, int64_t ld, void* W, int prec, const UserView& uv, int nrhs,
                           const int32_t* skip, hipStream_t s);
 hipError_t launch_perm_out(const void* W, void* X, int64_t ld, const UserView& uv, int nrhs, hipStream_t s);
-hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64,
+// R = B - K X (internal order, RHS fastest) and the column maxima of |R|;
+// P: kResSplit * N * nrhs complex128 of scratch for the partial products.
+hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64, void* P,
                            double* colmax, const UserView& uv, const RTaskDev* rt, int nrt, int nrhs,
                            const int32_t* skip, hipStream_t s);
 hipError_t launch_colmax(const void* V, int64_t rows, int nrhs, int64_t ld, int rhs_fastest, double* colmax,
