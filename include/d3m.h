@@ -121,6 +121,7 @@ typedef struct {
    * since the previous d3m_status_sync (summed), and their counts */
   double t_factor_dag_ms, t_solve_dag_ms;
   int32_t n_factor_dag, n_solve_dag;
+  double knorm;         /* ||K||_inf (max row sum of |k_ij|) of the last factorized K  */
 } d3m_run_info;
 
 /* Build the symbolic plan.

@@ -58,7 +58,7 @@ class RunInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("ir_iters", ctypes.c_int32), ("pivot_row", ctypes.c_int64),
                 ("eta", ctypes.c_double), ("eta_hist", ctypes.c_double * 32), ("fallbacks", ctypes.c_int32),
                 ("hang", ctypes.c_int32), ("t_factor_dag_ms", ctypes.c_double), ("t_solve_dag_ms", ctypes.c_double),
-                ("n_factor_dag", ctypes.c_int32), ("n_solve_dag", ctypes.c_int32)]
+                ("n_factor_dag", ctypes.c_int32), ("n_solve_dag", ctypes.c_int32), ("knorm", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -286,7 +286,7 @@ class Factor:
         return {"status": int(code), "ir_iters": int(ri.ir_iters), "pivot_row": int(ri.pivot_row),
                 "eta": float(ri.eta), "eta_hist": hist, "fallbacks": int(ri.fallbacks), "hang": int(ri.hang),
                 "t_factor_dag_ms": float(ri.t_factor_dag_ms), "t_solve_dag_ms": float(ri.t_solve_dag_ms),
-                "n_factor_dag": int(ri.n_factor_dag), "n_solve_dag": int(ri.n_solve_dag)}
+                "n_factor_dag": int(ri.n_factor_dag), "n_solve_dag": int(ri.n_solve_dag), "knorm": float(ri.knorm)}
 
     def set_trace(self, buf=None):
         """Record per-task timestamps of later DAG launches into the CUDA

@@ -263,42 +263,74 @@ hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void*
   return hipGetLastError();
 }
 
-// ||K||_inf: row sums of |k_ij| of the symmetric K, then the maximum.
-__global__ __launch_bounds__(256) void k_knorm(const double2* K, UserView uv, const RTaskDev* rt, IrCtrl* ctrl) {
+// ||K||_inf: row sums of |k_ij| of the symmetric K, then the maximum.  One
+// workgroup per row tile.  Every access runs along the stored blocks' unit
+// stride: blocks read by columns (K_IJ, and the lower part of the diagonal
+// block) with lanes over rows, blocks read by rows (K_JI^T, and the upper
+// part of the diagonal block from its lower triangle) with lanes over
+// columns.  Partial sums are combined in a fixed order (deterministic).
+__global__ __launch_bounds__(512) void k_knorm(const double2* K, UserView uv, const RTaskDev* rt, IrCtrl* ctrl) {
   const RTaskDev t = rt[blockIdx.x];
   const int I = t.I, nI = uv.n[I];
-  __shared__ double rowsum[kTileMax];
-  for (int i = threadIdx.x; i < t.sz; i += 256) rowsum[i] = 0;
-  __syncthreads();
-  // one wave per row, lanes over columns
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int i = w; i < t.sz; i += 4) {
+  __shared__ double part[5][kTileMax];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // lanes over rows: thread (row i, group g) sums the columns p = g mod 4
+  {
+    const int i = tid & (kTileMax - 1), g = tid >> 7;
+    double s = 0;
+    if (i < t.sz) {
+      const int gi = t.r0 + i;
+      for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
+        const RBlkDev b = uv.rblk[e];
+        if (b.mode == 2) continue;
+        const int pend = b.mode == 0 ? gi + 1 : uv.n[b.J];
+        for (int p = g; p < pend; p += 4) {
+          const double2 v = K[b.koff + gi + (int64_t)p * nI];
+          s += sqrt(v.x * v.x + v.y * v.y);
+        }
+      }
+    }
+    part[g][i] = s;
+  }
+  // lanes over columns: wave w sums rows w, w + 8, ... of the row-read blocks
+  for (int i = w; i < t.sz; i += 8) {
     const int gi = t.r0 + i;
     double s = 0;
     for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
       const RBlkDev b = uv.rblk[e];
-      const int nJ = uv.n[b.J];
-      for (int p = lane; p < nJ; p += 64) {
-        double2 v;
-        if (b.mode == 0) v = (gi >= p) ? K[b.koff + gi + (int64_t)p * nI] : K[b.koff + p + (int64_t)gi * nI];
-        else if (b.mode == 1) v = K[b.koff + gi + (int64_t)p * nI];
-        else v = K[b.koff + p + (int64_t)gi * nJ];
-        s += sqrt(v.x * v.x + v.y * v.y);
+      if (b.mode == 1) continue;
+      if (b.mode == 2) {
+        const int nJ = uv.n[b.J];
+        for (int p = lane; p < nJ; p += 64) {
+          const double2 v = K[b.koff + p + (int64_t)gi * nJ];
+          s += sqrt(v.x * v.x + v.y * v.y);
+        }
+      } else {
+        for (int p = gi + 1 + lane; p < nI; p += 64) {  // (gi, p) above the diagonal = (p, gi)
+          const double2 v = K[b.koff + p + (int64_t)gi * nI];
+          s += sqrt(v.x * v.x + v.y * v.y);
+        }
       }
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) rowsum[i] = s;
+    if (lane == 0) part[4][i] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0;
-    for (int i = 0; i < t.sz; ++i) m = fmax(m, rowsum[i]);
-    atomic_max_pos(&ctrl->knorm, m);
+  __shared__ double rmax[8];
+  double m = 0;
+  if (tid < t.sz) m = (((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid])) + part[4][tid]);
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  if (lane == 0) rmax[w] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double r = 0;
+    for (int q = 0; q < 8; ++q) r = fmax(r, rmax[q]);
+    atomic_max_pos(&ctrl->knorm, r);
   }
 }
 
 hipError_t launch_knorm(const void* K, const UserView& uv, const RTaskDev* rt, int nrt, IrCtrl* ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_knorm, dim3(nrt), dim3(256), 0, s, (const double2*)K, uv, rt, ctrl);
+  hipLaunchKernelGGL(k_knorm, dim3(nrt), dim3(512), 0, s, (const double2*)K, uv, rt, ctrl);
   return hipGetLastError();
 }
 

@@ -554,6 +554,7 @@ d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
   }
   out->ir_iters = c.iters;
   out->fallbacks = st[2];
+  out->knorm = c.knorm;
   out->eta = -1;
   for (int k = 0; k < 32; ++k) {
     out->eta_hist[k] = c.eta_hist[k];

@@ -131,6 +131,20 @@ def test_host_sync_refinement_matches_device_flag():
     assert np.array_equal(X1, X2)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_knorm_matches_oracle(precision):
+    # ||K||_inf from the device (row tiles of 128 and ragged ones, all three
+    # block modes) against the oracle's full symmetric row sums
+    inst = gen.make_instance((3, 2, 2), (60, 300), gen.COEF_PRECISION, 1, 606)
+    d3m = _d3m()
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid)
+    f = d3m.Factor(plan, precision, nrhs_max=1)
+    f.factorize(torch.from_numpy(inst.K).cuda())
+    st = f.status()
+    ref = oracle.k_norm_inf(inst.sizes, inst.pairs, inst.K)
+    assert abs(st["knorm"] - ref) <= 1e-13 * ref, (st["knorm"], ref)
+
+
 def test_determinism_bitwise():
     inst = gen.make_instance((3, 3, 2), (40, 150), gen.COEF_PLAIN, 3, 404)
     d3m = _d3m()
