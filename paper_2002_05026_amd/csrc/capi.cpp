@@ -27,7 +27,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Workspace layout of one factor.
 struct Layout {
   size_t L, LD, D, Linv, W, Z, X64, R64, P64, norms, ctrl, status, growth, counters, flags;
-  size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, iv;
+  size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, xsrc, iv;
   size_t kp, fills, rt, rptr, rblk, rsplit, nI, row0, prow0, perm, dkt;
   size_t total;
 };
@@ -129,6 +129,7 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.panels = take(p.panels.size() * sizeof(Panel));
   l.pblocks = take(p.pblocks.size() * sizeof(PBlock));
   l.tiles = take(p.tiles.size() * sizeof(Tile));
+  l.xsrc = take(p.xsrc.size() * sizeof(XSrc));
   l.iv = take(sizeof(InstView));
   l.kp = take(t.kp.size() * sizeof(KPlaceDev));
   l.fills = take(t.fills.size() * sizeof(KPlaceDev));
@@ -394,6 +395,7 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
   iv.panels = f->at<Panel>(f->lay.panels);
   iv.pblocks = f->at<PBlock>(f->lay.pblocks);
   iv.tiles = f->at<Tile>(f->lay.tiles);
+  iv.xsrc = f->at<XSrc>(f->lay.xsrc);
   iv.status = f->at<int32_t>(f->lay.status);
   iv.growth = f->at<float>(f->lay.growth);
   iv.nrhs = nrhs_max;
@@ -411,6 +413,7 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
             up(f->lay.panels, p.panels.data(), p.panels.size() * sizeof(Panel)) &&
             up(f->lay.pblocks, p.pblocks.data(), p.pblocks.size() * sizeof(PBlock)) &&
             up(f->lay.tiles, p.tiles.data(), p.tiles.size() * sizeof(Tile)) &&
+            up(f->lay.xsrc, p.xsrc.data(), p.xsrc.size() * sizeof(XSrc)) &&
             up(f->lay.iv, &iv, sizeof(iv)) &&
             up(f->lay.kp, f->tab.kp.data(), f->tab.kp.size() * sizeof(KPlaceDev)) &&
             up(f->lay.fills, f->tab.fills.data(), f->tab.fills.size() * sizeof(KPlaceDev)) &&

@@ -28,6 +28,16 @@ enum TaskKind : int32_t {
 // it, N rows each), which a TK_RED task adds into b before the tile is used.
 constexpr int kSolveSlots = 3;
 
+// One source of a merged update task: A = LD + a_off (lda), B = L + b_off
+// (lda), inner length k.
+struct XSrc {
+  int64_t a_off, b_off;
+  int32_t k, lda;
+};
+
+// Sources of one merged update task at most.
+constexpr int kMergeSrc = 4;
+
 // One task, in ticket order.  Offsets are in complex elements, relative to
 // the instance's base pointers (panel storage L, solve vector W).
 struct Task {
@@ -85,6 +95,7 @@ struct InstView {
   const Panel* panels;
   const PBlock* pblocks;
   const Tile* tiles;
+  const XSrc* xsrc;  // sources of merged update tasks
   int32_t* status;   // [0] first bad pivot (internal row, INT_MAX if none), [1] count, [2] FP64 re-factors
   float* growth;     // per panel: [2*I] min |d|, [2*I+1] max |L|
   int32_t nrhs;

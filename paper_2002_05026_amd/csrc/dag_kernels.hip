@@ -99,12 +99,19 @@ __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
   gemm_store<T>(acc, t.m, t.n, o);
 }
 
-// C -= (L D) L^T on one tile pair (TK_XUPD)
+// C -= sum over the task's sources of (L_rI D_I) L_sI^T on one tile pair
+// (TK_XUPD); t.pad0 > 1: the sources are xsrc[t.pad1 ...], else the task's
+// own operands
 template <typename T>
 __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.LD + t.a_off, t.lda), nullptr, opn<T>(cx.L + t.b_off, t.lda), cx.lds);
+  const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
+  for (int q = 0; q < nsrc; ++q) {
+    XSrc x{t.a_off, t.b_off, t.k, t.lda};
+    if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
+    gemm_acc<T>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr, opn<T>(cx.L + x.b_off, x.lda), cx.lds);
+  }
   gemm_store<T>(acc, t.m, t.n, outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1));
 }
 

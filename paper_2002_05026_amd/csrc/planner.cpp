@@ -419,9 +419,46 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   const int64_t kDKey = 1LL << 61;
   auto inv_key = [](int64_t a, int64_t b) { return (1LL << 59) | (a << 20) | b; };
   const bool want_acc = true;
+  // Updates of one target tile from consecutive source panels are merged
+  // into one XUPD task (up to kMergeSrc sources, run one after the other
+  // into one accumulator), so the target is read and written once per group
+  // and the fixed cost of a task is paid once.  A group waits in pend until
+  // it is full or its target panel comes up for elimination.
+  struct PendUpd {
+    Task t;
+    std::vector<int32_t> pr;
+    std::vector<Access> ac;
+    std::vector<XSrc> src;
+    double w;
+  };
+  std::unordered_map<int64_t, PendUpd> pend;
+  std::vector<std::vector<int64_t>> pend_of(nb);  // target panel -> keys possibly pending
+  auto emit_upd = [&](int64_t tk, PendUpd& pu) {
+    Task t = pu.t;
+    if (pu.src.size() > 1) {
+      t.pad0 = (int32_t)pu.src.size();
+      t.pad1 = (int32_t)p.xsrc.size();
+      t.k = 0;
+      for (auto& x : pu.src) {
+        p.xsrc.push_back(x);
+        t.k += x.k;
+      }
+    }
+    int id = g.add(t, pu.pr, pu.w);
+    lastw[tk] = id;
+    if (want_acc) facc.push_back(pu.ac);
+  };
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
     const int nI = P.n;
+    // updates still waiting for more sources whose target is this panel
+    for (int64_t tk : pend_of[I]) {
+      auto it = pend.find(tk);
+      if (it == pend.end()) continue;
+      emit_upd(tk, it->second);
+      pend.erase(it);
+    }
+    pend_of[I].clear();
     // row tiles of the panel: (global tile index, row offset in panel)
     std::vector<std::pair<int, int>> rows;
     for (int b = 0; b < P.npb; ++b) {
@@ -564,17 +601,30 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
             t.b_off = P.off + BK.prow + TS.r0;
             t.c_off = PK.off + rowJinK + TR.r0 + (int64_t)TS.r0 * PK.H;
             int64_t tk = key3(BK.J, PJ.tile0 + r, s2);
-            std::vector<int32_t> pr{trsm_last[ri], trsm_last[si], lw(tk)};
-            int id = g.add(t, pr, w_gemm(TR.sz, TS.sz, nI));
-            lastw[tk] = id;
-            if (want_acc) {
-              std::vector<Access> ac{{tk, true}};
+            auto it = pend.find(tk);
+            if (it == pend.end()) {
+              PendUpd pu;
+              pu.t = t;
+              pu.pr = {lw(tk)};
+              pu.ac = {{tk, true}};
+              pu.w = 22.0;
+              it = pend.emplace(tk, std::move(pu)).first;
+              pend_of[BK.J].push_back(tk);
+            }
+            PendUpd& pu = it->second;
+            pu.pr.push_back(trsm_last[ri]);
+            pu.pr.push_back(trsm_last[si]);
+            pu.src.push_back({t.a_off, t.b_off, nI, P.H});
+            pu.w += tile_work(TR.sz, TS.sz, nI) / 5.5e5 + (pu.src.size() > 1 ? 3.0 : 0.0);
+            if (want_acc)
               for (int c = 0; c < P.nt; ++c) {
-                ac.push_back({key3(I, PJ.tile0 + r, c), false});
-                ac.push_back({key3(I, PK.tile0 + s2, c), false});
-                ac.push_back({kDKey | (P.tile0 + c), false});
+                pu.ac.push_back({key3(I, PJ.tile0 + r, c), false});
+                pu.ac.push_back({key3(I, PK.tile0 + s2, c), false});
+                pu.ac.push_back({kDKey | (P.tile0 + c), false});
               }
-              facc.push_back(ac);
+            if ((int)pu.src.size() >= kMergeSrc) {
+              emit_upd(tk, pu);
+              pend.erase(it);
             }
           }
       }

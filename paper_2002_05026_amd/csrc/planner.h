@@ -55,6 +55,8 @@ struct PlanImpl {
   // residual row blocks: for each interface (user id), the K blocks of its block row
   struct RBlk { int64_t koff; int32_t J; int32_t mode; };  // mode 0 diag(sym), 1 K_IJ, 2 K_JI^T
   std::vector<std::vector<RBlk>> rrow;
+  // extra operand pairs of merged update tasks (Task.pad1 = first, pad0 = count)
+  std::vector<XSrc> xsrc;
   // DAGs
   TaskDag fdag, sdag;
   std::vector<std::vector<Access>> facc, sacc;  // per generation index (small plans only)
