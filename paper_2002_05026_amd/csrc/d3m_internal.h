@@ -35,8 +35,9 @@ struct XSrc {
   int32_t k, lda;
 };
 
-// Sources of one merged update task at most.
-constexpr int kMergeSrc = 4;
+// Sources of one merged update task at most (factor, forward solve).
+constexpr int kMergeSrc = 8;
+constexpr int kMergeSolve = 1;
 
 // One task, in ticket order.  Offsets are in complex elements, relative to
 // the instance's base pointers (panel storage L, solve vector W).

@@ -150,16 +150,22 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx, const Task& t) {
   gemm_store<T>(acc, t.m, nr, o);
 }
 
-// forward update: b_r -= (L_rI D_I) z_I
+// forward update: b_r -= sum over the task's sources of (L_rI D_I) z_I
+// (t.pad0 > 1: the sources are xsrc[t.pad1 ...], else the task's own
+// operands); t.n = 1: the target is an extra accumulator written first
 template <typename T>
 __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.LD + t.a_off, t.lda), nullptr, opn<T>(cx.Z + t.b_off * nr, nr), cx.lds);
-  // the first update into an extra accumulator overwrites it (two stores with
-  // a constant beta each, so neither has a per-element branch)
-  if (t.pad0) gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)0));
+  const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
+  for (int q = 0; q < nsrc; ++q) {
+    XSrc x{t.a_off, t.b_off, t.k, t.lda};
+    if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
+    gemm_acc<T>(acc, t.m, nr, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr, opn<T>(cx.Z + x.b_off * nr, nr), cx.lds);
+  }
+  // two stores with a constant beta each, so neither has a per-element branch
+  if (t.n) gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)0));
   else gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
 

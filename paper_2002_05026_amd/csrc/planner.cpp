@@ -663,12 +663,49 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   std::vector<std::vector<int>> ftile(nb), btile(nb);
   const int64_t kWKey = 1LL << 60, kZKey = 1LL << 58;
   auto wkey = [&](int slot, int r) { return kWKey | ((int64_t)slot << 40) | r; };
-  // forward updates into tile r: count so far, and the last one per extra slot
+  // forward updates into tile r: groups of up to kMergeSolve consecutive
+  // sources form one task; groups go round-robin to b and its extra
+  // accumulators (count of groups so far, last task per extra slot)
   std::vector<int> nupd(stl.size(), 0);
   std::vector<std::array<int, kSolveSlots + 1>> lastx(stl.size());
   for (auto& a : lastx) a.fill(-1);
+  struct PendF {
+    Task t;
+    std::vector<int32_t> pr;
+    std::vector<Access> ac;
+    std::vector<XSrc> src;
+    double w = 22.0;
+  };
+  std::vector<PendF> pendf(stl.size());
+  auto emit_fupd = [&](int r) {
+    PendF& pf = pendf[r];
+    if (pf.src.empty()) return;
+    const int slot = nupd[r]++ % (kSolveSlots + 1);
+    Task u = pf.t;
+    u.c_off += (int64_t)slot * p.N;                     // rows of b_r (or a copy) in W
+    u.n = (slot > 0 && lastx[r][slot] < 0) ? 1 : 0;     // first into a copy: overwrite
+    if (pf.src.size() > 1) {
+      u.pad0 = (int32_t)pf.src.size();
+      u.pad1 = (int32_t)p.xsrc.size();
+      u.k = 0;
+      for (auto& x : pf.src) {
+        p.xsrc.push_back(x);
+        u.k += x.k;
+      }
+    }
+    std::vector<int32_t> pr = pf.pr;
+    pr.push_back(slot == 0 ? lastb[r] : lastx[r][slot]);
+    std::vector<Access> ac = pf.ac;
+    ac[0] = {wkey(slot, r), true};
+    int uid = sg.add(u, pr, pf.w);
+    if (slot == 0) lastb[r] = uid;
+    else lastx[r][slot] = uid;
+    sacc.push_back(ac);
+    pf = PendF();
+  };
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
+    for (int c = st0[I]; c < st0[I + 1]; ++c) emit_fupd(c);
     // sum the extra accumulators of I's tiles into b_I
     for (int c = st0[I]; c < st0[I + 1]; ++c) {
       const int used = std::min(nupd[c], kSolveSlots + 1) - 1;
@@ -716,28 +753,26 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       const Panel& PJ = p.panels[B.J];
       for (int r = st0[B.J]; r < st0[B.J + 1]; ++r) {
         const int r0 = stl[r].first, sz = stl[r].second;
-        // slot of this update: b itself (0) or an extra accumulator
-        const int slot = nupd[r]++ % (kSolveSlots + 1);
-        Task u{};
-        u.kind = TK_FUPD;
-        u.panel = I;
-        u.m = sz;
-        u.k = P.n;
-        u.lda = P.H;
-        u.dofs = P.prow0;
-        u.aux = r;
-        u.a_off = P.off + B.prow + r0;
-        u.b_off = P.prow0;                                // rows of z_I in Z
-        u.c_off = slot * p.N + PJ.prow0 + r0;             // rows of b_r (or a copy) in W
-        u.pad0 = (slot > 0 && lastx[r][slot] < 0) ? 1 : 0;  // first into a copy: overwrite
-        std::vector<int32_t> pr2(ftile[I]);
-        pr2.push_back(slot == 0 ? lastb[r] : lastx[r][slot]);
-        std::vector<Access> ac2{{wkey(slot, r), true}};
-        for (int c = st0[I]; c < st0[I + 1]; ++c) ac2.push_back({kZKey | c, false});
-        int uid = sg.add(u, pr2, w_solve(sz, P.n));
-        if (slot == 0) lastb[r] = uid;
-        else lastx[r][slot] = uid;
-        sacc.push_back(ac2);
+        PendF& pf = pendf[r];
+        if (pf.src.empty()) {
+          Task u{};
+          u.kind = TK_FUPD;
+          u.panel = I;
+          u.m = sz;
+          u.k = P.n;
+          u.lda = P.H;
+          u.aux = r;
+          u.a_off = P.off + B.prow + r0;                  // rows of (L D)_rI in LD
+          u.b_off = P.prow0;                              // rows of z_I in Z
+          u.c_off = PJ.prow0 + r0;
+          pf.t = u;
+          pf.ac.push_back({0, true});  // the target, set when the slot is known
+        }
+        pf.pr.insert(pf.pr.end(), ftile[I].begin(), ftile[I].end());
+        for (int c = st0[I]; c < st0[I + 1]; ++c) pf.ac.push_back({kZKey | c, false});
+        pf.src.push_back({P.off + B.prow + r0, P.prow0, P.n, P.H});
+        pf.w += tile_work(sz, 64, P.n) / 5.5e5 + (pf.src.size() > 1 ? 3.0 : 0.0);
+        if ((int)pf.src.size() >= kMergeSolve) emit_fupd(r);
       }
     }
   }
