@@ -478,10 +478,10 @@ __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const doubl
   A.ld = B.ld = ld;
   A.p = Lam + ri;
   B.p = X + rj;
-  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
+  gemm_acc<double, 8, GeKB<double>::KB, OP_N>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
   A.p = X + ri;
   B.p = Lam + rj;
-  gemm_acc<double>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
+  gemm_acc<double, 8, GeKB<double>::KB, OP_N>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
   Out<double> o;
   const int nI = uv.n[t.I];
   o.dst = dK + t.koff + t.r0 + (int64_t)t.c0 * nI;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type*
     A.i0 = 0;
     B = A;
     B.p = base + 128 * 512;
-    gemm_acc<T>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
     Out<T> o;
     o.dst = base + 2 * 128 * 512;
     o.rs = 1;

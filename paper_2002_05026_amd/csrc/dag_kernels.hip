@@ -92,7 +92,8 @@ template <typename T>
 __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr, opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
+                                      opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
   Out<T> o = outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0);
   o.dst2 = cx.LD + t.a_off;
   o.coldiv = cx.D + t.dofs;
@@ -110,7 +111,8 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
   for (int q = 0; q < nsrc; ++q) {
     XSrc x{t.a_off, t.b_off, t.k, t.lda};
     if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
-    gemm_acc<T>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr, opn<T>(cx.L + x.b_off, x.lda), cx.lds);
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
+                                        opn<T>(cx.L + x.b_off, x.lda), cx.lds);
   }
   gemm_store<T>(acc, t.m, t.n, outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1));
 }
@@ -127,12 +129,14 @@ __device__ __noinline__ void task_inv(const Ctx<T>& cx, const Task& t) {
   const int n = P.n;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, tc.sz, tr.sz, tr.r0 - tc.r0, opn<T>(Lb + tc.r0 + (int64_t)tc.r0 * n, n, OP_T), nullptr,
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, tc.sz, tr.sz, tr.r0 - tc.r0, opn<T>(Lb + tc.r0 + (int64_t)tc.r0 * n, n, OP_T),
+                                    nullptr,
               opn<T>(cx.L + P.off + tr.r0 + (int64_t)tc.r0 * P.H, P.H), cx.lds);
   C* stage = Lb + tc.r0 + (int64_t)tr.r0 * n;
   gemm_store<T>(acc, tc.sz, tr.sz, outp<T>(stage, 1, n, (T)1, (T)0));
   acc.zero();
-  gemm_acc<T>(acc, tr.sz, tc.sz, tr.sz, opn<T>(Lb + tr.r0 + (int64_t)tr.r0 * n, n), nullptr, opn<T>(stage, n),
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, tr.sz, tc.sz, tr.sz, opn<T>(Lb + tr.r0 + (int64_t)tr.r0 * n, n), nullptr,
+                                    opn<T>(stage, n),
               cx.lds);
   gemm_store<T>(acc, tr.sz, tc.sz, outp<T>(Lb + tr.r0 + (int64_t)tc.r0 * n, 1, n, (T)-1, (T)0));
 }
@@ -143,7 +147,8 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda), nullptr, opn<T>(cx.W + t.b_off * nr, nr),
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda), nullptr,
+                                    opn<T>(cx.W + t.b_off * nr, nr),
               cx.lds);
   Out<T> o = outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)1, (T)0);
   o.rowdiv = cx.D + t.dofs;
@@ -162,7 +167,8 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   for (int q = 0; q < nsrc; ++q) {
     XSrc x{t.a_off, t.b_off, t.k, t.lda};
     if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
-    gemm_acc<T>(acc, t.m, nr, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr, opn<T>(cx.Z + x.b_off * nr, nr), cx.lds);
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, nr, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
+                                      opn<T>(cx.Z + x.b_off * nr, nr), cx.lds);
   }
   // two stores with a constant beta each, so neither has a per-element branch
   if (t.n) gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)0));
@@ -192,7 +198,8 @@ __device__ __noinline__ void task_bupd(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T), nullptr, opn<T>(cx.W + t.b_off * nr, nr),
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, t.m, nr, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T), nullptr,
+                                    opn<T>(cx.W + t.b_off * nr, nr),
               cx.lds);
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
@@ -203,7 +210,8 @@ __device__ __noinline__ void task_btile(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda, OP_T), nullptr, opn<T>(cx.Z + t.b_off * nr, nr),
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda, OP_T), nullptr,
+                                    opn<T>(cx.Z + t.b_off * nr, nr),
               cx.lds);
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)1, (T)0));
 }

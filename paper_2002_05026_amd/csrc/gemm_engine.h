@@ -167,11 +167,13 @@ template <typename T, int KB = GeKB<T>::KB> constexpr int ge_lds_bytes() {
 }
 constexpr int ge_log2(int v) { return v <= 1 ? 0 : 1 + ge_log2(v / 2); }
 
-// Address of A(i, p) for the operand mode (i, p inside the operand).
-template <typename T>
+// Address of A(i, p) for the operand mode (i, p inside the operand); AM >= 0
+// fixes the mode at compile time, AM < 0 takes A.mode.
+template <int AM, typename T>
 __device__ __forceinline__ const typename Cplx<T>::type* op_addr(const Opnd<T>& A, int i, int p) {
-  if (A.mode == OP_N) return A.p + i + (int64_t)p * A.ld;
-  if (A.mode == OP_T) return A.p + (int64_t)i * A.ld + p;
+  const int mode = AM >= 0 ? AM : A.mode;
+  if (mode == OP_N) return A.p + i + (int64_t)p * A.ld;
+  if (mode == OP_T) return A.p + (int64_t)i * A.ld + p;
   const int gi = A.i0 + i;
   return (gi >= p) ? A.p + gi + (int64_t)p * A.ld : A.p + p + (int64_t)gi * A.ld;
 }
@@ -188,23 +190,24 @@ template <typename T, int KB = GeKB<T>::KB> struct Slab {
   uint32_t amask, bmask;
 };
 
-template <typename T, int KB>
+template <typename T, int KB, int AM>
 __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, const typename Cplx<T>::type* dA,
                                          const Opnd<T>& B, int m, int n, int k, int p0) {
   typedef typename Cplx<T>::type C;
   const int tid = threadIdx.x;
   constexpr int NE = Slab<T, KB>::NE, LOG = ge_log2(KB);
+  const int amode = AM >= 0 ? AM : A.mode;
   sl.amask = 0;
   sl.bmask = 0;
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = tid + GE_THREADS * q;
     int i, pp;
-    if (A.mode == OP_T) { pp = e & (KB - 1); i = e >> LOG; }
+    if (amode == OP_T) { pp = e & (KB - 1); i = e >> LOG; }
     else { i = e & (GE_TM - 1); pp = e >> 7; }
     const int p = p0 + pp;
     const bool ok = (i < m) & (p < k);
-    const C* src = ok ? op_addr(A, i, p) : A.p;
+    const C* src = ok ? op_addr<AM>(A, i, p) : A.p;
     sl.a[q] = *gptr<T>(src);
     if (dA) sl.d[q] = *gptr<T>(dA + (ok ? p : 0));
     sl.amask |= (ok ? 1u : 0u) << q;
@@ -220,11 +223,12 @@ __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, cons
   }
 }
 
-template <typename T, int KB>
-__device__ __forceinline__ void ge_stash(const Slab<T, KB>& sl, int amode, bool scaled, D3M_LDS cpx<T>* As,
+template <typename T, int KB, int AM>
+__device__ __forceinline__ void ge_stash(const Slab<T, KB>& sl, int amode_rt, bool scaled, D3M_LDS cpx<T>* As,
                                          D3M_LDS cpx<T>* Bs) {
   const int tid = threadIdx.x;
   constexpr int NE = Slab<T, KB>::NE, LOG = ge_log2(KB);
+  const int amode = AM >= 0 ? AM : amode_rt;
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = tid + GE_THREADS * q;
@@ -299,7 +303,9 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
 // is known to be small pass it so that only the narrow accumulators stay live.
 // KB: complex columns per slab (lds holds ge_lds_bytes<T, KB>()); callers
 // with registers to spare take deeper slabs, which cover more load latency.
-template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB>
+// AM: A's mode fixed at compile time (OP_N or OP_T; -1: A.mode at run time),
+// which keeps the per-element address and layout choice out of the slab code.
+template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1>
 __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
@@ -315,9 +321,9 @@ __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const
   // slab s lives in buffer s & 1: while slab s is multiplied, slab s+1 is
   // written to the other buffer and slab s+2 is loaded into registers; one
   // barrier per slab
-  ge_fetch<T, KB>(sl, A, dA, B, m, n, k, 0);
-  ge_stash<T, KB>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-  if (KB < k) ge_fetch<T, KB>(sl, A, dA, B, m, n, k, KB);
+  ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, 0);
+  ge_stash<T, KB, AM>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+  if (KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, KB);
   __syncthreads();
   int s = 0;
   for (int p0 = 0; p0 < k; p0 += KB, ++s) {
@@ -334,8 +340,8 @@ __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const
       else ge_mma<1>(acc, ap, bp, kend);
     }
     if (p0 + KB < k) {
-      ge_stash<T, KB>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
-      if (p0 + 2 * KB < k) ge_fetch<T, KB>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
+      ge_stash<T, KB, AM>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
+      if (p0 + 2 * KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
     }
     __syncthreads();
   }
