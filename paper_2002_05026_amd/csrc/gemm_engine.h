@@ -314,34 +314,42 @@ __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const
   const int lr = lane & 15, lk = lane >> 4;
   const bool rowok = 16 * w < m;
   const int nbj = (n + 15) >> 4;
-  Slab<T, KB> sl;
+  Slab<T, KB> sa, sb;  // two slabs in flight in registers
   const bool scaled = dA != nullptr;
   wg_sync_global();
   if (k <= 0 || m <= 0 || n <= 0) return;
-  // slab s lives in buffer s & 1: while slab s is multiplied, slab s+1 is
-  // written to the other buffer and slab s+2 is loaded into registers; one
-  // barrier per slab
-  ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, 0);
-  ge_stash<T, KB, AM>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-  if (KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, KB);
+  // slab s lives in LDS buffer s & 1; while slab s is multiplied, slab s+1
+  // is written to the other buffer and slab s+3 is loaded into the register
+  // slab that held s+1 (sb for even s, sa for odd s): each load has two
+  // slabs of products to arrive; one barrier per slab
+  auto mma = [&](const D3M_LDS cpx<T>* cur, int p0) {
+    if (!rowok) return;
+    const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
+    const D3M_LDS cpx<T>* bp = cur + KB * GE_LDP + lk * GE_LDP + lr;
+    // three widths only (more variants make the allocator copy the
+    // accumulator); LDS columns beyond n hold zeros
+    const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KB ? k - p0 : KB);
+    if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
+    else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
+    else ge_mma<1>(acc, ap, bp, kend);
+  };
+  ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 0);
+  if (KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, KB);
+  ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+  if (2 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 2 * KB);
   __syncthreads();
-  int s = 0;
-  for (int p0 = 0; p0 < k; p0 += KB, ++s) {
-    D3M_LDS cpx<T>* cur = (s & 1) ? buf1 : buf0;
-    D3M_LDS cpx<T>* nxt = (s & 1) ? buf0 : buf1;
-    if (rowok) {
-      const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
-      const D3M_LDS cpx<T>* bp = cur + KB * GE_LDP + lk * GE_LDP + lr;
-      // three widths only (more variants make the allocator copy the
-      // accumulator); LDS columns beyond n hold zeros
-      const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KB ? k - p0 : KB);
-      if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
-      else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
-      else ge_mma<1>(acc, ap, bp, kend);
-    }
+  for (int p0 = 0; p0 < k; p0 += 2 * KB) {
+    mma(buf0, p0);
     if (p0 + KB < k) {
-      ge_stash<T, KB, AM>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
-      if (p0 + 2 * KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
+      ge_stash<T, KB, AM>(sb, A.mode, scaled, buf1, buf1 + KB * GE_LDP);
+      if (p0 + 3 * KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, p0 + 3 * KB);
+    }
+    __syncthreads();
+    if (p0 + KB >= k) break;
+    mma(buf1, p0 + KB);
+    if (p0 + 2 * KB < k) {
+      ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+      if (p0 + 4 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, p0 + 4 * KB);
     }
     __syncthreads();
   }
