@@ -467,7 +467,7 @@ hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
 // dK(I,J) tile = -1/2 sum_k (lam_I x_J^T + x_I lam_J^T); user layout vectors.
 __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const double2* X, int64_t ld, int nrhs, double2* dK,
                                             UserView uv, const DkTaskDev* dt) {
-  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double>()];
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes_dma<double>()];
   const DkTaskDev t = dt[blockIdx.x];
   const int64_t ri = uv.row0[t.I] + t.r0, rj = uv.row0[t.J] + t.c0;
   Acc<double> acc;
@@ -478,10 +478,10 @@ __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const doubl
   A.ld = B.ld = ld;
   A.p = Lam + ri;
   B.p = X + rj;
-  gemm_acc<double, 8, GeKB<double>::KB, OP_N>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
+  gemm_acc<double, 8, GeKB<double>::KB, OP_N, true>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
   A.p = X + ri;
   B.p = Lam + rj;
-  gemm_acc<double, 8, GeKB<double>::KB, OP_N>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
+  gemm_acc<double, 8, GeKB<double>::KB, OP_N, true>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
   Out<double> o;
   const int nI = uv.n[t.I];
   o.dst = dK + t.koff + t.r0 + (int64_t)t.c0 * nI;
@@ -578,7 +578,7 @@ hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, c
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type* buf, int reps) {
   typedef typename Cplx<T>::type C;
-  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<T>()];
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes_dma<T>()];
   C* base = buf + (int64_t)blockIdx.x * (3 * 128 * 512);
   Acc<T> acc;
   for (int r = 0; r < reps; ++r) {
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type*
     A.i0 = 0;
     B = A;
     B.p = base + 128 * 512;
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
     Out<T> o;
     o.dst = base + 2 * 128 * 512;
     o.rs = 1;

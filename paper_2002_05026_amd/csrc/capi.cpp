@@ -104,7 +104,9 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   const size_t es = prec == 0 ? 16 : 8;
   Layout l;
   size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+  // 64 bytes of slack after every section: a paired complex64 load of an
+  // odd last row reads one element past its operand
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1) + 64); return at; };
   l.L = take(p.L_elems * es);
   l.LD = take(p.L_elems * es);
   l.D = take(p.N * es);
@@ -695,7 +697,9 @@ struct BatchLayout {
 BatchLayout batch_layout(const TaskDag& fd, const TaskDag& sd, int n) {
   BatchLayout l;
   size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+  // 64 bytes of slack after every section: a paired complex64 load of an
+  // odd last row reads one element past its operand
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1) + 64); return at; };
   l.ftasks = take(fd.tasks.size() * sizeof(Task));
   l.fsucc = take(fd.succ.size() * 4);
   l.fcnt = take(fd.npred.size() * 4);

@@ -92,7 +92,7 @@ template <typename T>
 __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
                                       opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
   Out<T> o = outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0);
   o.dst2 = cx.LD + t.a_off;
@@ -111,7 +111,7 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
   for (int q = 0; q < nsrc; ++q) {
     XSrc x{t.a_off, t.b_off, t.k, t.lda};
     if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
                                         opn<T>(cx.L + x.b_off, x.lda), cx.lds);
   }
   gemm_store<T>(acc, t.m, t.n, outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1));
@@ -135,7 +135,7 @@ __device__ __noinline__ void task_inv(const Ctx<T>& cx, const Task& t) {
   C* stage = Lb + tc.r0 + (int64_t)tr.r0 * n;
   gemm_store<T>(acc, tc.sz, tr.sz, outp<T>(stage, 1, n, (T)1, (T)0));
   acc.zero();
-  gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, tr.sz, tc.sz, tr.sz, opn<T>(Lb + tr.r0 + (int64_t)tr.r0 * n, n), nullptr,
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, tr.sz, tc.sz, tr.sz, opn<T>(Lb + tr.r0 + (int64_t)tr.r0 * n, n), nullptr,
                                     opn<T>(stage, n),
               cx.lds);
   gemm_store<T>(acc, tr.sz, tc.sz, outp<T>(Lb + tr.r0 + (int64_t)tc.r0 * n, 1, n, (T)-1, (T)0));
@@ -147,7 +147,7 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda), nullptr,
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda), nullptr,
                                     opn<T>(cx.W + t.b_off * nr, nr),
               cx.lds);
   Out<T> o = outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)1, (T)0);
@@ -167,7 +167,7 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   for (int q = 0; q < nsrc; ++q) {
     XSrc x{t.a_off, t.b_off, t.k, t.lda};
     if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N>(acc, t.m, nr, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, nr, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
                                       opn<T>(cx.Z + x.b_off * nr, nr), cx.lds);
   }
   // two stores with a constant beta each, so neither has a per-element branch
@@ -245,7 +245,8 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
 
 // the complex64 kernel also holds the FP64 re-factor of a tile
 template <typename T> constexpr int dag_lds_bytes() {
-  return tile_ldlt_lds_bytes<double>() > ge_lds_bytes<T>() ? tile_ldlt_lds_bytes<double>() : ge_lds_bytes<T>();
+  constexpr int a = tile_ldlt_lds_bytes<double>(), b = ge_lds_bytes_dma<T>();
+  return a > b ? a : b;
 }
 
 // ---------------------------------------------------------------- the executor

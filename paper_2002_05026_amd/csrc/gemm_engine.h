@@ -297,6 +297,72 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
   }
 }
 
+// ---------------------------------------------------------------- direct loads
+// LDS bytes of the direct-load path: three slab buffers.
+template <typename T, int KB = GeKB<T>::KB> constexpr int ge_lds_bytes_dma() {
+  return 3 * 2 * KB * GE_LDP * (int)sizeof(cpx<T>);
+}
+// Global->LDS load instructions each wave issues per slab (A and B).
+template <typename T, int KB> constexpr int ge_dma_per_wave() {
+  return 2 * KB * (GE_TM / (64 * (16 / (int)sizeof(cpx<T>)))) / 8;
+}
+
+// Wait until at most N vector-memory operations of this wave are in flight
+// and its LDS writes are done (gfx9 s_waitcnt encoding: vmcnt in bits 3:0
+// and 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8 = 0).
+template <int N> __device__ __forceinline__ void ge_wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// One slab (A and B, both OP_N, KB columns from p0) straight from global
+// memory into LDS buffer buf, in the slab layout (column p of A at p*LDP,
+// of B at (KB + p)*LDP): each wave instruction moves 16 bytes per lane, a
+// whole 128-row column for complex64 (two rows per lane) or 64 rows for
+// complex128.  Columns at or beyond k are zero-filled instead, so the last
+// k-step adds nothing from them.  Rows beyond m (n) read row 0 of the
+// operand, or for complex64 the element after an odd last row (inside the
+// operand's allocation): they only reach output rows (columns) beyond the
+// tile, which are never stored.
+template <typename T, int KB>
+__device__ __forceinline__ void ge_dma(const Opnd<T>& A, const Opnd<T>& B, int m, int n, int k, int p0,
+                                       D3M_LDS cpx<T>* buf) {
+  constexpr int RPL = 16 / (int)sizeof(cpx<T>);    // rows per lane
+  constexpr int NCI = GE_TM / (64 * RPL);           // instructions per column
+  constexpr int NW = ge_dma_per_wave<T, KB>();
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const int g = w + 8 * q;  // instruction index: operand, column, part of the column
+    const int op = g / (KB * NCI);
+    const int rem = g - op * KB * NCI;
+    const int p = rem / NCI, h = rem - p * NCI;
+    const typename Cplx<T>::type* xp = op ? B.p : A.p;
+    const int64_t ld = op ? B.ld : A.ld;
+    const int rows = op ? n : m;
+    D3M_LDS cpx<T>* dst = buf + (op * KB + p) * GE_LDP + h * 64 * RPL;
+    if (p0 + p < k) {
+      int r = h * 64 * RPL + lane * RPL;
+      if (r >= rows) r = 0;
+      __builtin_amdgcn_global_load_lds((const void*)(xp + r + (int64_t)(p0 + p) * ld), (D3M_LDS void*)dst, 16, 0, 0);
+    } else {
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) dst[lane * RPL + e] = cpx<T>{0, 0};
+    }
+  }
+}
+
+// Whether gemm_acc may load A and B directly into LDS: complex64, both
+// OP_N, no D scaling, 16-byte aligned columns (even leading dimensions and
+// even base offsets).  complex128 keeps the register path: its register
+// loads already move 16 bytes per lane, and measured the same or faster.
+template <typename T>
+__device__ __forceinline__ bool ge_dma_ok(const Opnd<T>& A, const typename Cplx<T>::type* dA, const Opnd<T>& B) {
+  if (dA != nullptr || sizeof(cpx<T>) != 8) return false;
+  return (((uintptr_t)A.p | (uintptr_t)B.p) & 15) == 0 && ((A.ld | B.ld) & 1) == 0;
+}
+
 // acc += A * diag(dA) * B^T over k columns.  Starts and ends with a barrier,
 // so callers may overwrite the operands (or LDS) right after it returns.
 // NBMAX (8, 4 or 1) bounds n by 16 * NBMAX at compile time; callers whose n
@@ -305,7 +371,9 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
 // with registers to spare take deeper slabs, which cover more load latency.
 // AM: A's mode fixed at compile time (OP_N or OP_T; -1: A.mode at run time),
 // which keeps the per-element address and layout choice out of the slab code.
-template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1>
+// DMA: the caller's lds holds ge_lds_bytes_dma<T, KB>() and A is OP_N (AM),
+// so that aligned operands may take the direct-load path.
+template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false>
 __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
@@ -314,6 +382,47 @@ __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const
   const int lr = lane & 15, lk = lane >> 4;
   const bool rowok = 16 * w < m;
   const int nbj = (n + 15) >> 4;
+  auto mma = [&](const D3M_LDS cpx<T>* cur, int p0) {
+    if (!rowok) return;
+    const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
+    const D3M_LDS cpx<T>* bp = cur + KB * GE_LDP + lk * GE_LDP + lr;
+    // three widths only (more variants make the allocator copy the
+    // accumulator); LDS columns beyond n hold zeros or columns of B that
+    // only reach discarded outputs
+    const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KB ? k - p0 : KB);
+    if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
+    else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
+    else ge_mma<1>(acc, ap, bp, kend);
+  };
+  if constexpr (DMA && AM == OP_N) {
+    if (ge_dma_ok<T>(A, dA, B)) {
+      // three LDS buffers: slab s is multiplied from buffer s % 3 while slab
+      // s + 2 loads into buffer (s + 2) % 3; before the barrier that ends
+      // step s each wave waits for its own loads of slab s + 1
+      constexpr int SL = 2 * KB * GE_LDP, NW = ge_dma_per_wave<T, KB>();
+      wg_sync_global();
+      if (k <= 0 || m <= 0 || n <= 0) return;
+      ge_dma<T, KB>(A, B, m, n, k, 0, buf0);
+      if (KB < k) {
+        ge_dma<T, KB>(A, B, m, n, k, KB, buf0 + SL);
+        ge_wait_vm<NW>();
+      } else {
+        ge_wait_vm<0>();
+      }
+      __syncthreads();
+      int s = 0;
+      for (int p0 = 0; p0 < k; p0 += KB, ++s) {
+        const int b = s % 3, b2 = (s + 2) % 3;
+        const bool more = p0 + 2 * KB < k;
+        if (more) ge_dma<T, KB>(A, B, m, n, k, p0 + 2 * KB, buf0 + b2 * SL);
+        mma(buf0 + b * SL, p0);
+        if (more) ge_wait_vm<NW>();
+        else ge_wait_vm<0>();
+        __syncthreads();
+      }
+      return;
+    }
+  }
   Slab<T, KB> sa, sb;  // two slabs in flight in registers
   const bool scaled = dA != nullptr;
   wg_sync_global();
@@ -322,17 +431,6 @@ __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const
   // is written to the other buffer and slab s+3 is loaded into the register
   // slab that held s+1 (sb for even s, sa for odd s): each load has two
   // slabs of products to arrive; one barrier per slab
-  auto mma = [&](const D3M_LDS cpx<T>* cur, int p0) {
-    if (!rowok) return;
-    const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
-    const D3M_LDS cpx<T>* bp = cur + KB * GE_LDP + lk * GE_LDP + lr;
-    // three widths only (more variants make the allocator copy the
-    // accumulator); LDS columns beyond n hold zeros
-    const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KB ? k - p0 : KB);
-    if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
-    else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
-    else ge_mma<1>(acc, ap, bp, kend);
-  };
   ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 0);
   if (KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, KB);
   ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);

@@ -336,7 +336,10 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       b.prow0 = 0;  // filled below once all prow0 are known
       prow_in[I][J] = h;
       p.pblocks.push_back(b);
-      h += b.n;
+      // blocks start at even rows and the panel height is even, so every
+      // tile column of L and LD starts 16-byte aligned in complex64 (the
+      // engine's direct LDS loads need it); an odd block leaves one unused row
+      h += b.n + (b.n & 1);
     }
     P.npb = (int32_t)rowlist.size();
     P.H = h;
@@ -651,7 +654,8 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       const Tile& T = p.tiles[P.tile0 + c];
       const int nt = (T.sz + kSolveTile - 1) / kSolveTile;
       for (int q = 0; q < nt; ++q) {
-        const int r0 = T.sz * q / nt, r1 = T.sz * (q + 1) / nt;
+        // even starts (16-byte aligned operand columns, as for the factor tiles)
+        const int r0 = (T.sz * q / nt) & ~1, r1 = q + 1 == nt ? T.sz : (T.sz * (q + 1) / nt) & ~1;
         stl.push_back({T.r0 + r0, r1 - r0});
       }
     }
