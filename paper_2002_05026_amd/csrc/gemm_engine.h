@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace d3m {
 
 template <typename T> struct Cplx;
@@ -298,9 +300,14 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
 }
 
 // ---------------------------------------------------------------- direct loads
-// LDS bytes of the direct-load path: three slab buffers.
-template <typename T, int KB = GeKB<T>::KB> constexpr int ge_lds_bytes_dma() {
-  return 3 * 2 * KB * GE_LDP * (int)sizeof(cpx<T>);
+// Slab depth and LDS buffers of the direct-load path (no slab registers, so
+// the depth is bounded by LDS only).
+template <typename T> struct GeDma;
+template <> struct GeDma<float> { static constexpr int KB = 16, NBUF = 3; };
+template <> struct GeDma<double> { static constexpr int KB = 8, NBUF = 2; };  // path not taken
+// LDS bytes of the direct-load path.
+template <typename T> constexpr int ge_lds_bytes_dma() {
+  return GeDma<T>::NBUF * 2 * GeDma<T>::KB * GE_LDP * (int)sizeof(cpx<T>);
 }
 // Global->LDS load instructions each wave issues per slab (A and B).
 template <typename T, int KB> constexpr int ge_dma_per_wave() {
@@ -382,74 +389,97 @@ __device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const
   const int lr = lane & 15, lk = lane >> 4;
   const bool rowok = 16 * w < m;
   const int nbj = (n + 15) >> 4;
-  auto mma = [&](const D3M_LDS cpx<T>* cur, int p0) {
+  // one LDS slab of KBX columns into the accumulator; three widths only
+  // (more variants make the allocator copy the accumulator); LDS columns
+  // beyond n hold zeros or columns of B that only reach discarded outputs
+  auto mma = [&](const D3M_LDS cpx<T>* cur, int p0, auto kbx) {
+    constexpr int KBX = decltype(kbx)::value;
     if (!rowok) return;
     const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
-    const D3M_LDS cpx<T>* bp = cur + KB * GE_LDP + lk * GE_LDP + lr;
-    // three widths only (more variants make the allocator copy the
-    // accumulator); LDS columns beyond n hold zeros or columns of B that
-    // only reach discarded outputs
-    const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KB ? k - p0 : KB);
+    const D3M_LDS cpx<T>* bp = cur + KBX * GE_LDP + lk * GE_LDP + lr;
+    const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KBX ? k - p0 : KBX);
     if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
     else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
     else ge_mma<1>(acc, ap, bp, kend);
   };
   if constexpr (DMA && AM == OP_N) {
     if (ge_dma_ok<T>(A, dA, B)) {
-      // three LDS buffers: slab s is multiplied from buffer s % 3 while slab
-      // s + 2 loads into buffer (s + 2) % 3; before the barrier that ends
-      // step s each wave waits for its own loads of slab s + 1
-      constexpr int SL = 2 * KB * GE_LDP, NW = ge_dma_per_wave<T, KB>();
+      // NB LDS buffers: slab s is multiplied from buffer s % NB while slab
+      // s + NB - 1 loads into buffer (s + NB - 1) % NB; before the barrier
+      // that ends step s each wave waits for its own loads of slab s + 1
+      constexpr int KD = GeDma<T>::KB, NB = GeDma<T>::NBUF;
+      constexpr int SL = 2 * KD * GE_LDP, NW = ge_dma_per_wave<T, KD>();
+      using kdc = std::integral_constant<int, KD>;
       wg_sync_global();
       if (k <= 0 || m <= 0 || n <= 0) return;
-      ge_dma<T, KB>(A, B, m, n, k, 0, buf0);
-      if (KB < k) {
-        ge_dma<T, KB>(A, B, m, n, k, KB, buf0 + SL);
-        ge_wait_vm<NW>();
-      } else {
-        ge_wait_vm<0>();
-      }
+#pragma unroll
+      for (int q = 0; q < NB - 1; ++q)
+        if (q * KD < k) ge_dma<T, KD>(A, B, m, n, k, q * KD, buf0 + q * SL);
+      if (NB > 2 && KD < k) ge_wait_vm<NW * (NB - 2)>();
+      else ge_wait_vm<0>();
       __syncthreads();
       int s = 0;
-      for (int p0 = 0; p0 < k; p0 += KB, ++s) {
-        const int b = s % 3, b2 = (s + 2) % 3;
-        const bool more = p0 + 2 * KB < k;
-        if (more) ge_dma<T, KB>(A, B, m, n, k, p0 + 2 * KB, buf0 + b2 * SL);
-        mma(buf0 + b * SL, p0);
-        if (more) ge_wait_vm<NW>();
+      for (int p0 = 0; p0 < k; p0 += KD, ++s) {
+        const bool more = p0 + (NB - 1) * KD < k;
+        if (more) ge_dma<T, KD>(A, B, m, n, k, p0 + (NB - 1) * KD, buf0 + ((s + NB - 1) % NB) * SL);
+        mma(buf0 + (s % NB) * SL, p0, kdc());
+        if (more && NB > 2) ge_wait_vm<NW * (NB - 2)>();
         else ge_wait_vm<0>();
         __syncthreads();
       }
       return;
     }
   }
-  Slab<T, KB> sa, sb;  // two slabs in flight in registers
+  using kbc = std::integral_constant<int, KB>;
   const bool scaled = dA != nullptr;
   wg_sync_global();
   if (k <= 0 || m <= 0 || n <= 0) return;
-  // slab s lives in LDS buffer s & 1; while slab s is multiplied, slab s+1
-  // is written to the other buffer and slab s+3 is loaded into the register
-  // slab that held s+1 (sb for even s, sa for odd s): each load has two
-  // slabs of products to arrive; one barrier per slab
-  ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 0);
-  if (KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, KB);
-  ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-  if (2 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 2 * KB);
-  __syncthreads();
-  for (int p0 = 0; p0 < k; p0 += 2 * KB) {
-    mma(buf0, p0);
-    if (p0 + KB < k) {
-      ge_stash<T, KB, AM>(sb, A.mode, scaled, buf1, buf1 + KB * GE_LDP);
-      if (p0 + 3 * KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, p0 + 3 * KB);
-    }
+  if constexpr (sizeof(cpx<T>) == 8) {
+    // complex64: slab s lives in LDS buffer s & 1; while slab s is
+    // multiplied, slab s+1 is written to the other buffer and slab s+3 is
+    // loaded into the register slab that held s+1 (sb for even s, sa for odd
+    // s): each load has two slabs of products to arrive; one barrier per slab
+    Slab<T, KB> sa, sb;
+    ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 0);
+    if (KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, KB);
+    ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+    if (2 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 2 * KB);
     __syncthreads();
-    if (p0 + KB >= k) break;
-    mma(buf1, p0 + KB);
-    if (p0 + 2 * KB < k) {
-      ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-      if (p0 + 4 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, p0 + 4 * KB);
+    for (int p0 = 0; p0 < k; p0 += 2 * KB) {
+      mma(buf0, p0, kbc());
+      if (p0 + KB < k) {
+        ge_stash<T, KB, AM>(sb, A.mode, scaled, buf1, buf1 + KB * GE_LDP);
+        if (p0 + 3 * KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, p0 + 3 * KB);
+      }
+      __syncthreads();
+      if (p0 + KB >= k) break;
+      mma(buf1, p0 + KB, kbc());
+      if (p0 + 2 * KB < k) {
+        ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+        if (p0 + 4 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, p0 + 4 * KB);
+      }
+      __syncthreads();
     }
+  } else {
+    // complex128 (no registers for a second slab): slab s lives in buffer
+    // s & 1; while slab s is multiplied, slab s+1 is written to the other
+    // buffer and slab s+2 is loaded into registers; one barrier per slab
+    Slab<T, KB> sl;
+    ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, 0);
+    ge_stash<T, KB, AM>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
+    if (KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, KB);
     __syncthreads();
+    int s = 0;
+    for (int p0 = 0; p0 < k; p0 += KB, ++s) {
+      D3M_LDS cpx<T>* cur = (s & 1) ? buf1 : buf0;
+      D3M_LDS cpx<T>* nxt = (s & 1) ? buf0 : buf1;
+      mma(cur, p0, kbc());
+      if (p0 + KB < k) {
+        ge_stash<T, KB, AM>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
+        if (p0 + 2 * KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
+      }
+      __syncthreads();
+    }
   }
 }
 
