@@ -208,7 +208,7 @@ double w_gemm(double m, double n, double k) { return 22.0 + tile_work(m, n, k) /
 double w_trsm(double m, double n, double k) { return 23.0 + tile_work(m, n, k) / 4.2e5; }
 double w_fact(double n) {
   const double r = n / 128.0;
-  return 46.0 + 93.0 * r * r * r + 128.0 * r;
+  return 23.0 + 28.5 * r * r * r + 97.0 * r;
 }
 // solve tasks: weighted for 64 right-hand sides
 double w_solve(double m, double k) { return 22.0 + tile_work(m, 64, k) / 5.5e5; }

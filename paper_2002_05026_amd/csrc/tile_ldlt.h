@@ -4,19 +4,22 @@
 // 512-thread workgroup needs a few dozen barriers instead of one per pivot:
 //
 //   for each 16-column block k:
-//     wave 0: unblocked LDL^T of the 16x16 diagonal block and the inverse
-//             X_k of its unit lower factor (kept transposed in the block's
-//             free upper triangle)
-//     all:    L_ik = A_ik X_k^T D_k^-1 for the blocks below
+//     wave 0: unblocked LDL^T of the 16x16 diagonal block in registers (one
+//             row per lane, pivots and multipliers broadcast across lanes)
+//             and, from the same multipliers, the inverse X_k of its unit
+//             lower factor (one column per lane), kept transposed in the
+//             block's free upper triangle
+//     waves:  L_ik = A_ik X_k^T D_k^-1 for the blocks below (one block per
+//             wave on the matrix cores)
 //     all:    A_ij -= L_ik D_k L_jk^T on the trailing blocks (one 16x16x16
 //             complex product per block pair on the matrix cores)
 //
 // then L (strictly below the diagonal) and D (on it) go back to the tile in
 // global memory, and the full inverse Linv = L^-1 (m x m, column-major with
-// leading dimension ldl, zeros above the diagonal) is assembled by block
-// diagonals:
-//   Linv_ij = -X_i sum_{j <= q < i} L_iq Linv_qj.
-// Rows/columns beyond m are padded with the identity.
+// leading dimension ldl, zeros above the diagonal) is formed in place of L in
+// LDS, one block column at a time from the right (Linv L = I):
+//   Linv_ij = -(sum_{j < q <= i} Linv_iq L_qj) X_j,
+// and then written out.  Rows/columns beyond m are padded with the identity.
 #pragma once
 #include "gemm_engine.h"
 
@@ -65,6 +68,40 @@ template <typename T, typename S> __device__ __forceinline__ cpx<T> cvt_cpx(cpx<
   return r;
 }
 
+// value of v in lane l (l uniform across the wave)
+__device__ __forceinline__ float tl_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double tl_bcast(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <typename T> __device__ __forceinline__ cpx<T> tl_bcast(cpx<T> v, int l) {
+  cpx<T> r;
+  r.x = tl_bcast(v.x, l);
+  r.y = tl_bcast(v.y, l);
+  return r;
+}
+
+template <typename T> __device__ __forceinline__ cpx<T> tl_inv(cpx<T> d) {
+  const T den = d.x * d.x + d.y * d.y;
+  cpx<T> r;
+  r.x = d.x / den;
+  r.y = -d.y / den;
+  return r;
+}
+
+// v -= a * b
+template <typename T> __device__ __forceinline__ void tl_msub(cpx<T>& v, cpx<T> a, cpx<T> b) {
+  v.x -= a.x * b.x - a.y * b.y;
+  v.y -= a.x * b.y + a.y * b.x;
+}
+
+// Element (i, j), i >= j, of the lower block triangle.
+template <typename T> __device__ __forceinline__ int tl_at(int i, int j) {
+  return tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15);
+}
+
 // T: arithmetic precision; TS: storage precision of the tile, D and Linv.
 // Returns true (and writes nothing back) when the growth check is on and
 // trips; bad pivots are only recorded when the check is off.
@@ -80,118 +117,126 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
   D3M_GLB cpx<TS>* dout = gptr_mut<TS>(dout_);
   D3M_GLB cpx<TS>* linv = gptr_mut<TS>(linv_);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
   const int nb = (m + 15) >> 4;
   const int M = nb * 16;
+  // element loops: thread -> row ri (coalesced in global memory), columns
+  // cj, cj + 4, ...
+  constexpr int kColStep = kThreads / kTileMax;
+  const int ri = tid % kTileMax, cj = tid / kTileMax;
   wg_sync_global();
   if (tid < 4) flags[tid] = (tid == 1) ? 0x7f800000 : 0;
   __syncthreads();
-  // lower block triangle from the tile's lower triangle; identity padding
-  float amax = 0.f;
-  for (int e = tid; e < M * M; e += kThreads) {
-    const int i = e % M, j = e / M;
-    if ((i >> 4) < (j >> 4)) continue;
-    cpx<T> v;
-    if (i < m && j < m) {
-      if (i >= j) {
-        v = cvt_cpx<T>(a[i + (int64_t)j * lda]);
-        amax = fmaxf(amax, (float)sqrt(v.x * v.x + v.y * v.y));
-      } else { v.x = 0; v.y = 0; }  // upper part of a diagonal block: scratch
-    } else {
-      v.x = (i == j) ? (T)1 : (T)0;
-      v.y = 0;
+  // lower block triangle from the tile's lower triangle; identity padding.
+  // Loads are issued in batches so that their latencies overlap.
+  {
+    constexpr int U = 16;
+    float amax = 0.f;
+    for (int j0 = 0; j0 < M; j0 += kColStep * U) {
+      cpx<TS> buf[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + cj + kColStep * u;
+        if (ri < m && j < m && ri >= j) buf[u] = a[ri + (int64_t)j * lda];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + cj + kColStep * u;
+        if (ri >= M || j >= M || (ri >> 4) < (j >> 4)) continue;
+        cpx<T> v;
+        if (ri < m && j < m) {
+          if (ri >= j) {
+            v = cvt_cpx<T>(buf[u]);
+            amax = fmaxf(amax, (float)sqrt(v.x * v.x + v.y * v.y));
+          } else { v.x = 0; v.y = 0; }  // upper part of a diagonal block: scratch
+        } else {
+          v.x = (ri == j) ? (T)1 : (T)0;
+          v.y = 0;
+        }
+        S[tl_at<T>(ri, j)] = v;
+      }
     }
-    S[tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15)] = v;
+    if (gc.on) atomicMax((int*)(flags), __float_as_int(amax));
   }
-  if (gc.on) atomicMax((int*)(flags), __float_as_int(amax));
   __syncthreads();
   for (int kb = 0; kb < nb; ++kb) {
     const int bkk = tl_blk(kb, kb);
     if (w == 0) {
-      // unblocked LDL^T of the 16x16 diagonal block
+      // Lane r holds row r of the diagonal block (ra) and column r of X
+      // (xc).  Step k: pivot d = A(k,k); multipliers L(c,k) = A(c,k)/d come
+      // from lane c; A(r,c) -= A(r,k) L(c,k) and X(c,r) -= L(c,k) X(k,r)
+      // for c > k (X(k,r) is final once step k is reached).
+      // (r is made opaque so that the per-lane constants below are not
+      // hoisted out of the kb loop into registers held across it)
+      int r = lr;
+      asm volatile("" : "+v"(r));
+      cpx<T> ra[16], xc[16], dr;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        ra[c] = S[bkk + c * 16 + r];
+        xc[c].x = (c == r) ? (T)1 : (T)0;
+        xc[c].y = 0;
+      }
+      dr.x = 1;
+      dr.y = 0;
+#pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const cpx<T> d = S[bkk + k * 16 + k];
-        if (lane == 0 && kb * 16 + k < m) {
-          const T ad = sqrt(d.x * d.x + d.y * d.y);
-          const bool bad = !(ad > (T)0) || !isfinite(d.x) || !isfinite(d.y);
+        const cpx<T> d = tl_bcast(ra[k], k);
+        if (r == k) dr = d;
+        const cpx<T> l = tl_mul(ra[k], tl_inv(d));  // L(r,k) for r > k
+#pragma unroll
+        for (int c = k + 1; c < 16; ++c) {
+          const cpx<T> lc = tl_bcast(l, c);
+          tl_msub(ra[c], ra[k], lc);
+          tl_msub(xc[c], lc, xc[k]);
+        }
+        if (r > k) ra[k] = l;
+      }
+      if (lane < 16) {
+        // row r of the block: L(r,c) left of the diagonal, d_r on it, X(c,r)
+        // to the right (the transposed X)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) S[bkk + c * 16 + r] = (c < r) ? ra[c] : (c == r) ? dr : xc[c];
+        dv[kb * 16 + r] = dr;
+        if (kb * 16 + r < m) {
+          const T ad = sqrt(dr.x * dr.x + dr.y * dr.y);
+          const bool bad = !(ad > (T)0) || !isfinite(dr.x) || !isfinite(dr.y);
           if (gc.on) {
             if (bad) flags[3] = 1;
             else atomicMin((int*)(flags + 1), __float_as_int((float)ad));
           } else {
             if (bad) {
-              atomicMin(&status[0], row0 + kb * 16 + k);
+              atomicMin(&status[0], row0 + kb * 16 + r);
               atomicAdd(&status[1], 1);
             }
             if (gmin_d) atomicMin(reinterpret_cast<int*>(gmin_d), __float_as_int((float)ad));
           }
         }
-        const T den = d.x * d.x + d.y * d.y;
-        cpx<T> dinv;
-        dinv.x = d.x / den;
-        dinv.y = -d.y / den;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int e = lane + 64 * t, r = e & 15, c = e >> 4;
-          if (c > k && r >= c) {
-            const cpx<T> lr = S[bkk + k * 16 + r], lc = S[bkk + k * 16 + c];
-            const cpx<T> u = tl_mul(tl_mul(lr, dinv), lc);
-            cpx<T> v = S[bkk + c * 16 + r];
-            v.x -= u.x;
-            v.y -= u.y;
-            S[bkk + c * 16 + r] = v;
-          }
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane > k && lane < 16) S[bkk + k * 16 + lane] = tl_mul(S[bkk + k * 16 + lane], dinv);
-        __builtin_amdgcn_wave_barrier();
       }
-      // X = inverse of the unit lower factor, column j by lane j, stored
-      // transposed above the diagonal: S(j, i) = X(i, j)
-      if (lane < 16) {
-        const int j = lane;
-        for (int i = j + 1; i < 16; ++i) {
-          cpx<T> s = S[bkk + j * 16 + i];  // L(i, j) * X(j, j)
-          for (int q = j + 1; q < i; ++q) {
-            const cpx<T> l = S[bkk + q * 16 + i], x = S[bkk + q * 16 + j];  // L(i,q), X(q,j)
-            const cpx<T> p = tl_mul(l, x);
-            s.x += p.x;
-            s.y += p.y;
-          }
-          s.x = -s.x;
-          s.y = -s.y;
-          S[bkk + i * 16 + j] = s;  // X(i, j) at (row j, col i)
-        }
-      }
-      if (lane < 16) dv[kb * 16 + lane] = S[bkk + lane * 16 + lane];
     }
     __syncthreads();
-    // L_ik = A_ik X_k^T D_k^-1 for block rows i > kb
-    {
-      const int nbelow = nb - kb - 1;
-      cpx<T> res[4];
-      int cnt = 0;
-      for (int e = tid; e < nbelow * 256 && cnt < 4; e += kThreads, ++cnt) {
-        const int bi = kb + 1 + (e >> 8), r = e & 15, c = (e >> 4) & 15;
-        const int bo = tl_blk(bi, kb);
-        cpx<T> s;
-        s.x = 0;
-        s.y = 0;
-        for (int q = 0; q <= c; ++q) {
-          const cpx<T> p = tl_mul(S[bo + q * 16 + r], tl_x(S, kb, c, q));
-          s.x += p.x;
-          s.y += p.y;
-        }
-        const cpx<T> d = dv[kb * 16 + c];
-        const T den = d.x * d.x + d.y * d.y;
-        cpx<T> dinv;
-        dinv.x = d.x / den;
-        dinv.y = -d.y / den;
-        res[cnt] = tl_mul(s, dinv);
+    // L_ik = A_ik X_k^T D_k^-1 for block rows i > kb, one block per wave;
+    // each wave overwrites only the block it read
+    if (w < nb - kb - 1) {
+      const int bo = tl_blk(kb + 1 + w, kb);
+      v4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int kq = kk + lk;
+        const cpx<T> av = S[bo + kq * 16 + lr];  // A_ik(lr, kq)
+        const cpx<T> bv = tl_x(S, kb, lr, kq);   // B(kq, lr) = X_k(lr, kq)
+        re = mfma16(av.x, bv.x, re);
+        re = mfma16(-av.y, bv.y, re);
+        im = mfma16(av.x, bv.y, im);
+        im = mfma16(av.y, bv.x, im);
       }
-      __syncthreads();
-      cnt = 0;
-      for (int e = tid; e < nbelow * 256 && cnt < 4; e += kThreads, ++cnt) {
-        const int bi = kb + 1 + (e >> 8), r = e & 15, c = (e >> 4) & 15;
-        S[tl_blk(bi, kb) + c * 16 + r] = res[cnt];
+      const cpx<T> dinv = tl_inv(dv[kb * 16 + lr]);  // column lr of the result
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cpx<T> t;
+        t.x = re[v];
+        t.y = im[v];
+        S[bo + lr * 16 + acc_row<T>(lk, v)] = tl_mul(t, dinv);
       }
     }
     __syncthreads();
@@ -199,7 +244,6 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
     {
       const int nt = nb - kb - 1;
       const int npair = nt * (nt + 1) / 2;
-      const int lr = lane & 15, lk = lane >> 4;
       for (int pr = w; pr < npair; pr += kThreads / 64) {
         int bi = 0, rem = pr;
         while (rem > bi) { rem -= bi + 1; ++bi; }
@@ -233,14 +277,13 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
   if (gc.on) {
     float lm = 0.f;
     bool nf = false;
-    for (int e = tid; e < m * m; e += kThreads) {
-      const int i = e % m, j = e / m;
-      if (i <= j) continue;
-      const cpx<T> v = S[tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15)];
-      const float av = (float)sqrt(v.x * v.x + v.y * v.y);
-      if (!(av <= 3.0e38f)) nf = true;
-      else lm = fmaxf(lm, av);
-    }
+    if (ri < m)
+      for (int j = cj; j < ri; j += kColStep) {
+        const cpx<T> v = S[tl_at<T>(ri, j)];
+        const float av = (float)sqrt(v.x * v.x + v.y * v.y);
+        if (!(av <= 3.0e38f)) nf = true;
+        else lm = fmaxf(lm, av);
+      }
     atomicMax((int*)(flags + 2), __float_as_int(lm));
     if (nf) flags[3] = 1;
     __syncthreads();
@@ -251,93 +294,85 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
     if (tid == 0 && gmin_d) atomicMin(reinterpret_cast<int*>(gmin_d), __float_as_int(fd));
   }
   // L and D back to the tile; D to dout
-  float lmax = 0.f;
-  for (int e = tid; e < m * m; e += kThreads) {
-    const int i = e % m, j = e / m;
-    if (i < j) continue;
-    const cpx<T> v = S[tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15)];
-    a[i + (int64_t)j * lda] = cvt_cpx<TS>(v);
-    if (i == j) dout[i] = cvt_cpx<TS>(v);
-    else lmax = fmaxf(lmax, (float)sqrt(v.x * v.x + v.y * v.y));
+  {
+    float lmax = 0.f;
+    if (ri < m)
+      for (int j = cj; j <= ri; j += kColStep) {
+        const cpx<T> v = S[tl_at<T>(ri, j)];
+        a[ri + (int64_t)j * lda] = cvt_cpx<TS>(v);
+        if (ri == j) dout[ri] = cvt_cpx<TS>(v);
+        else lmax = fmaxf(lmax, (float)sqrt(v.x * v.x + v.y * v.y));
+      }
+    if (gmax_l) atomicMax(reinterpret_cast<int*>(gmax_l), __float_as_int(lmax));
   }
-  if (gmax_l) atomicMax(reinterpret_cast<int*>(gmax_l), __float_as_int(lmax));
-  // Linv: diagonal blocks and zeros above them
-  for (int e = tid; e < m * m; e += kThreads) {
-    const int i = e % m, j = e / m;
-    if ((i >> 4) > (j >> 4)) continue;
-    cpx<T> v;
-    if ((i >> 4) == (j >> 4)) v = tl_x(S, i >> 4, i & 15, j & 15);
-    else { v.x = 0; v.y = 0; }
-    linv[i + (int64_t)j * ldl] = cvt_cpx<TS>(v);
-  }
-  // block diagonals d = 1.. of Linv: T = sum_q L_iq Linv_qj, Linv_ij = -X_i T
-  const int lr = lane & 15, lk = lane >> 4;
-  for (int dist = 1; dist < nb; ++dist) {
-    wg_sync_global();
-    for (int bj = w; bj + dist < nb; bj += kThreads / 64) {
-      const int bi = bj + dist;
-      v4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-      for (int q = bj; q < bi; ++q) {
-        const int boq = tl_blk(bi, q);
+  // Linv in place of L, block column j from the right:
+  //   T = sum_{j < q <= i} Linv_iq L_qj   (Linv_ii = X_i),   Linv_ij = -T X_j
+  // Wave w takes block row i = j + 1 + w.  T replaces L_ij only after every
+  // wave has read column j; the product with X_j reads T back through LDS
+  // to change its register layout.
+  for (int j = nb - 2; j >= 0; --j) {
+    const int bi = j + 1 + w;
+    const bool act = bi < nb;
+    v4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+    if (act) {
+      for (int q = j + 1; q <= bi; ++q) {
+        const int boa = tl_blk(bi, q), bob = tl_blk(q, j);
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
           const int kq = kk + lk;
-          const cpx<T> av = S[boq + kq * 16 + lr];  // L(bi,q)(lr, kq)
-          cpx<T> bv;                               // Linv(q,bj)(kq, lr)
-          if (q == bj) bv = tl_x(S, bj, kq, lr);
-          else {
-            const int gr = 16 * q + kq, gcl = 16 * bj + lr;
-            if (gr < m && gcl < m) bv = cvt_cpx<T>(linv[gr + (int64_t)gcl * ldl]);
-            else { bv.x = (gr == gcl) ? (T)1 : (T)0; bv.y = 0; }
-          }
+          const cpx<T> av = (q == bi) ? tl_x(S, bi, lr, kq) : S[boa + kq * 16 + lr];  // Linv_iq(lr, kq)
+          const cpx<T> bv = S[bob + lr * 16 + kq];                                      // L_qj(kq, lr)
           re = mfma16(av.x, bv.x, re);
           re = mfma16(-av.y, bv.y, re);
           im = mfma16(av.x, bv.y, im);
           im = mfma16(av.y, bv.x, im);
         }
       }
-      // T goes through the output block of Linv to change register layout
-      const int gcl = 16 * bj + lr;
+    }
+    __syncthreads();
+    if (act) {
+      const int bo = tl_blk(bi, j);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gr = 16 * bi + acc_row<T>(lk, v);
-        if (gr < m && gcl < m) {
-          cpx<T> t;
-          t.x = re[v];
-          t.y = im[v];
-          linv[gr + (int64_t)gcl * ldl] = cvt_cpx<TS>(t);
-        }
+        cpx<T> t;
+        t.x = re[v];
+        t.y = im[v];
+        S[bo + lr * 16 + acc_row<T>(lk, v)] = t;
       }
-      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // LDS writes done
       __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       v4 re2 = {0, 0, 0, 0}, im2 = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < 16; kk += 4) {
         const int kq = kk + lk;
-        const cpx<T> av = tl_x(S, bi, lr, kq);  // X_i(lr, kq)
-        cpx<T> bv;                             // T(kq, lr)
-        const int gr = 16 * bi + kq;
-        if (gr < m && gcl < m) bv = cvt_cpx<T>(linv[gr + (int64_t)gcl * ldl]);
-        else { bv.x = 0; bv.y = 0; }
+        const cpx<T> av = S[bo + kq * 16 + lr];  // T(lr, kq)
+        const cpx<T> bv = tl_x(S, j, kq, lr);    // X_j(kq, lr)
         re2 = mfma16(av.x, bv.x, re2);
         re2 = mfma16(-av.y, bv.y, re2);
         im2 = mfma16(av.x, bv.y, im2);
         im2 = mfma16(av.y, bv.x, im2);
       }
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gr = 16 * bi + acc_row<T>(lk, v);
-        if (gr < m && gcl < m) {
-          cpx<T> t;
-          t.x = -re2[v];
-          t.y = -im2[v];
-          linv[gr + (int64_t)gcl * ldl] = cvt_cpx<TS>(t);
-        }
+        cpx<T> t;
+        t.x = -re2[v];
+        t.y = -im2[v];
+        S[bo + lr * 16 + acc_row<T>(lk, v)] = t;
       }
     }
+    __syncthreads();
   }
+  // Linv out: zeros above the block diagonal, X_i on it, the blocks below
+  if (ri < m)
+    for (int j = cj; j < m; j += kColStep) {
+      cpx<T> v;
+      if ((ri >> 4) < (j >> 4)) { v.x = 0; v.y = 0; }
+      else if ((ri >> 4) == (j >> 4)) v = tl_x(S, ri >> 4, ri & 15, j & 15);
+      else v = S[tl_at<T>(ri, j)];
+      linv[ri + (int64_t)j * ldl] = cvt_cpx<TS>(v);
+    }
   wg_sync_global();
   return false;
 }
