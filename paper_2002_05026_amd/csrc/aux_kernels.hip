@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const doubl
   __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes_dma<double>()];
   const DkTaskDev t = dt[blockIdx.x];
   const int64_t ri = uv.row0[t.I] + t.r0, rj = uv.row0[t.J] + t.c0;
-  Acc<double> acc;
+  Acc<double, true> acc;
   acc.zero();
   Opnd<double> A, B;
   A.mode = B.mode = OP_N;

@@ -90,14 +90,14 @@ __device__ __noinline__ void task_fact(const Ctx<T>& cx, const Task& t) {
 // LD at the same place (TK_TRSM)
 template <typename T>
 __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
-  Acc<T> acc;
+  Acc<T, true> acc;
   acc.zero();
   gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
                                       opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
   Out<T> o = outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0);
   o.dst2 = cx.LD + t.a_off;
   o.coldiv = cx.D + t.dofs;
-  gemm_store<T>(acc, t.m, t.n, o);
+  gemm_store<T>(acc, t.m, t.n, o, cx.lds);
 }
 
 // C -= sum over the task's sources of (L_rI D_I) L_sI^T on one tile pair
@@ -105,7 +105,7 @@ __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
 // own operands
 template <typename T>
 __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
-  Acc<T> acc;
+  Acc<T, true> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
   for (int q = 0; q < nsrc; ++q) {
@@ -127,7 +127,7 @@ __device__ __noinline__ void task_inv(const Ctx<T>& cx, const Task& t) {
   typedef typename Cplx<T>::type C;
   C* Lb = cx.Li + P.ioff;
   const int n = P.n;
-  Acc<T> acc;
+  Acc<T, true> acc;
   acc.zero();
   gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, tc.sz, tr.sz, tr.r0 - tc.r0, opn<T>(Lb + tc.r0 + (int64_t)tc.r0 * n, n, OP_T),
                                     nullptr,

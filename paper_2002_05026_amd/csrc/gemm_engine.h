@@ -125,7 +125,15 @@ template <typename T> struct Out {
 // so re = P1 - P2 and im = P3 - P1 - P2; this takes 3 instead of 4 MFMAs per
 // block and k-step.  The parts stay separate until read with acc_val, so
 // several gemm_acc calls may add into one accumulator.
-template <typename T> struct Acc {
+//
+// TR picks the fragment orientation.  false: item v of column block bj in
+// lane (lr, lk) of wave w is C(16w + acc_row(lk, v), 16bj + lr), so a store
+// instruction covers 16 consecutive columns (whole lines of a row-major C).
+// true: the MFMA operands are swapped (the block is formed as (B A^T)^T,
+// the same products summed in the same order), and the item is
+// C(16w + lr, 16bj + acc_row(lk, v)): 16 consecutive rows, whole lines of a
+// column-major C.
+template <typename T, bool TR = false> struct Acc {
   typename V4<T>::type re[8], im[8];
   __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -135,7 +143,7 @@ template <typename T> struct Acc {
     }
   }
 };
-template <> struct Acc<float> {
+template <bool TR> struct Acc<float, TR> {
   v4f p1[8], p2[8], p3[8];
   __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -148,18 +156,25 @@ template <> struct Acc<float> {
 };
 
 // Complex value of accumulator item v of column block bj.
-__device__ __forceinline__ cpx<double> acc_val(const Acc<double>& a, int bj, int v) {
+template <bool TR> __device__ __forceinline__ cpx<double> acc_val(const Acc<double, TR>& a, int bj, int v) {
   cpx<double> r;
   r.x = a.re[bj][v];
   r.y = a.im[bj][v];
   return r;
 }
-__device__ __forceinline__ cpx<float> acc_val(const Acc<float>& a, int bj, int v) {
+template <bool TR> __device__ __forceinline__ cpx<float> acc_val(const Acc<float, TR>& a, int bj, int v) {
   cpx<float> r;
   const float x = a.p1[bj][v], y = a.p2[bj][v];
   r.x = x - y;
   r.y = a.p3[bj][v] - x - y;
   return r;
+}
+
+// c + a b^T on the matrix cores with a's fragment as the A operand (or as
+// the B operand when TR)
+template <bool TR, typename T, typename V> __device__ __forceinline__ V mfma_or(T a, T b, V c) {
+  if constexpr (TR) return mfma16(b, a, c);
+  else return mfma16(a, b, c);
 }
 
 // LDS bytes the engine needs for slabs of KB columns.
@@ -259,8 +274,8 @@ __device__ __forceinline__ void ge_stash(const Slab<T, KB>& sl, int amode_rt, bo
 // One LDS slab into the accumulator: NBJ column blocks (compile time, so the
 // fragment reads of a k-step are issued together ahead of its MFMAs), k-steps
 // below kend (the slab's columns beyond k hold zeros and are skipped).
-template <int NBJ>
-__device__ __forceinline__ void ge_mma(Acc<double>& acc, const D3M_LDS cpx<double>* ap,
+template <int NBJ, bool TR>
+__device__ __forceinline__ void ge_mma(Acc<double, TR>& acc, const D3M_LDS cpx<double>* ap,
                                        const D3M_LDS cpx<double>* bp, int kend) {
   // one k-step at a time keeps the fragment registers few (the other wave
   // on the SIMD covers the LDS latency)
@@ -273,15 +288,15 @@ __device__ __forceinline__ void ge_mma(Acc<double>& acc, const D3M_LDS cpx<doubl
     const double nai = -a0.y;
 #pragma unroll
     for (int bj = 0; bj < NBJ; ++bj) {
-      acc.re[bj] = mfma16(a0.x, b[bj].x, acc.re[bj]);
-      acc.re[bj] = mfma16(nai, b[bj].y, acc.re[bj]);
-      acc.im[bj] = mfma16(a0.x, b[bj].y, acc.im[bj]);
-      acc.im[bj] = mfma16(a0.y, b[bj].x, acc.im[bj]);
+      acc.re[bj] = mfma_or<TR>(a0.x, b[bj].x, acc.re[bj]);
+      acc.re[bj] = mfma_or<TR>(nai, b[bj].y, acc.re[bj]);
+      acc.im[bj] = mfma_or<TR>(a0.x, b[bj].y, acc.im[bj]);
+      acc.im[bj] = mfma_or<TR>(a0.y, b[bj].x, acc.im[bj]);
     }
   }
 }
-template <int NBJ>
-__device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>* ap,
+template <int NBJ, bool TR>
+__device__ __forceinline__ void ge_mma(Acc<float, TR>& acc, const D3M_LDS cpx<float>* ap,
                                        const D3M_LDS cpx<float>* bp, int kend) {
 #pragma unroll 1
   for (int kk = 0; kk < kend; kk += 4) {
@@ -292,9 +307,9 @@ __device__ __forceinline__ void ge_mma(Acc<float>& acc, const D3M_LDS cpx<float>
     const float as = a0.x + a0.y;
 #pragma unroll
     for (int bj = 0; bj < NBJ; ++bj) {
-      acc.p1[bj] = mfma16(a0.x, b[bj].x, acc.p1[bj]);
-      acc.p2[bj] = mfma16(a0.y, b[bj].y, acc.p2[bj]);
-      acc.p3[bj] = mfma16(as, b[bj].x + b[bj].y, acc.p3[bj]);
+      acc.p1[bj] = mfma_or<TR>(a0.x, b[bj].x, acc.p1[bj]);
+      acc.p2[bj] = mfma_or<TR>(a0.y, b[bj].y, acc.p2[bj]);
+      acc.p3[bj] = mfma_or<TR>(as, b[bj].x + b[bj].y, acc.p3[bj]);
     }
   }
 }
@@ -380,8 +395,8 @@ __device__ __forceinline__ bool ge_dma_ok(const Opnd<T>& A, const typename Cplx<
 // which keeps the per-element address and layout choice out of the slab code.
 // DMA: the caller's lds holds ge_lds_bytes_dma<T, KB>() and A is OP_N (AM),
 // so that aligned operands may take the direct-load path.
-template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false>
-__device__ __forceinline__ void gemm_acc(Acc<T>& acc, int m, int n, int k, const Opnd<T>& A,
+template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool TR = false>
+__device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   D3M_LDS cpx<T>* buf1 = buf0 + 2 * KB * GE_LDP;
@@ -499,58 +514,110 @@ template <> struct GeStoreBatch<double> { static constexpr int NB = 4; };
 
 // Write the accumulator through the store descriptor.  All loads of a batch
 // of column blocks (beta term, divisors) are issued first from clamped
-// addresses, then the results are formed and stored.
-template <typename T>
-__device__ __forceinline__ void gemm_store(const Acc<T>& acc, int m, int n, const Out<T>& o) {
+// addresses, then the results are formed and stored.  With TR the column
+// divisors go through LDS (lds: at least n elements, free after gemm_acc)
+// and every wave of the workgroup must call, since that takes a barrier.
+template <typename T, bool TR>
+__device__ __forceinline__ void gemm_store(const Acc<T, TR>& acc, int m, int n, const Out<T>& o,
+                                           lds_char* lds = nullptr) {
   constexpr int NBB = GeStoreBatch<T>::NB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  if (16 * w >= m) return;
   D3M_GLB cpx<T>* dst = gptr_mut<T>(o.dst);
-  cpx<T> rd[4];
-  if (o.rowdiv) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 16 * w + acc_row<T>(lk, v);
-      rd[v] = *gptr<T>(o.rowdiv + (i < m ? i : 0));
+  if constexpr (TR) {
+    D3M_LDS cpx<T>* cds = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
+    if (o.coldiv) {
+      for (int j = threadIdx.x; j < n; j += kThreads) cds[j] = *gptr<T>(o.coldiv + j);
+      __syncthreads();
     }
-  }
+    if (16 * w >= m) return;
+    const int i = 16 * w + lr;
+    const bool iok = i < m;
+    const int ic = iok ? i : 0;
+    cpx<T> rd;
+    if (o.rowdiv) rd = *gptr<T>(o.rowdiv + ic);
 #pragma unroll
-  for (int bt = 0; bt < 8 / NBB; ++bt) {
-    if (16 * NBB * bt >= n) break;
-    cpx<T> src[NBB][4], cd[NBB];
+    for (int bt = 0; bt < 8 / NBB; ++bt) {
+      if (16 * NBB * bt >= n) break;
+      cpx<T> src[NBB][4];
 #pragma unroll
-    for (int b4 = 0; b4 < NBB; ++b4) {
-      const int bj = NBB * bt + b4;
-      const int j = 16 * bj + lr;
-      const int jc = j < n ? j : 0;
-      if (o.coldiv) cd[b4] = *gptr<T>(o.coldiv + jc);
+      for (int b4 = 0; b4 < NBB; ++b4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * (NBB * bt + b4) + acc_row<T>(lk, v);
+          const int jc = j < n ? j : 0;
+          if (o.src) src[b4][v] = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
+        }
+      }
+#pragma unroll
+      for (int b4 = 0; b4 < NBB; ++b4) {
+        const int bj = NBB * bt + b4;
+        if (16 * bj >= n) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * bj + acc_row<T>(lk, v);
+          cpx<T> r = acc_val(acc, bj, v);
+          r.x *= o.alpha;
+          r.y *= o.alpha;
+          if (o.src) {
+            r.x += o.beta * src[b4][v].x;
+            r.y += o.beta * src[b4][v].y;
+          }
+          const bool ok = iok && j < n;
+          if (o.dst2 && ok) gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+          if (o.rowdiv) r = cpx_div(r, rd);
+          if (o.coldiv) r = cpx_div(r, cds[j < n ? j : 0]);
+          if (ok) dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+        }
+      }
+    }
+  } else {
+    if (16 * w >= m) return;
+    cpx<T> rd[4];
+    if (o.rowdiv) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * w + acc_row<T>(lk, v);
-        const int ic = i < m ? i : 0;
-        if (o.src) src[b4][v] = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
+        rd[v] = *gptr<T>(o.rowdiv + (i < m ? i : 0));
       }
     }
 #pragma unroll
-    for (int b4 = 0; b4 < NBB; ++b4) {
-      const int bj = NBB * bt + b4;
-      const int j = 16 * bj + lr;
-      if (16 * bj >= n) break;
+    for (int bt = 0; bt < 8 / NBB; ++bt) {
+      if (16 * NBB * bt >= n) break;
+      cpx<T> src[NBB][4], cd[NBB];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * w + acc_row<T>(lk, v);
-        cpx<T> r = acc_val(acc, bj, v);
-        r.x *= o.alpha;
-        r.y *= o.alpha;
-        if (o.src) {
-          r.x += o.beta * src[b4][v].x;
-          r.y += o.beta * src[b4][v].y;
+      for (int b4 = 0; b4 < NBB; ++b4) {
+        const int bj = NBB * bt + b4;
+        const int j = 16 * bj + lr;
+        const int jc = j < n ? j : 0;
+        if (o.coldiv) cd[b4] = *gptr<T>(o.coldiv + jc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * w + acc_row<T>(lk, v);
+          const int ic = i < m ? i : 0;
+          if (o.src) src[b4][v] = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
         }
-        if (o.dst2 && i < m && j < n) gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
-        if (o.rowdiv) r = cpx_div(r, rd[v]);
-        if (o.coldiv) r = cpx_div(r, cd[b4]);
-        if (i < m && j < n) dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+      }
+#pragma unroll
+      for (int b4 = 0; b4 < NBB; ++b4) {
+        const int bj = NBB * bt + b4;
+        const int j = 16 * bj + lr;
+        if (16 * bj >= n) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * w + acc_row<T>(lk, v);
+          cpx<T> r = acc_val(acc, bj, v);
+          r.x *= o.alpha;
+          r.y *= o.alpha;
+          if (o.src) {
+            r.x += o.beta * src[b4][v].x;
+            r.y += o.beta * src[b4][v].y;
+          }
+          if (o.dst2 && i < m && j < n) gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+          if (o.rowdiv) r = cpx_div(r, rd[v]);
+          if (o.coldiv) r = cpx_div(r, cd[b4]);
+          if (i < m && j < n) dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+        }
       }
     }
   }
