@@ -347,11 +347,14 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
     loff += (int64_t)h * nI;
     P.ioff = linv;
     linv += (int64_t)nI * nI;
-    // tiles: nt = ceil(n/T), near-equal sizes rounded up to 16
+    // tiles: nt = ceil(n/T), all of size T but the last.  A tile product
+    // costs the same MFMA time for any row count in (64, 128] (8 waves of 16
+    // rows, two per SIMD) and any column count in (64, 128], so full tiles
+    // and one short remainder (which costs half when it is 64 or less) take
+    // less MFMA time than near-equal sizes: n = 300 as 128+128+44 costs
+    // 128+128+64 rows against 3*128 for 112+112+76.
     int nt = (nI + tile - 1) / tile;
-    int base = (nI + nt - 1) / nt;
-    base = ((base + 15) / 16) * 16;
-    if (base > tile) base = tile;
+    int base = tile;
     P.tile0 = (int32_t)p.tiles.size();
     P.nt = nt;
     for (int c = 0; c < nt; ++c) {
