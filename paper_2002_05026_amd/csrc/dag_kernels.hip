@@ -108,13 +108,25 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
   Acc<T, true> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
-  for (int q = 0; q < nsrc; ++q) {
+  const Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1);
+  // complex64: the target's loads go out with the last slab of the last
+  // source (registers allow it; complex128 loads it after the product)
+  GePre<T> pre;
+  pre.ok = false;
+  auto src = [&](int q) {
     XSrc x{t.a_off, t.b_off, t.k, t.lda};
     if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
+    return x;
+  };
+  for (int q = 0; q < nsrc - 1; ++q) {
+    const XSrc x = src(q);
     gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
                                         opn<T>(cx.L + x.b_off, x.lda), cx.lds);
   }
-  gemm_store<T>(acc, t.m, t.n, outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1));
+  const XSrc x = src(nsrc - 1);
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, sizeof(T) == 4>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda),
+                                                      nullptr, opn<T>(cx.L + x.b_off, x.lda), cx.lds, &pre, &o);
+  gemm_store<T>(acc, t.m, t.n, o, nullptr, pre);
 }
 
 // tile (r, c) of the inverse of panel I's unit lower diagonal block:

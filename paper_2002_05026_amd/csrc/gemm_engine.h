@@ -395,9 +395,19 @@ __device__ __forceinline__ bool ge_dma_ok(const Opnd<T>& A, const typename Cplx<
 // which keeps the per-element address and layout choice out of the slab code.
 // DMA: the caller's lds holds ge_lds_bytes_dma<T, KB>() and A is OP_N (AM),
 // so that aligned operands may take the direct-load path.
-template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool TR = false>
+// PRE: on the direct-load path the beta term of the store *po is loaded
+// into *pre at the start of the last slab's products, so that its latency
+// overlaps them (pre->ok tells the store).  A flag rather than a null test:
+// a null test of a pointer to a local keeps the local out of registers.
+template <typename T> struct GePre;
+template <typename T> struct Out;
+template <typename T>
+__device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Out<T>& o);
+template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool PRE = false,
+          bool TR = false>
 __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
-                         const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds) {
+                         const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds,
+                         GePre<T>* pre = nullptr, const Out<T>* po = nullptr) {
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   D3M_LDS cpx<T>* buf1 = buf0 + 2 * KB * GE_LDP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -433,13 +443,23 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
       if (NB > 2 && KD < k) ge_wait_vm<NW * (NB - 2)>();
       else ge_wait_vm<0>();
       __syncthreads();
-      int s = 0;
-      for (int p0 = 0; p0 < k; p0 += KD, ++s) {
+      auto step = [&](int s, int p0) __attribute__((always_inline)) {
         const bool more = p0 + (NB - 1) * KD < k;
         if (more) ge_dma<T, KD>(A, B, m, n, k, p0 + (NB - 1) * KD, buf0 + ((s + NB - 1) % NB) * SL);
         mma(buf0 + (s % NB) * SL, p0, kdc());
         if (more && NB > 2) ge_wait_vm<NW * (NB - 2)>();
         else ge_wait_vm<0>();
+        __syncthreads();
+      };
+      // with PRE the last slab is peeled off, so that the preloaded values
+      // are live only while it is multiplied
+      const int nsl = (k + KD - 1) / KD;
+      for (int s = 0; s < nsl - (PRE ? 1 : 0); ++s) step(s, s * KD);
+      if constexpr (PRE) {
+        const int s = nsl - 1;
+        ge_preload<T>(*pre, m, n, *po);
+        mma(buf0 + (s % NB) * SL, s * KD, kdc());
+        ge_wait_vm<0>();
         __syncthreads();
       }
       return;
@@ -512,14 +532,39 @@ template <typename T> struct GeStoreBatch;
 template <> struct GeStoreBatch<float> { static constexpr int NB = 8; };
 template <> struct GeStoreBatch<double> { static constexpr int NB = 4; };
 
+// The beta term of a TR store, loaded ahead (ge_preload) so that its latency
+// overlaps the last slab's products; ok is set once the loads are issued.
+template <typename T> struct GePre {
+  typename V4<T>::type re[8], im[8];  // laid out like an accumulator
+  bool ok;
+};
+template <typename T>
+__device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Out<T>& o) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int i = 16 * w + lr;
+  const int ic = (i < m) ? i : 0;
+#pragma unroll
+  for (int bj = 0; bj < 8; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 16 * bj + acc_row<T>(lk, v);
+      const int jc = j < n ? j : 0;
+      const cpx<T> c = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
+      pre.re[bj][v] = c.x;
+      pre.im[bj][v] = c.y;
+    }
+  pre.ok = true;
+}
+
 // Write the accumulator through the store descriptor.  All loads of a batch
 // of column blocks (beta term, divisors) are issued first from clamped
 // addresses, then the results are formed and stored.  With TR the column
 // divisors go through LDS (lds: at least n elements, free after gemm_acc)
 // and every wave of the workgroup must call, since that takes a barrier.
-template <typename T, bool TR>
-__device__ __forceinline__ void gemm_store(const Acc<T, TR>& acc, int m, int n, const Out<T>& o,
-                                           lds_char* lds = nullptr) {
+template <typename T, bool TR, bool PRE = false>
+__device__ __forceinline__ void gemm_store_impl(const Acc<T, TR>& acc, int m, int n, const Out<T>& o, lds_char* lds,
+                                                const GePre<T>* pre) {
   constexpr int NBB = GeStoreBatch<T>::NB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -540,13 +585,25 @@ __device__ __forceinline__ void gemm_store(const Acc<T, TR>& acc, int m, int n, 
     for (int bt = 0; bt < 8 / NBB; ++bt) {
       if (16 * NBB * bt >= n) break;
       cpx<T> src[NBB][4];
+      bool have = false;
+      if constexpr (PRE) have = pre->ok;
+      if (have) {
 #pragma unroll
-      for (int b4 = 0; b4 < NBB; ++b4) {
+        for (int b4 = 0; b4 < NBB; ++b4)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int j = 16 * (NBB * bt + b4) + acc_row<T>(lk, v);
-          const int jc = j < n ? j : 0;
-          if (o.src) src[b4][v] = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
+          for (int v = 0; v < 4; ++v) {
+            src[b4][v].x = pre->re[NBB * bt + b4][v];
+            src[b4][v].y = pre->im[NBB * bt + b4][v];
+          }
+      } else {
+#pragma unroll
+        for (int b4 = 0; b4 < NBB; ++b4) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = 16 * (NBB * bt + b4) + acc_row<T>(lk, v);
+            const int jc = j < n ? j : 0;
+            if (o.src) src[b4][v] = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
+          }
         }
       }
 #pragma unroll
@@ -621,6 +678,18 @@ __device__ __forceinline__ void gemm_store(const Acc<T, TR>& acc, int m, int n, 
       }
     }
   }
+}
+
+template <typename T, bool TR>
+__device__ __forceinline__ void gemm_store(const Acc<T, TR>& acc, int m, int n, const Out<T>& o,
+                                           lds_char* lds = nullptr) {
+  gemm_store_impl<T, TR, false>(acc, m, n, o, lds, nullptr);
+}
+// the same with the beta term possibly loaded ahead into pre (TR only)
+template <typename T, bool TR>
+__device__ __forceinline__ void gemm_store(const Acc<T, TR>& acc, int m, int n, const Out<T>& o, lds_char* lds,
+                                           const GePre<T>& pre) {
+  gemm_store_impl<T, TR, true>(acc, m, n, o, lds, &pre);
 }
 
 }  // namespace d3m
