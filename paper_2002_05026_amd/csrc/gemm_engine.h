@@ -440,14 +440,16 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
 #pragma unroll
       for (int q = 0; q < NB - 1; ++q)
         if (q * KD < k) ge_dma<T, KD>(A, B, m, n, k, q * KD, buf0 + q * SL);
-      if (NB > 2 && KD < k) ge_wait_vm<NW * (NB - 2)>();
+      // slab 1 may stay in flight only if it is full: a wave issues no load
+      // for an instruction wholly beyond k, so a partial slab may count less
+      if (NB > 2 && 2 * KD <= k) ge_wait_vm<NW * (NB - 2)>();
       else ge_wait_vm<0>();
       __syncthreads();
       auto step = [&](int s, int p0) __attribute__((always_inline)) {
         const bool more = p0 + (NB - 1) * KD < k;
         if (more) ge_dma<T, KD>(A, B, m, n, k, p0 + (NB - 1) * KD, buf0 + ((s + NB - 1) % NB) * SL);
         mma(buf0 + (s % NB) * SL, p0, kdc());
-        if (more && NB > 2) ge_wait_vm<NW * (NB - 2)>();
+        if (more && NB > 2 && p0 + NB * KD <= k) ge_wait_vm<NW * (NB - 2)>();
         else ge_wait_vm<0>();
         __syncthreads();
       };
