@@ -109,8 +109,6 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
   const Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1);
-  // complex64: the target's loads go out with the last slab of the last
-  // source (registers allow it; complex128 loads it after the product)
   GePre<T> pre;
   pre.ok = false;
   auto src = [&](int q) {
@@ -118,14 +116,39 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
     if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
     return x;
   };
-  for (int q = 0; q < nsrc - 1; ++q) {
-    const XSrc x = src(q);
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
-                                        opn<T>(cx.L + x.b_off, x.lda), cx.lds);
+  bool done = false;
+  if constexpr (sizeof(T) == 4) {
+    // complex64: the sources go to LDS above the slab buffers, then one
+    // direct-load pipeline runs over the slabs of all of them; the target's
+    // loads go out with the last slab
+    D3M_LDS GeSrc<T>* tab = reinterpret_cast<D3M_LDS GeSrc<T>*>(cx.lds + ge_lds_bytes_dma<T>());
+    if ((int)threadIdx.x < nsrc) {
+      const XSrc x = src(threadIdx.x);
+      GeSrc<T> e;
+      e.a = cx.LD + x.a_off;
+      e.b = cx.L + x.b_off;
+      e.lda = e.ldb = x.lda;
+      e.k = x.k;
+      e.pad = 0;
+      ge_src_put(tab, (int)threadIdx.x, e);
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int q = 0; q < nsrc; ++q) {
+      const GeSrc<T> e = ge_src_lds(tab, q);
+      ok = ok && ((((uintptr_t)e.a | (uintptr_t)e.b) & 15) == 0) && (((e.lda | e.ldb) & 1) == 0);
+    }
+    if (ok) {
+      ge_pipe<T, 8, true, true>(acc, t.m, t.n, nsrc, [&](int q) { return ge_src_lds(tab, q); }, cx.lds, &pre, &o);
+      done = true;
+    }
   }
-  const XSrc x = src(nsrc - 1);
-  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, sizeof(T) == 4>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda),
-                                                      nullptr, opn<T>(cx.L + x.b_off, x.lda), cx.lds, &pre, &o);
+  if (!done)
+    for (int q = 0; q < nsrc; ++q) {
+      const XSrc x = src(q);
+      gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
+                                          opn<T>(cx.L + x.b_off, x.lda), cx.lds);
+    }
   gemm_store<T>(acc, t.m, t.n, o, nullptr, pre);
 }
 

@@ -346,14 +346,16 @@ template <int N> __device__ __forceinline__ void ge_wait_vm() {
 // operand, or for complex64 the element after an odd last row (inside the
 // operand's allocation): they only reach output rows (columns) beyond the
 // tile, which are never stored.
+// Returns the number of loads this wave issued (wave-uniform).
 template <typename T, int KB>
-__device__ __forceinline__ void ge_dma(const Opnd<T>& A, const Opnd<T>& B, int m, int n, int k, int p0,
-                                       D3M_LDS cpx<T>* buf) {
+__device__ __forceinline__ int ge_dma(const Opnd<T>& A, const Opnd<T>& B, int m, int n, int k, int p0,
+                                      D3M_LDS cpx<T>* buf) {
   constexpr int RPL = 16 / (int)sizeof(cpx<T>);    // rows per lane
   constexpr int NCI = GE_TM / (64 * RPL);           // instructions per column
   constexpr int NW = ge_dma_per_wave<T, KB>();
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int cnt = 0;
 #pragma unroll
   for (int q = 0; q < NW; ++q) {
     const int g = w + 8 * q;  // instruction index: operand, column, part of the column
@@ -368,11 +370,61 @@ __device__ __forceinline__ void ge_dma(const Opnd<T>& A, const Opnd<T>& B, int m
       int r = h * 64 * RPL + lane * RPL;
       if (r >= rows) r = 0;
       __builtin_amdgcn_global_load_lds((const void*)(xp + r + (int64_t)(p0 + p) * ld), (D3M_LDS void*)dst, 16, 0, 0);
+      ++cnt;
     } else {
 #pragma unroll
       for (int e = 0; e < RPL; ++e) dst[lane * RPL + e] = cpx<T>{0, 0};
     }
   }
+  return cnt;
+}
+
+// Wait until at most n (0..8) vector-memory operations of this wave are in
+// flight (n known only at run time; the instruction takes an immediate).
+__device__ __forceinline__ void ge_wait_vm_n(int n) {
+  switch (n) {
+    case 0: ge_wait_vm<0>(); break;
+    case 1: ge_wait_vm<1>(); break;
+    case 2: ge_wait_vm<2>(); break;
+    case 3: ge_wait_vm<3>(); break;
+    case 4: ge_wait_vm<4>(); break;
+    case 5: ge_wait_vm<5>(); break;
+    case 6: ge_wait_vm<6>(); break;
+    case 7: ge_wait_vm<7>(); break;
+    default: ge_wait_vm<8>(); break;
+  }
+}
+
+// One source of a summed product: A (m x k) and B (n x k), both OP_N.
+template <typename T> struct GeSrc {
+  const typename Cplx<T>::type* a;
+  const typename Cplx<T>::type* b;
+  int64_t lda, ldb;
+  int k, pad;
+};
+// Entry q of a source table in LDS, as wave-uniform values (and the store).
+template <typename T> __device__ __forceinline__ GeSrc<T> ge_src_lds(const D3M_LDS GeSrc<T>* tab, int q) {
+  const D3M_LDS GeSrc<T>& e = tab[q];
+  auto u64 = [](uint64_t v) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+  };
+  GeSrc<T> r;
+  r.a = reinterpret_cast<const typename Cplx<T>::type*>(u64((uint64_t)(uintptr_t)e.a));
+  r.b = reinterpret_cast<const typename Cplx<T>::type*>(u64((uint64_t)(uintptr_t)e.b));
+  r.lda = (int64_t)u64((uint64_t)e.lda);
+  r.ldb = (int64_t)u64((uint64_t)e.ldb);
+  r.k = __builtin_amdgcn_readfirstlane(e.k);
+  r.pad = 0;
+  return r;
+}
+template <typename T> __device__ __forceinline__ void ge_src_put(D3M_LDS GeSrc<T>* tab, int q, const GeSrc<T>& e) {
+  tab[q].a = e.a;
+  tab[q].b = e.b;
+  tab[q].lda = e.lda;
+  tab[q].ldb = e.ldb;
+  tab[q].k = e.k;
+  tab[q].pad = 0;
 }
 
 // Whether gemm_acc may load A and B directly into LDS: complex64, both
@@ -383,6 +435,90 @@ template <typename T>
 __device__ __forceinline__ bool ge_dma_ok(const Opnd<T>& A, const typename Cplx<T>::type* dA, const Opnd<T>& B) {
   if (dA != nullptr || sizeof(cpx<T>) != 8) return false;
   return (((uintptr_t)A.p | (uintptr_t)B.p) & 15) == 0 && ((A.ld | B.ld) & 1) == 0;
+}
+
+template <typename T> struct GePre;
+template <typename T> struct Out;
+template <typename T>
+__device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Out<T>& o);
+
+// acc += sum_q A_q B_q^T over nsrc sources (src(q) gives them, wave-uniform),
+// all direct-loadable (ge_dma_ok), as one direct-load pipeline over the slabs
+// of all sources: a source boundary costs no refill.  Three LDS buffers:
+// slab s is multiplied from buffer s % 3 while slab s + 2 loads into buffer
+// (s + 2) % 3; before the barrier that ends step s each wave waits for its
+// own loads of slab s + 1, letting exactly the loads it issued for slab s + 2
+// stay in flight (a slab partly beyond its source's k issues fewer).
+// PRE: the store's beta term goes out at the start of the last slab (the
+// last slab is peeled off so that those values are live only there).
+// Starts and ends with a barrier.
+template <typename T, int NBMAX, bool PRE, bool TR, typename SRC>
+__device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc, const SRC& src, lds_char* lds,
+                                        GePre<T>* pre, const Out<T>* po) {
+  constexpr int KD = GeDma<T>::KB, NB = GeDma<T>::NBUF, SL = 2 * KD * GE_LDP;
+  static_assert(NB == 3, "the wait counts assume three buffers");
+  D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool rowok = 16 * w < m;
+  const int nbj = (n + 15) >> 4;
+  wg_sync_global();
+  int nsl = 0;
+  for (int q = 0; q < nsrc; ++q) {
+    const int kq = src(q).k;
+    if (kq > 0) nsl += (kq + KD - 1) / KD;
+  }
+  if (m <= 0 || n <= 0 || nsl == 0) return;
+  // load and compute cursors: source, first column of the slab, operands
+  int ql = 0, pl = 0, qc = 0, pc = 0;
+  GeSrc<T> el = src(0), ec = el;
+  while (el.k <= 0) el = src(++ql);
+  qc = ql;
+  ec = el;
+  auto issue = [&](int slot) -> int {
+    Opnd<T> A, B;
+    A.p = el.a; A.ld = el.lda; A.mode = OP_N; A.i0 = 0;
+    B.p = el.b; B.ld = el.ldb; B.mode = OP_N; B.i0 = 0;
+    const int c = ge_dma<T, KD>(A, B, m, n, el.k, pl, buf0 + slot * SL);
+    pl += KD;
+    if (pl >= el.k) {
+      pl = 0;
+      do { ++ql; if (ql < nsrc) el = src(ql); } while (ql < nsrc && el.k <= 0);
+    }
+    return c;
+  };
+  auto slab = [&](int s) {
+    if (rowok) {
+      const D3M_LDS cpx<T>* cur = buf0 + (s % NB) * SL;
+      const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
+      const D3M_LDS cpx<T>* bp = cur + KD * GE_LDP + lk * GE_LDP + lr;
+      const int kend = __builtin_amdgcn_readfirstlane(ec.k - pc < KD ? ec.k - pc : KD);
+      if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
+      else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
+      else ge_mma<1>(acc, ap, bp, kend);
+    }
+    pc += KD;
+    if (pc >= ec.k) {
+      pc = 0;
+      do { ++qc; if (qc < nsrc) ec = src(qc); } while (qc < nsrc && ec.k <= 0);
+    }
+  };
+  issue(0);
+  const int c1 = nsl > 1 ? issue(1) : 0;
+  ge_wait_vm_n(c1);
+  __syncthreads();
+  for (int s = 0; s < nsl - (PRE ? 1 : 0); ++s) {
+    const int c2 = s + 2 < nsl ? issue((s + 2) % NB) : 0;
+    slab(s);
+    ge_wait_vm_n(c2);
+    __syncthreads();
+  }
+  if constexpr (PRE) {
+    ge_preload<T>(*pre, m, n, *po);
+    slab(nsl - 1);
+    ge_wait_vm<0>();
+    __syncthreads();
+  }
 }
 
 // acc += A * diag(dA) * B^T over k columns.  Starts and ends with a barrier,
@@ -399,10 +535,6 @@ __device__ __forceinline__ bool ge_dma_ok(const Opnd<T>& A, const typename Cplx<
 // into *pre at the start of the last slab's products, so that its latency
 // overlaps them (pre->ok tells the store).  A flag rather than a null test:
 // a null test of a pointer to a local keeps the local out of registers.
-template <typename T> struct GePre;
-template <typename T> struct Out;
-template <typename T>
-__device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Out<T>& o);
 template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool PRE = false,
           bool TR = false>
 __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
@@ -427,43 +559,14 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
     else ge_mma<1>(acc, ap, bp, kend);
   };
-  if constexpr (DMA && AM == OP_N) {
+  if constexpr (DMA && AM == OP_N && sizeof(cpx<T>) == 8) {
     if (ge_dma_ok<T>(A, dA, B)) {
-      // NB LDS buffers: slab s is multiplied from buffer s % NB while slab
-      // s + NB - 1 loads into buffer (s + NB - 1) % NB; before the barrier
-      // that ends step s each wave waits for its own loads of slab s + 1
-      constexpr int KD = GeDma<T>::KB, NB = GeDma<T>::NBUF;
-      constexpr int SL = 2 * KD * GE_LDP, NW = ge_dma_per_wave<T, KD>();
-      using kdc = std::integral_constant<int, KD>;
-      wg_sync_global();
-      if (k <= 0 || m <= 0 || n <= 0) return;
-#pragma unroll
-      for (int q = 0; q < NB - 1; ++q)
-        if (q * KD < k) ge_dma<T, KD>(A, B, m, n, k, q * KD, buf0 + q * SL);
-      // slab 1 may stay in flight only if it is full: a wave issues no load
-      // for an instruction wholly beyond k, so a partial slab may count less
-      if (NB > 2 && 2 * KD <= k) ge_wait_vm<NW * (NB - 2)>();
-      else ge_wait_vm<0>();
-      __syncthreads();
-      auto step = [&](int s, int p0) __attribute__((always_inline)) {
-        const bool more = p0 + (NB - 1) * KD < k;
-        if (more) ge_dma<T, KD>(A, B, m, n, k, p0 + (NB - 1) * KD, buf0 + ((s + NB - 1) % NB) * SL);
-        mma(buf0 + (s % NB) * SL, p0, kdc());
-        if (more && NB > 2 && p0 + NB * KD <= k) ge_wait_vm<NW * (NB - 2)>();
-        else ge_wait_vm<0>();
-        __syncthreads();
+      auto one = [&](int) {
+        GeSrc<T> e;
+        e.a = A.p; e.b = B.p; e.lda = A.ld; e.ldb = B.ld; e.k = k; e.pad = 0;
+        return e;
       };
-      // with PRE the last slab is peeled off, so that the preloaded values
-      // are live only while it is multiplied
-      const int nsl = (k + KD - 1) / KD;
-      for (int s = 0; s < nsl - (PRE ? 1 : 0); ++s) step(s, s * KD);
-      if constexpr (PRE) {
-        const int s = nsl - 1;
-        ge_preload<T>(*pre, m, n, *po);
-        mma(buf0 + (s % NB) * SL, s * KD, kdc());
-        ge_wait_vm<0>();
-        __syncthreads();
-      }
+      ge_pipe<T, NBMAX, PRE, TR>(acc, m, n, 1, one, lds, pre, po);
       return;
     }
   }
