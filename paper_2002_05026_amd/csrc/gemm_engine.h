@@ -341,12 +341,17 @@ template <int N> __device__ __forceinline__ void ge_wait_vm() {
 // memory into LDS buffer buf, in the slab layout (column p of A at p*LDP,
 // of B at (KB + p)*LDP): each wave instruction moves 16 bytes per lane, a
 // whole 128-row column for complex64 (two rows per lane) or 64 rows for
-// complex128.  Columns at or beyond k are zero-filled instead, so the last
-// k-step adds nothing from them.  Rows beyond m (n) read row 0 of the
+// complex128.  Columns at or beyond k are loaded from ge_zero_bytes, so the
+// last k-step adds nothing from them.  Rows beyond m (n) read row 0 of the
 // operand, or for complex64 the element after an odd last row (inside the
 // operand's allocation): they only reach output rows (columns) beyond the
 // tile, which are never stored.
-// Returns the number of loads this wave issued (wave-uniform).
+// 1 KB of zeros in device memory: the source of slab columns at or beyond k,
+// so that every slab is one uninterrupted series of direct loads (an LDS
+// store between them would have to wait for all loads in flight).
+static __device__ __attribute__((aligned(256))) unsigned char ge_zero_bytes[1024];
+
+// Returns the number of loads this wave issued (wave-uniform; always NW).
 template <typename T, int KB>
 __device__ __forceinline__ int ge_dma(const Opnd<T>& A, const Opnd<T>& B, int m, int n, int k, int p0,
                                       D3M_LDS cpx<T>* buf) {
@@ -366,15 +371,12 @@ __device__ __forceinline__ int ge_dma(const Opnd<T>& A, const Opnd<T>& B, int m,
     const int64_t ld = op ? B.ld : A.ld;
     const int rows = op ? n : m;
     D3M_LDS cpx<T>* dst = buf + (op * KB + p) * GE_LDP + h * 64 * RPL;
-    if (p0 + p < k) {
-      int r = h * 64 * RPL + lane * RPL;
-      if (r >= rows) r = 0;
-      __builtin_amdgcn_global_load_lds((const void*)(xp + r + (int64_t)(p0 + p) * ld), (D3M_LDS void*)dst, 16, 0, 0);
-      ++cnt;
-    } else {
-#pragma unroll
-      for (int e = 0; e < RPL; ++e) dst[lane * RPL + e] = cpx<T>{0, 0};
-    }
+    int r = h * 64 * RPL + lane * RPL;
+    if (r >= rows) r = 0;
+    const void* src = (p0 + p < k) ? (const void*)(xp + r + (int64_t)(p0 + p) * ld)
+                                   : (const void*)(ge_zero_bytes + 16 * lane);
+    __builtin_amdgcn_global_load_lds(src, (D3M_LDS void*)dst, 16, 0, 0);
+    ++cnt;
   }
   return cnt;
 }
@@ -711,10 +713,12 @@ __device__ __forceinline__ void gemm_store_impl(const Acc<T, TR>& acc, int m, in
           }
         }
       }
+      // all results first, then all stores: a use of a loaded value after a
+      // store under a branch would wait for that store too
+      cpx<T> res[NBB][4];
 #pragma unroll
       for (int b4 = 0; b4 < NBB; ++b4) {
         const int bj = NBB * bt + b4;
-        if (16 * bj >= n) break;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int j = 16 * bj + acc_row<T>(lk, v);
@@ -725,11 +729,33 @@ __device__ __forceinline__ void gemm_store_impl(const Acc<T, TR>& acc, int m, in
             r.x += o.beta * src[b4][v].x;
             r.y += o.beta * src[b4][v].y;
           }
-          const bool ok = iok && j < n;
-          if (o.dst2 && ok) gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
           if (o.rowdiv) r = cpx_div(r, rd);
           if (o.coldiv) r = cpx_div(r, cds[j < n ? j : 0]);
-          if (ok) dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+          asm volatile("" : "+v"(r.x), "+v"(r.y));  // formed here, not sunk into the store branches
+          res[b4][v] = r;
+        }
+      }
+#pragma unroll
+      for (int b4 = 0; b4 < NBB; ++b4) {
+        const int bj = NBB * bt + b4;
+        if (16 * bj >= n) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * bj + acc_row<T>(lk, v);
+          if (iok && j < n) {
+            if (o.dst2) {
+              // the value before the divisions
+              cpx<T> r = acc_val(acc, bj, v);
+              r.x *= o.alpha;
+              r.y *= o.alpha;
+              if (o.src) {
+                r.x += o.beta * src[b4][v].x;
+                r.y += o.beta * src[b4][v].y;
+              }
+              gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+            }
+            dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = res[b4][v];
+          }
         }
       }
     }
@@ -760,6 +786,26 @@ __device__ __forceinline__ void gemm_store_impl(const Acc<T, TR>& acc, int m, in
           if (o.src) src[b4][v] = *gptr<T>(o.src + (int64_t)ic * o.srs + (int64_t)jc * o.scs);
         }
       }
+      // all results first, then all stores (see the TR branch)
+      cpx<T> res[NBB][4];
+#pragma unroll
+      for (int b4 = 0; b4 < NBB; ++b4) {
+        const int bj = NBB * bt + b4;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cpx<T> r = acc_val(acc, bj, v);
+          r.x *= o.alpha;
+          r.y *= o.alpha;
+          if (o.src) {
+            r.x += o.beta * src[b4][v].x;
+            r.y += o.beta * src[b4][v].y;
+          }
+          if (o.rowdiv) r = cpx_div(r, rd[v]);
+          if (o.coldiv) r = cpx_div(r, cd[b4]);
+          asm volatile("" : "+v"(r.x), "+v"(r.y));
+          res[b4][v] = r;
+        }
+      }
 #pragma unroll
       for (int b4 = 0; b4 < NBB; ++b4) {
         const int bj = NBB * bt + b4;
@@ -768,17 +814,19 @@ __device__ __forceinline__ void gemm_store_impl(const Acc<T, TR>& acc, int m, in
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = 16 * w + acc_row<T>(lk, v);
-          cpx<T> r = acc_val(acc, bj, v);
-          r.x *= o.alpha;
-          r.y *= o.alpha;
-          if (o.src) {
-            r.x += o.beta * src[b4][v].x;
-            r.y += o.beta * src[b4][v].y;
+          if (i < m && j < n) {
+            if (o.dst2) {
+              cpx<T> r = acc_val(acc, bj, v);
+              r.x *= o.alpha;
+              r.y *= o.alpha;
+              if (o.src) {
+                r.x += o.beta * src[b4][v].x;
+                r.y += o.beta * src[b4][v].y;
+              }
+              gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+            }
+            dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = res[b4][v];
           }
-          if (o.dst2 && i < m && j < n) gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
-          if (o.rowdiv) r = cpx_div(r, rd[v]);
-          if (o.coldiv) r = cpx_div(r, cd[b4]);
-          if (i < m && j < n) dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
         }
       }
     }

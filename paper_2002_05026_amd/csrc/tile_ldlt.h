@@ -6,9 +6,10 @@
 //   for each 16-column block k:
 //     wave 0: unblocked LDL^T of the 16x16 diagonal block in registers (one
 //             row per lane, pivots and multipliers broadcast across lanes)
-//             and, from the same multipliers, the inverse X_k of its unit
-//             lower factor (one column per lane), kept transposed in the
-//             block's free upper triangle
+//             and, from the same multipliers in the same instructions on
+//             other lanes, the inverse X_k of its unit lower factor (one
+//             column per lane), kept transposed in the block's free upper
+//             triangle
 //     waves:  L_ik = A_ik X_k^T D_k^-1 for the blocks below (one block per
 //             wave on the matrix cores)
 //     all:    A_ij -= L_ik D_k L_jk^T on the trailing blocks (one 16x16x16
@@ -91,10 +92,12 @@ template <typename T> __device__ __forceinline__ cpx<T> tl_inv(cpx<T> d) {
   return r;
 }
 
-// v -= a * b
+// v -= a * b (four fused multiply-adds)
 template <typename T> __device__ __forceinline__ void tl_msub(cpx<T>& v, cpx<T> a, cpx<T> b) {
-  v.x -= a.x * b.x - a.y * b.y;
-  v.y -= a.x * b.y + a.y * b.x;
+  v.x = fma(-a.x, b.x, v.x);
+  v.x = fma(a.y, b.y, v.x);
+  v.y = fma(-a.x, b.y, v.y);
+  v.y = fma(-a.y, b.x, v.y);
 }
 
 // Element (i, j), i >= j, of the lower block triangle.
@@ -130,14 +133,17 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
   // lower block triangle from the tile's lower triangle; identity padding.
   // Loads are issued in batches so that their latencies overlap.
   {
-    constexpr int U = 16;
+    constexpr int U = sizeof(cpx<TS>) == 8 ? 32 : 16;  // one batch of loads for a 128-row complex64 tile
     float amax = 0.f;
     for (int j0 = 0; j0 < M; j0 += kColStep * U) {
       cpx<TS> buf[U];
+      // unconditional loads (element 0 stands in outside the lower
+      // triangle): a load under a branch gets a wait for all earlier loads
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + cj + kColStep * u;
-        if (ri < m && j < m && ri >= j) buf[u] = a[ri + (int64_t)j * lda];
+        const bool in = ri < m && j < m && ri >= j;
+        buf[u] = a[in ? ri + (int64_t)j * lda : 0];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -162,41 +168,44 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
   for (int kb = 0; kb < nb; ++kb) {
     const int bkk = tl_blk(kb, kb);
     if (w == 0) {
-      // Lane r holds row r of the diagonal block (ra) and column r of X
-      // (xc).  Step k: pivot d = A(k,k); multipliers L(c,k) = A(c,k)/d come
-      // from lane c; A(r,c) -= A(r,k) L(c,k) and X(c,r) -= L(c,k) X(k,r)
-      // for c > k (X(k,r) is final once step k is reached).
+      // Lanes 0..15 hold row r of the diagonal block, lanes 16..31 column r of
+      // X (lanes 32..63 repeat them and write nothing).  Step k: pivot
+      // d = A(k,k); multipliers L(c,k) = A(c,k)/d come from lane c; then for
+      // c > k one instruction stream does A(r,c) -= A(r,k) L(c,k) on the row
+      // lanes and X(c,r) -= X(k,r) L(c,k) on the column lanes (X(k,r) is
+      // final once step k is reached).
       // (r is made opaque so that the per-lane constants below are not
       // hoisted out of the kb loop into registers held across it)
       int r = lr;
       asm volatile("" : "+v"(r));
-      cpx<T> ra[16], xc[16], dr;
+      const bool xl = (lane & 16) != 0;
+      cpx<T> v[16], dr;
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        ra[c] = S[bkk + c * 16 + r];
-        xc[c].x = (c == r) ? (T)1 : (T)0;
-        xc[c].y = 0;
+        const cpx<T> a = S[bkk + c * 16 + r];
+        v[c].x = xl ? ((c == r) ? (T)1 : (T)0) : a.x;
+        v[c].y = xl ? (T)0 : a.y;
       }
       dr.x = 1;
       dr.y = 0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const cpx<T> d = tl_bcast(ra[k], k);
+        const cpx<T> d = tl_bcast(v[k], k);
         if (r == k) dr = d;
-        const cpx<T> l = tl_mul(ra[k], tl_inv(d));  // L(r,k) for r > k
+        const cpx<T> l = tl_mul(v[k], tl_inv(d));  // L(r,k) on the row lanes, r > k
 #pragma unroll
-        for (int c = k + 1; c < 16; ++c) {
-          const cpx<T> lc = tl_bcast(l, c);
-          tl_msub(ra[c], ra[k], lc);
-          tl_msub(xc[c], lc, xc[k]);
-        }
-        if (r > k) ra[k] = l;
+        for (int c = k + 1; c < 16; ++c) tl_msub(v[c], v[k], tl_bcast(l, c));
+        if (!xl && r > k) v[k] = l;
+      }
+      if (lane < 32) {
+        // row r of the block: L(r,c) left of the diagonal and d_r on it from
+        // the row lanes, X(c,r) to the right (the transposed X) from the
+        // column lanes
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (xl ? (c > r) : (c <= r)) S[bkk + c * 16 + r] = (c == r) ? dr : v[c];
       }
       if (lane < 16) {
-        // row r of the block: L(r,c) left of the diagonal, d_r on it, X(c,r)
-        // to the right (the transposed X)
-#pragma unroll
-        for (int c = 0; c < 16; ++c) S[bkk + c * 16 + r] = (c < r) ? ra[c] : (c == r) ? dr : xc[c];
         dv[kb * 16 + r] = dr;
         if (kb * 16 + r < m) {
           const T ad = sqrt(dr.x * dr.x + dr.y * dr.y);
