@@ -36,6 +36,54 @@ template <typename T> struct Ctx {
   int nrhs;
 };
 
+// Task bodies are separate functions (each gets its own register
+// allocation), and a function's arguments count as per-lane values.  The
+// task and its context are the same for the whole workgroup: these copies
+// say so (readfirstlane), so that everything derived from them is computed
+// once per wave in scalar registers and branches on it are scalar branches.
+__device__ __forceinline__ int32_t ufirst(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t ufirst(int64_t v) {
+  return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)((uint64_t)v >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)v));
+}
+template <typename P> __device__ __forceinline__ P* ufirst_ptr(P* p) {
+  return reinterpret_cast<P*>((uintptr_t)ufirst((int64_t)(uintptr_t)p));
+}
+__device__ __forceinline__ Task uniform_task(const Task& a) {
+  Task t;
+  t.kind = ufirst(a.kind);
+  t.inst = ufirst(a.inst);
+  t.panel = ufirst(a.panel);
+  t.m = ufirst(a.m);
+  t.n = ufirst(a.n);
+  t.k = ufirst(a.k);
+  t.lda = ufirst(a.lda);
+  t.ldc = ufirst(a.ldc);
+  t.dofs = ufirst(a.dofs);
+  t.aux = ufirst(a.aux);
+  t.a_off = ufirst(a.a_off);
+  t.b_off = ufirst(a.b_off);
+  t.c_off = ufirst(a.c_off);
+  t.succ_begin = ufirst(a.succ_begin);
+  t.nsucc = ufirst(a.nsucc);
+  t.pad0 = ufirst(a.pad0);
+  t.pad1 = ufirst(a.pad1);
+  return t;
+}
+template <typename T> __device__ __forceinline__ Ctx<T> uniform_ctx(const Ctx<T>& a) {
+  Ctx<T> c;
+  c.L = ufirst_ptr(a.L);
+  c.LD = ufirst_ptr(a.LD);
+  c.D = ufirst_ptr(a.D);
+  c.Li = ufirst_ptr(a.Li);
+  c.W = ufirst_ptr(a.W);
+  c.Z = ufirst_ptr(a.Z);
+  c.iv = ufirst_ptr(a.iv);
+  c.lds = (lds_char*)(uintptr_t)(uint32_t)ufirst((int32_t)(uint32_t)(uintptr_t)a.lds);
+  c.nrhs = ufirst(a.nrhs);
+  return c;
+}
+
 template <typename T>
 __device__ __forceinline__ Opnd<T> opn(const typename Cplx<T>::type* p, int64_t ld, int mode = OP_N, int i0 = 0) {
   Opnd<T> o;
@@ -68,7 +116,9 @@ __device__ __forceinline__ Out<T> outp(typename Cplx<T>::type* dst, int64_t rs, 
 // in FP64 from the same (Schur-complemented) tile and stored rounded to
 // complex64.
 template <typename T>
-__device__ __noinline__ void task_fact(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_fact(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   const Tile tc = cx.iv->tiles[t.aux];
   float* gr = cx.iv->growth ? cx.iv->growth + 2 * t.panel : nullptr;
   const Panel P = cx.iv->panels[t.panel];
@@ -89,7 +139,9 @@ __device__ __noinline__ void task_fact(const Ctx<T>& cx, const Task& t) {
 // L_rc = A_rc Linv_c^T D_c^-1, in place, and L_rc D_c = A_rc Linv_c^T into
 // LD at the same place (TK_TRSM)
 template <typename T>
-__device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_trsm(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   Acc<T, true> acc;
   acc.zero();
   gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
@@ -104,7 +156,9 @@ __device__ __noinline__ void task_trsm(const Ctx<T>& cx, const Task& t) {
 // (TK_XUPD); t.pad0 > 1: the sources are xsrc[t.pad1 ...], else the task's
 // own operands
 template <typename T>
-__device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   Acc<T, true> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
@@ -156,7 +210,9 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx, const Task& t) {
 // Y^T = (sum_{c <= q < r} L_rq Linv_qc)^T into the unused upper tile (c, r),
 // then Linv_rc = -Linv_rr Y (TK_INV)
 template <typename T>
-__device__ __noinline__ void task_inv(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_inv(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   const Panel P = cx.iv->panels[t.panel];
   const Tile tr = cx.iv->tiles[t.aux], tc = cx.iv->tiles[t.dofs];
   typedef typename Cplx<T>::type C;
@@ -322,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
       }
     }
     __syncthreads();
-    const int t = s_ticket;
+    const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: the task is read with scalar loads
     if (t < 0) break;
     const Task task = a.tasks[t];
     run_task<T>(task, a.inst, a.nrhs, (lds_char*)lds);
