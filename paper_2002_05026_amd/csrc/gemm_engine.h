@@ -489,15 +489,13 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
     }
     return c;
   };
-  auto slab = [&](int s) {
+  auto slab = [&](int s, auto nbjc) {
     if (rowok) {
       const D3M_LDS cpx<T>* cur = buf0 + (s % NB) * SL;
       const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
       const D3M_LDS cpx<T>* bp = cur + KD * GE_LDP + lk * GE_LDP + lr;
       const int kend = __builtin_amdgcn_readfirstlane(ec.k - pc < KD ? ec.k - pc : KD);
-      if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
-      else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
-      else ge_mma<1>(acc, ap, bp, kend);
+      ge_mma<decltype(nbjc)::value>(acc, ap, bp, kend);
     }
     pc += KD;
     if (pc >= ec.k) {
@@ -509,18 +507,24 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
   const int c1 = nsl > 1 ? issue(1) : 0;
   ge_wait_vm_n(c1);
   __syncthreads();
-  for (int s = 0; s < nsl - (PRE ? 1 : 0); ++s) {
-    const int c2 = s + 2 < nsl ? issue((s + 2) % NB) : 0;
-    slab(s);
-    ge_wait_vm_n(c2);
-    __syncthreads();
-  }
-  if constexpr (PRE) {
-    ge_preload<T>(*pre, m, n, *po);
-    slab(nsl - 1);
-    ge_wait_vm<0>();
-    __syncthreads();
-  }
+  // one copy of the loop per accumulator width (no width switch inside it)
+  auto run = [&](auto nbjc) {
+    for (int s = 0; s < nsl - (PRE ? 1 : 0); ++s) {
+      const int c2 = s + 2 < nsl ? issue((s + 2) % NB) : 0;
+      slab(s, nbjc);
+      ge_wait_vm_n(c2);
+      __syncthreads();
+    }
+    if constexpr (PRE) {
+      ge_preload<T>(*pre, m, n, *po);
+      slab(nsl - 1, nbjc);
+      ge_wait_vm<0>();
+      __syncthreads();
+    }
+  };
+  if (NBMAX > 4 && nbj > 4) run(std::integral_constant<int, (NBMAX > 4 ? 8 : 1)>());
+  else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
+  else run(std::integral_constant<int, 1>());
 }
 
 // acc += A * diag(dA) * B^T over k columns.  Starts and ends with a barrier,
@@ -551,15 +555,16 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
   // one LDS slab of KBX columns into the accumulator; three widths only
   // (more variants make the allocator copy the accumulator); LDS columns
   // beyond n hold zeros or columns of B that only reach discarded outputs
-  auto mma = [&](const D3M_LDS cpx<T>* cur, int p0, auto kbx) {
-    constexpr int KBX = decltype(kbx)::value;
+  // (NBJ is fixed for a whole call, below: one copy of the slab loop per
+  // accumulator width, so that the allocator keeps the accumulator in place
+  // instead of copying it around a width switch inside the loop)
+  auto mma = [&](const D3M_LDS cpx<T>* cur, int p0, auto kbx, auto nbjc) {
+    constexpr int KBX = decltype(kbx)::value, NBJ = decltype(nbjc)::value;
     if (!rowok) return;
     const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
     const D3M_LDS cpx<T>* bp = cur + KBX * GE_LDP + lk * GE_LDP + lr;
     const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KBX ? k - p0 : KBX);
-    if (NBMAX > 4 && nbj > 4) ge_mma<(NBMAX > 4 ? 8 : 1)>(acc, ap, bp, kend);
-    else if (NBMAX > 1 && nbj > 1) ge_mma<(NBMAX > 1 ? 4 : 1)>(acc, ap, bp, kend);
-    else ge_mma<1>(acc, ap, bp, kend);
+    ge_mma<NBJ>(acc, ap, bp, kend);
   };
   if constexpr (DMA && AM == OP_N && sizeof(cpx<T>) == 8) {
     if (ge_dma_ok<T>(A, dA, B)) {
@@ -576,6 +581,7 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
   const bool scaled = dA != nullptr;
   wg_sync_global();
   if (k <= 0 || m <= 0 || n <= 0) return;
+  auto run = [&](auto nbjc) {
   if constexpr (sizeof(cpx<T>) == 8) {
     // complex64: slab s lives in LDS buffer s & 1; while slab s is
     // multiplied, slab s+1 is written to the other buffer and slab s+3 is
@@ -588,14 +594,14 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     if (2 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 2 * KB);
     __syncthreads();
     for (int p0 = 0; p0 < k; p0 += 2 * KB) {
-      mma(buf0, p0, kbc());
+      mma(buf0, p0, kbc(), nbjc);
       if (p0 + KB < k) {
         ge_stash<T, KB, AM>(sb, A.mode, scaled, buf1, buf1 + KB * GE_LDP);
         if (p0 + 3 * KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, p0 + 3 * KB);
       }
       __syncthreads();
       if (p0 + KB >= k) break;
-      mma(buf1, p0 + KB, kbc());
+      mma(buf1, p0 + KB, kbc(), nbjc);
       if (p0 + 2 * KB < k) {
         ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
         if (p0 + 4 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, p0 + 4 * KB);
@@ -615,7 +621,7 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     for (int p0 = 0; p0 < k; p0 += KB, ++s) {
       D3M_LDS cpx<T>* cur = (s & 1) ? buf1 : buf0;
       D3M_LDS cpx<T>* nxt = (s & 1) ? buf0 : buf1;
-      mma(cur, p0, kbc());
+      mma(cur, p0, kbc(), nbjc);
       if (p0 + KB < k) {
         ge_stash<T, KB, AM>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
         if (p0 + 2 * KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
@@ -623,6 +629,10 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
       __syncthreads();
     }
   }
+  };
+  if (NBMAX > 4 && nbj > 4) run(std::integral_constant<int, (NBMAX > 4 ? 8 : 1)>());
+  else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
+  else run(std::integral_constant<int, 1>());
 }
 
 template <typename T> __device__ __forceinline__ cpx<T> cpx_div(cpx<T> a, cpx<T> b) {
