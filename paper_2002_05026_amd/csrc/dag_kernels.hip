@@ -234,7 +234,9 @@ __device__ __noinline__ void task_inv(const Ctx<T>& cx_, const Task& t_) {
 
 // forward, one tile: z_c = D_c^-1 sum_{p < r0_c + sz_c} Linv_II(c, p) b_p
 template <typename T>
-__device__ __noinline__ void task_ftile(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
@@ -268,7 +270,9 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
 
 // b_r += the t.k extra accumulators of tile r (N rows apart) (TK_RED)
 template <typename T>
-__device__ __noinline__ void task_red(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   const int64_t nr = cx.nrhs, stride = cx.iv->N * nr;
   D3M_GLB cpx<T>* w = gptr_mut<T>(cx.W + t.c_off * nr);
   const int64_t tot = (int64_t)t.m * nr;
@@ -285,7 +289,9 @@ __device__ __noinline__ void task_red(const Ctx<T>& cx, const Task& t) {
 
 // backward push: t_c(I) -= L_Jc^T x_J for one row block J of panel I
 template <typename T>
-__device__ __noinline__ void task_bupd(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_bupd(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
@@ -297,7 +303,9 @@ __device__ __noinline__ void task_bupd(const Ctx<T>& cx, const Task& t) {
 
 // backward, one tile: x_c = sum_{p >= r0_c} Linv_II(p, c) t_p
 template <typename T>
-__device__ __noinline__ void task_btile(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
