@@ -69,22 +69,40 @@ __global__ __launch_bounds__(256) void k_scatter(const double2* K, typename Cplx
         }
       }
     } else if (!P.trans) {
-      for (int cc = ty; cc < 32; cc += 8) {
-        int r = r0 + tx, c = c0 + cc;
+      // the four loads of a thread go out together (unconditional, from a
+      // valid address outside the block), then the stores
+      double2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + tx, c = c0 + ty + 8 * q;
+        const bool in = r < P.rows && c < P.cols;
+        v[q] = K[P.src + (in ? r + (int64_t)c * P.rows : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + tx, c = c0 + ty + 8 * q;
         if (r < P.rows && c < P.cols) {
-          double2 v = K[P.src + r + (int64_t)c * P.rows];
           C o;
-          o.x = (T)v.x;
-          o.y = (T)v.y;
+          o.x = (T)v[q].x;
+          o.y = (T)v[q].y;
           L[P.dst + r + (int64_t)c * P.ld_dst] = o;
         }
       }
     } else {
       // dst(r, c) = src[c + r * cols]: read src rows c contiguous
       __syncthreads();
-      for (int rr = ty; rr < 32; rr += 8) {
-        int r = r0 + rr, c = c0 + tx;
-        if (r < P.rows && c < P.cols) tileb[rr][tx] = K[P.src + c + (int64_t)r * P.cols];
+      double2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + ty + 8 * q, c = c0 + tx;
+        const bool in = r < P.rows && c < P.cols;
+        v[q] = K[P.src + (in ? c + (int64_t)r * P.cols : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        asm volatile("" : "+v"(v[q].x), "+v"(v[q].y));  // keeps the loads together, not sunk into the branches
+        const int rr = ty + 8 * q;
+        if (r0 + rr < P.rows && c0 + tx < P.cols) tileb[rr][tx] = v[q];
       }
       __syncthreads();
       for (int cc = ty; cc < 32; cc += 8) {
@@ -274,6 +292,25 @@ __global__ __launch_bounds__(512) void k_knorm(const double2* K, UserView uv, co
   const int I = t.I, nI = uv.n[I];
   __shared__ double part[5][kTileMax];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // s += |K[base + p * stride]| for p = p0, p0 + step, .. < pend, in that
+  // order; eight loads go out together (from a valid address past pend)
+  // and the terms past pend add zero, so the loads stay unconditional
+  auto sum = [&](double& s, int64_t base, int64_t stride, int p0, int pend, int step) {
+    constexpr int U = 8;
+    for (int q = p0; q < pend; q += U * step) {
+      double2 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int p = q + u * step;
+        v[u] = K[base + (int64_t)(p < pend ? p : p0) * stride];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double a = sqrt(v[u].x * v[u].x + v[u].y * v[u].y);
+        s += (q + u * step < pend) ? a : 0.0;
+      }
+    }
+  };
   // lanes over rows: thread (row i, group g) sums the columns p = g mod 4
   {
     const int i = tid & (kTileMax - 1), g = tid >> 7;
@@ -284,10 +321,7 @@ __global__ __launch_bounds__(512) void k_knorm(const double2* K, UserView uv, co
         const RBlkDev b = uv.rblk[e];
         if (b.mode == 2) continue;
         const int pend = b.mode == 0 ? gi + 1 : uv.n[b.J];
-        for (int p = g; p < pend; p += 4) {
-          const double2 v = K[b.koff + gi + (int64_t)p * nI];
-          s += sqrt(v.x * v.x + v.y * v.y);
-        }
+        sum(s, b.koff + gi, nI, g, pend, 4);
       }
     }
     part[g][i] = s;
@@ -301,15 +335,9 @@ __global__ __launch_bounds__(512) void k_knorm(const double2* K, UserView uv, co
       if (b.mode == 1) continue;
       if (b.mode == 2) {
         const int nJ = uv.n[b.J];
-        for (int p = lane; p < nJ; p += 64) {
-          const double2 v = K[b.koff + p + (int64_t)gi * nJ];
-          s += sqrt(v.x * v.x + v.y * v.y);
-        }
+        sum(s, b.koff + (int64_t)gi * nJ, 1, lane, nJ, 64);
       } else {
-        for (int p = gi + 1 + lane; p < nI; p += 64) {  // (gi, p) above the diagonal = (p, gi)
-          const double2 v = K[b.koff + p + (int64_t)gi * nI];
-          s += sqrt(v.x * v.x + v.y * v.y);
-        }
+        sum(s, b.koff + (int64_t)gi * nI, 1, gi + 1 + lane, nI, 64);  // (gi, p) above the diagonal = (p, gi)
       }
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
