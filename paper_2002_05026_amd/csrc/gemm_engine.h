@@ -337,49 +337,19 @@ template <int N> __device__ __forceinline__ void ge_wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
 }
 
-// One slab (A and B, both OP_N, KB columns from p0) straight from global
-// memory into LDS buffer buf, in the slab layout (column p of A at p*LDP,
-// of B at (KB + p)*LDP): each wave instruction moves 16 bytes per lane, a
-// whole 128-row column for complex64 (two rows per lane) or 64 rows for
-// complex128.  Columns at or beyond k are loaded from ge_zero_bytes, so the
-// last k-step adds nothing from them.  Rows beyond m (n) read row 0 of the
-// operand, or for complex64 the element after an odd last row (inside the
-// operand's allocation): they only reach output rows (columns) beyond the
-// tile, which are never stored.
+// Slab layout of the direct-load path (ge_pipe): a slab of KB columns of A
+// and B (both OP_N) goes straight from global memory into an LDS buffer,
+// column p of A at p*LDP and of B at (KB + p)*LDP; each wave instruction
+// moves 16 bytes per lane, a whole 128-row complex64 column (two rows per
+// lane).  Columns at or beyond k are loaded from ge_zero_bytes, so the last
+// k-step adds nothing from them.  Rows beyond m (n) read row 0 of the
+// operand, or the element after an odd last row (inside the operand's
+// allocation): they only reach output rows (columns) beyond the tile, which
+// are never stored.
 // 1 KB of zeros in device memory: the source of slab columns at or beyond k,
 // so that every slab is one uninterrupted series of direct loads (an LDS
 // store between them would have to wait for all loads in flight).
 static __device__ __attribute__((aligned(256))) unsigned char ge_zero_bytes[1024];
-
-// Returns the number of loads this wave issued (wave-uniform; always NW).
-template <typename T, int KB>
-__device__ __forceinline__ int ge_dma(const Opnd<T>& A, const Opnd<T>& B, int m, int n, int k, int p0,
-                                      D3M_LDS cpx<T>* buf) {
-  constexpr int RPL = 16 / (int)sizeof(cpx<T>);    // rows per lane
-  constexpr int NCI = GE_TM / (64 * RPL);           // instructions per column
-  constexpr int NW = ge_dma_per_wave<T, KB>();
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int cnt = 0;
-#pragma unroll
-  for (int q = 0; q < NW; ++q) {
-    const int g = w + 8 * q;  // instruction index: operand, column, part of the column
-    const int op = g / (KB * NCI);
-    const int rem = g - op * KB * NCI;
-    const int p = rem / NCI, h = rem - p * NCI;
-    const typename Cplx<T>::type* xp = op ? B.p : A.p;
-    const int64_t ld = op ? B.ld : A.ld;
-    const int rows = op ? n : m;
-    D3M_LDS cpx<T>* dst = buf + (op * KB + p) * GE_LDP + h * 64 * RPL;
-    int r = h * 64 * RPL + lane * RPL;
-    if (r >= rows) r = 0;
-    const void* src = (p0 + p < k) ? (const void*)(xp + r + (int64_t)(p0 + p) * ld)
-                                   : (const void*)(ge_zero_bytes + 16 * lane);
-    __builtin_amdgcn_global_load_lds(src, (D3M_LDS void*)dst, 16, 0, 0);
-    ++cnt;
-  }
-  return cnt;
-}
 
 // Wait until at most n (0..8) vector-memory operations of this wave are in
 // flight (n known only at run time; the instruction takes an immediate).
@@ -477,17 +447,48 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
   while (el.k <= 0) el = src(++ql);
   qc = ql;
   ec = el;
+  // Direct loads of the load cursor's slab (the slab layout above): wave
+  // instruction q moves column cq[q] of operand opq[q] (A or B), 16 bytes
+  // (two rows) per lane.  The per-lane addresses are formed once per source
+  // and advance by a whole slab per slab, so a slab costs one add per load;
+  // only a source's last, partial slab selects ge_zero_bytes for columns
+  // beyond its k.
+  static_assert(sizeof(cpx<T>) == 8 && GE_TM == 128, "complex64, one instruction per column");
+  constexpr int NW = ge_dma_per_wave<T, KD>();
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const typename Cplx<T>::type* gp[NW];  // column cq[q] of the current slab, this lane's rows
+  int64_t gstep[NW];                      // elements per slab
+  auto src_start = [&]() {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const int g = wq + 8 * q, op = g / KD, cq = g - op * KD;
+      const typename Cplx<T>::type* xp = op ? el.b : el.a;
+      const int64_t ld = op ? el.ldb : el.lda;
+      int r = 2 * lane;
+      if (r >= (op ? n : m)) r = 0;
+      gp[q] = xp + r + (int64_t)cq * ld;
+      gstep[q] = (int64_t)KD * ld;
+    }
+  };
+  src_start();
   auto issue = [&](int slot) -> int {
-    Opnd<T> A, B;
-    A.p = el.a; A.ld = el.lda; A.mode = OP_N; A.i0 = 0;
-    B.p = el.b; B.ld = el.ldb; B.mode = OP_N; B.i0 = 0;
-    const int c = ge_dma<T, KD>(A, B, m, n, el.k, pl, buf0 + slot * SL);
+    D3M_LDS cpx<T>* bs = buf0 + slot * SL;
+    const bool full = pl + KD <= el.k;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const int g = wq + 8 * q, op = g / KD, cq = g - op * KD;
+      D3M_LDS cpx<T>* dst = bs + (op * KD + cq) * GE_LDP;
+      const void* a = (full || pl + cq < el.k) ? (const void*)gp[q] : (const void*)(ge_zero_bytes + 16 * lane);
+      __builtin_amdgcn_global_load_lds(a, (D3M_LDS void*)dst, 16, 0, 0);
+      gp[q] += gstep[q];
+    }
     pl += KD;
     if (pl >= el.k) {
       pl = 0;
       do { ++ql; if (ql < nsrc) el = src(ql); } while (ql < nsrc && el.k <= 0);
+      if (ql < nsrc) src_start();
     }
-    return c;
+    return NW;
   };
   auto slab = [&](int s, auto nbjc) {
     if (rowok) {
