@@ -298,18 +298,47 @@ __device__ __forceinline__ void ge_mma(Acc<double, TR>& acc, const D3M_LDS cpx<d
 template <int NBJ, bool TR>
 __device__ __forceinline__ void ge_mma(Acc<float, TR>& acc, const D3M_LDS cpx<float>* ap,
                                        const D3M_LDS cpx<float>* bp, int kend) {
+  if constexpr (NBJ <= 4) {
+    // narrow accumulators (tiles of at most 64 columns, e.g. the solve's
+    // right-hand sides) mostly run one wave per SIMD, which has no second
+    // wave to cover the fragment reads: the reads of the next k-step go out
+    // before the products of this one
+    if (kend <= 0) return;
+    cpx<float> a0 = ap[0], b[NBJ];
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj) b[bj] = bp[16 * bj];
 #pragma unroll 1
-  for (int kk = 0; kk < kend; kk += 4) {
-    const cpx<float> a0 = ap[kk * GE_LDP];
-    cpx<float> b[NBJ];
+    for (int kk = 0; kk < kend; kk += 4) {
+      const int kn = kk + 4 < kend ? kk + 4 : kk;  // last step: a harmless re-read
+      const cpx<float> a1 = ap[kn * GE_LDP];
+      cpx<float> b1[NBJ];
 #pragma unroll
-    for (int bj = 0; bj < NBJ; ++bj) b[bj] = bp[kk * GE_LDP + 16 * bj];
-    const float as = a0.x + a0.y;
+      for (int bj = 0; bj < NBJ; ++bj) b1[bj] = bp[kn * GE_LDP + 16 * bj];
+      const float as = a0.x + a0.y;
 #pragma unroll
-    for (int bj = 0; bj < NBJ; ++bj) {
-      acc.p1[bj] = mfma_or<TR>(a0.x, b[bj].x, acc.p1[bj]);
-      acc.p2[bj] = mfma_or<TR>(a0.y, b[bj].y, acc.p2[bj]);
-      acc.p3[bj] = mfma_or<TR>(as, b[bj].x + b[bj].y, acc.p3[bj]);
+      for (int bj = 0; bj < NBJ; ++bj) {
+        acc.p1[bj] = mfma_or<TR>(a0.x, b[bj].x, acc.p1[bj]);
+        acc.p2[bj] = mfma_or<TR>(a0.y, b[bj].y, acc.p2[bj]);
+        acc.p3[bj] = mfma_or<TR>(as, b[bj].x + b[bj].y, acc.p3[bj]);
+      }
+      a0 = a1;
+#pragma unroll
+      for (int bj = 0; bj < NBJ; ++bj) b[bj] = b1[bj];
+    }
+  } else {
+#pragma unroll 1
+    for (int kk = 0; kk < kend; kk += 4) {
+      const cpx<float> a0 = ap[kk * GE_LDP];
+      cpx<float> b[NBJ];
+#pragma unroll
+      for (int bj = 0; bj < NBJ; ++bj) b[bj] = bp[kk * GE_LDP + 16 * bj];
+      const float as = a0.x + a0.y;
+#pragma unroll
+      for (int bj = 0; bj < NBJ; ++bj) {
+        acc.p1[bj] = mfma_or<TR>(a0.x, b[bj].x, acc.p1[bj]);
+        acc.p2[bj] = mfma_or<TR>(a0.y, b[bj].y, acc.p2[bj]);
+        acc.p3[bj] = mfma_or<TR>(as, b[bj].x + b[bj].y, acc.p3[bj]);
+      }
     }
   }
 }
