@@ -18,8 +18,8 @@
 // then L (strictly below the diagonal) and D (on it) go back to the tile in
 // global memory, and the full inverse Linv = L^-1 (m x m, column-major with
 // leading dimension ldl, zeros above the diagonal) is formed in place of L in
-// LDS, one block column at a time from the right (Linv L = I):
-//   Linv_ij = -(sum_{j < q <= i} Linv_iq L_qj) X_j,
+// LDS by recursive doubling over 16-block super-blocks,
+//   [A 0; C D]^-1 = [A^-1 0; -D^-1 C A^-1  D^-1],
 // and then written out.  Rows/columns beyond m are padded with the identity.
 #pragma once
 #include "gemm_engine.h"
@@ -45,12 +45,14 @@ __device__ __forceinline__ cpx<T> tl_mul(cpx<T> a, cpx<T> b) {
 
 // X_b(i, k) of the inverse of diagonal block b: 1 on the diagonal, stored
 // transposed in the upper triangle, zero above.
+// The element is read unconditionally (from inside the block) and selected,
+// so that reads of several k-steps can be issued together.
 template <typename T>
 __device__ __forceinline__ cpx<T> tl_x(const D3M_LDS cpx<T>* S, int b, int i, int k) {
+  const cpx<T> e = S[tl_blk(b, b) + max(i, k) * 16 + min(i, k)];  // element (row k, col i) holds X(i, k), i > k
   cpx<T> v;
-  if (i == k) { v.x = 1; v.y = 0; }
-  else if (i > k) v = S[tl_blk(b, b) + i * 16 + k];  // element (row k, col i) holds X(i, k)
-  else { v.x = 0; v.y = 0; }
+  v.x = (i > k) ? e.x : ((i == k) ? (T)1 : (T)0);
+  v.y = (i > k) ? e.y : (T)0;
   return v;
 }
 
@@ -84,11 +86,15 @@ template <typename T> __device__ __forceinline__ cpx<T> tl_bcast(cpx<T> v, int l
   return r;
 }
 
+// 1/d through one reciprocal of |d|^2: the hardware reciprocal (within one
+// ulp) in FP32, a correctly rounded division in FP64.
+__device__ __forceinline__ float tl_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double tl_rcp(double x) { return 1.0 / x; }
 template <typename T> __device__ __forceinline__ cpx<T> tl_inv(cpx<T> d) {
-  const T den = d.x * d.x + d.y * d.y;
+  const T s = tl_rcp(d.x * d.x + d.y * d.y);
   cpx<T> r;
-  r.x = d.x / den;
-  r.y = -d.y / den;
+  r.x = d.x * s;
+  r.y = -d.y * s;
   return r;
 }
 
@@ -134,7 +140,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
   // Loads are issued in batches so that their latencies overlap.
   {
     constexpr int U = sizeof(cpx<TS>) == 8 ? 32 : 16;  // one batch of loads for a 128-row complex64 tile
-    float amax = 0.f;
+    float amax = 0.f;  // max |A|^2 (an overflow to inf only makes the check trip)
     for (int j0 = 0; j0 < M; j0 += kColStep * U) {
       cpx<TS> buf[U];
       // unconditional loads (element 0 stands in outside the lower
@@ -153,7 +159,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
         if (ri < m && j < m) {
           if (ri >= j) {
             v = cvt_cpx<T>(buf[u]);
-            amax = fmaxf(amax, (float)sqrt(v.x * v.x + v.y * v.y));
+            amax = fmaxf(amax, (float)(v.x * v.x + v.y * v.y));
           } else { v.x = 0; v.y = 0; }  // upper part of a diagonal block: scratch
         } else {
           v.x = (ri == j) ? (T)1 : (T)0;
@@ -162,7 +168,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
         S[tl_at<T>(ri, j)] = v;
       }
     }
-    if (gc.on) atomicMax((int*)(flags), __float_as_int(amax));
+    if (gc.on) atomicMax((int*)(flags), __float_as_int(sqrtf(amax)));
   }
   __syncthreads();
   for (int kb = 0; kb < nb; ++kb) {
@@ -283,17 +289,27 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
     }
     __syncthreads();
   }
+  // Element loops over a row's lower triangle: the 64 rows of a wave are
+  // consecutive, so one past the wave's last row bounds the columns of all
+  // its lanes; reads are clamped into the row and issued eight at a time.
+  const int cjs = __builtin_amdgcn_readfirstlane(cj);
+  const int jend = __builtin_amdgcn_readfirstlane(min(m, (ri | 63) + 1));
   if (gc.on) {
-    float lm = 0.f;
+    float lm = 0.f;  // max |L|^2
     bool nf = false;
-    if (ri < m)
-      for (int j = cj; j < ri; j += kColStep) {
-        const cpx<T> v = S[tl_at<T>(ri, j)];
-        const float av = (float)sqrt(v.x * v.x + v.y * v.y);
-        if (!(av <= 3.0e38f)) nf = true;
-        else lm = fmaxf(lm, av);
+    for (int j0 = cjs; j0 < jend; j0 += 8 * kColStep) {
+      cpx<T> e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = S[tl_at<T>(ri, min(j0 + kColStep * u, ri))];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (!(ri < m && j0 + kColStep * u < ri)) continue;
+        const float sq = (float)(e[u].x * e[u].x + e[u].y * e[u].y);
+        if (!(sq <= 3.0e38f)) nf = true;  // not finite (or |l| beyond 1.7e19)
+        else lm = fmaxf(lm, sq);
       }
-    atomicMax((int*)(flags + 2), __float_as_int(lm));
+    }
+    atomicMax((int*)(flags + 2), __float_as_int(sqrtf(lm)));
     if (nf) flags[3] = 1;
     __syncthreads();
     const float fa = __int_as_float(flags[0]), fd = __int_as_float(flags[1]), fl = __int_as_float(flags[2]);
@@ -304,84 +320,133 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
   }
   // L and D back to the tile; D to dout
   {
-    float lmax = 0.f;
-    if (ri < m)
-      for (int j = cj; j <= ri; j += kColStep) {
-        const cpx<T> v = S[tl_at<T>(ri, j)];
-        a[ri + (int64_t)j * lda] = cvt_cpx<TS>(v);
-        if (ri == j) dout[ri] = cvt_cpx<TS>(v);
-        else lmax = fmaxf(lmax, (float)sqrt(v.x * v.x + v.y * v.y));
-      }
-    if (gmax_l) atomicMax(reinterpret_cast<int*>(gmax_l), __float_as_int(lmax));
-  }
-  // Linv in place of L, block column j from the right:
-  //   T = sum_{j < q <= i} Linv_iq L_qj   (Linv_ii = X_i),   Linv_ij = -T X_j
-  // Wave w takes block row i = j + 1 + w.  T replaces L_ij only after every
-  // wave has read column j; the product with X_j reads T back through LDS
-  // to change its register layout.
-  for (int j = nb - 2; j >= 0; --j) {
-    const int bi = j + 1 + w;
-    const bool act = bi < nb;
-    v4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-    if (act) {
-      for (int q = j + 1; q <= bi; ++q) {
-        const int boa = tl_blk(bi, q), bob = tl_blk(q, j);
+    float lmax = 0.f;  // max |L|^2
+    for (int j0 = cjs; j0 < jend; j0 += 8 * kColStep) {
+      cpx<T> e[8];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int kq = kk + lk;
-          const cpx<T> av = (q == bi) ? tl_x(S, bi, lr, kq) : S[boa + kq * 16 + lr];  // Linv_iq(lr, kq)
-          const cpx<T> bv = S[bob + lr * 16 + kq];                                      // L_qj(kq, lr)
-          re = mfma16(av.x, bv.x, re);
-          re = mfma16(-av.y, bv.y, re);
-          im = mfma16(av.x, bv.y, im);
-          im = mfma16(av.y, bv.x, im);
-        }
+      for (int u = 0; u < 8; ++u) e[u] = S[tl_at<T>(ri, min(j0 + kColStep * u, ri))];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + kColStep * u;
+        if (!(ri < m && j <= ri)) continue;
+        a[ri + (int64_t)j * lda] = cvt_cpx<TS>(e[u]);
+        if (ri == j) dout[ri] = cvt_cpx<TS>(e[u]);
+        else lmax = fmaxf(lmax, (float)(e[u].x * e[u].x + e[u].y * e[u].y));
       }
     }
-    __syncthreads();
-    if (act) {
-      const int bo = tl_blk(bi, j);
+    if (gmax_l) atomicMax(reinterpret_cast<int*>(gmax_l), __float_as_int(sqrtf(lmax)));
+  }
+  // Linv in place of L by recursive doubling.  At level s = 1, 2, 4 (in
+  // 16-blocks), pairs of already inverted diagonal super-blocks A = blocks
+  // [a0, a0 + s) and D = [d0, min(d0 + s, nb)), d0 = a0 + s, turn the block
+  // C = L(D, A) below them into Linv(D, A) = -D^-1 C A^-1: first P = C A^-1
+  // (in place of C), then -D^-1 P.  A level has at most 16 output blocks,
+  // two per wave, so the serial depth is three levels of a few block
+  // products each (X_i = Linv_ii, kept transposed in the diagonal blocks).
+  for (int sl = 1; sl < nb; sl *= 2) {
+    const int npair = (nb - sl + 2 * sl - 1) / (2 * sl);  // pairs with d0 < nb
+    const int tot = npair * sl * sl;
+    auto blk = [&](int e, int& i, int& j, int& a0, int& d0) {
+      const int q = e / (sl * sl), r = e - q * sl * sl;
+      a0 = 2 * sl * q;
+      d0 = a0 + sl;
+      i = d0 + r / sl;
+      j = a0 + r % sl;
+      return e < tot && i < nb;
+    };
+    v4 re[2], im[2];
+    // P(i, j) = sum_{j <= q < a0 + s} C(i, q) A^-1(q, j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        cpx<T> t;
-        t.x = re[v];
-        t.y = im[v];
-        S[bo + lr * 16 + acc_row<T>(lk, v)] = t;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // LDS writes done
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      v4 re2 = {0, 0, 0, 0}, im2 = {0, 0, 0, 0};
+    for (int u = 0; u < 2; ++u) {
+      re[u] = v4{0, 0, 0, 0};
+      im[u] = v4{0, 0, 0, 0};
+      int i, j, a0, d0;
+      if (blk(w + 8 * u, i, j, a0, d0))
+        for (int q = j; q < a0 + sl; ++q) {
 #pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const int kq = kk + lk;
-        const cpx<T> av = S[bo + kq * 16 + lr];  // T(lr, kq)
-        const cpx<T> bv = tl_x(S, j, kq, lr);    // X_j(kq, lr)
-        re2 = mfma16(av.x, bv.x, re2);
-        re2 = mfma16(-av.y, bv.y, re2);
-        im2 = mfma16(av.x, bv.y, im2);
-        im2 = mfma16(av.y, bv.x, im2);
-      }
+          for (int kk = 0; kk < 16; kk += 4) {
+            const int kq = kk + lk;
+            const cpx<T> av = S[tl_blk(i, q) + kq * 16 + lr];                              // C(i,q)(lr, kq)
+            const cpx<T> bv = (q == j) ? tl_x(S, j, kq, lr) : S[tl_blk(q, j) + lr * 16 + kq];  // A^-1(q,j)(kq, lr)
+            re[u] = mfma16(av.x, bv.x, re[u]);
+            re[u] = mfma16(-av.y, bv.y, re[u]);
+            im[u] = mfma16(av.x, bv.y, im[u]);
+            im[u] = mfma16(av.y, bv.x, im[u]);
+          }
+        }
+    }
+    __syncthreads();  // every C read
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        cpx<T> t;
-        t.x = -re2[v];
-        t.y = -im2[v];
-        S[bo + lr * 16 + acc_row<T>(lk, v)] = t;
-      }
+    for (int u = 0; u < 2; ++u) {
+      int i, j, a0, d0;
+      if (blk(w + 8 * u, i, j, a0, d0))
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cpx<T> t;
+          t.x = re[u][v];
+          t.y = im[u][v];
+          S[tl_blk(i, j) + lr * 16 + acc_row<T>(lk, v)] = t;
+        }
+    }
+    __syncthreads();  // P in place
+    // Linv(i, j) = -sum_{d0 <= q <= i} D^-1(i, q) P(q, j)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      re[u] = v4{0, 0, 0, 0};
+      im[u] = v4{0, 0, 0, 0};
+      int i, j, a0, d0;
+      if (blk(w + 8 * u, i, j, a0, d0))
+        for (int q = d0; q <= i; ++q) {
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const int kq = kk + lk;
+            const cpx<T> av = (q == i) ? tl_x(S, i, lr, kq) : S[tl_blk(i, q) + kq * 16 + lr];  // D^-1(i,q)(lr, kq)
+            const cpx<T> bv = S[tl_blk(q, j) + lr * 16 + kq];                                  // P(q,j)(kq, lr)
+            re[u] = mfma16(av.x, bv.x, re[u]);
+            re[u] = mfma16(-av.y, bv.y, re[u]);
+            im[u] = mfma16(av.x, bv.y, im[u]);
+            im[u] = mfma16(av.y, bv.x, im[u]);
+          }
+        }
+    }
+    __syncthreads();  // every P read
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int i, j, a0, d0;
+      if (blk(w + 8 * u, i, j, a0, d0))
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cpx<T> t;
+          t.x = -re[u][v];
+          t.y = -im[u][v];
+          S[tl_blk(i, j) + lr * 16 + acc_row<T>(lk, v)] = t;
+        }
     }
     __syncthreads();
   }
   // Linv out: zeros above the block diagonal, X_i on it, the blocks below
-  if (ri < m)
-    for (int j = cj; j < m; j += kColStep) {
+  // (each read at an address inside the lower block triangle, then selected)
+  for (int j0 = cjs; j0 < m; j0 += 8 * kColStep) {
+    cpx<T> e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + kColStep * u, bi = ri >> 4, bj = j >> 4;
+      const int ad = (bi > bj) ? tl_at<T>(ri, j)
+                               : (bi == bj) ? tl_blk(bi, bi) + max(ri & 15, j & 15) * 16 + min(ri & 15, j & 15)
+                                            : tl_at<T>(ri, ri);
+      e[u] = S[ad];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + kColStep * u, bi = ri >> 4, bj = j >> 4;
+      if (!(ri < m && j < m)) continue;
       cpx<T> v;
-      if ((ri >> 4) < (j >> 4)) { v.x = 0; v.y = 0; }
-      else if ((ri >> 4) == (j >> 4)) v = tl_x(S, ri >> 4, ri & 15, j & 15);
-      else v = S[tl_at<T>(ri, j)];
+      const bool keep = bi > bj || (bi == bj && (ri & 15) > (j & 15));
+      v.x = keep ? e[u].x : ((ri == j) ? (T)1 : (T)0);
+      v.y = keep ? e[u].y : (T)0;
       linv[ri + (int64_t)j * ldl] = cvt_cpx<TS>(v);
     }
+  }
   wg_sync_global();
   return false;
 }
