@@ -45,7 +45,8 @@ hipError_t launch_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ct
 
 // ---------------------------------------------------------------- scatter
 // blockIdx.y: block (K placements first, then fill blocks); 32x32 tiles of
-// the block are spread over blockIdx.x.  Transposed blocks go through LDS.
+// a K block (the elements of a fill block) are spread over blockIdx.x.
+// Transposed blocks go through LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter(const double2* K, typename Cplx<T>::type* L, const KPlaceDev* kp,
                                                  int nkp, const KPlaceDev* fills, int nfill) {
@@ -54,21 +55,24 @@ __global__ __launch_bounds__(256) void k_scatter(const double2* K, typename Cplx
   const int b = blockIdx.y;
   const bool fill = b >= nkp;
   const KPlaceDev P = fill ? fills[b - nkp] : kp[b];
+  if (fill) {
+    // zeros, 16 bytes per store (a row pair in complex64): a fill block
+    // starts at an even row of an even-height panel, and the row after an
+    // odd last row is the panel's unused padding row
+    constexpr int PER = 16 / (int)sizeof(C);
+    const int64_t rp = (P.rows + PER - 1) / PER, tot = rp * P.cols;
+    const float4 z = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t c = e / rp, q = e - c * rp;
+      *reinterpret_cast<float4*>(L + P.dst + PER * q + c * P.ld_dst) = z;
+    }
+    return;
+  }
   const int tr = (P.rows + 31) / 32, tc = (P.cols + 31) / 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int t = blockIdx.x; t < tr * tc; t += gridDim.x) {
     const int r0 = (t % tr) * 32, c0 = (t / tr) * 32;
-    if (fill) {
-      for (int cc = ty; cc < 32; cc += 8) {
-        int r = r0 + tx, c = c0 + cc;
-        if (r < P.rows && c < P.cols) {
-          C z;
-          z.x = 0;
-          z.y = 0;
-          L[P.dst + r + (int64_t)c * P.ld_dst] = z;
-        }
-      }
-    } else if (!P.trans) {
+    if (!P.trans) {
       // the four loads of a thread go out together (unconditional, from a
       // valid address outside the block), then the stores
       double2 v[4];
