@@ -72,7 +72,33 @@ __global__ __launch_bounds__(256) void k_scatter(const double2* K, typename Cplx
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int t = blockIdx.x; t < tr * tc; t += gridDim.x) {
     const int r0 = (t % tr) * 32, c0 = (t / tr) * 32;
-    if (!P.trans) {
+    if (sizeof(C) == 8 && !P.trans) {
+      // complex64: lane (tp, cc) converts rows 2tp, 2tp + 1 of columns cc and
+      // cc + 16 and stores each pair with one 16-byte store (blocks start at
+      // even rows of even-height panels; the row after an odd last row is
+      // the panel's padding row and gets zero).  Loads as below.
+      const int tp = threadIdx.x & 15, cc = threadIdx.x >> 4;
+      double2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + 2 * tp + (q & 1), c = c0 + cc + 16 * (q >> 1);
+        const bool in = r < P.rows && c < P.cols;
+        v[q] = K[P.src + (in ? r + (int64_t)c * P.rows : 0)];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = r0 + 2 * tp, c = c0 + cc + 16 * h;
+        if (r < P.rows && c < P.cols) {
+          const bool two = r + 1 < P.rows;
+          float4 o;
+          o.x = (float)v[2 * h].x;
+          o.y = (float)v[2 * h].y;
+          o.z = two ? (float)v[2 * h + 1].x : 0.f;
+          o.w = two ? (float)v[2 * h + 1].y : 0.f;
+          *reinterpret_cast<float4*>(L + P.dst + r + (int64_t)c * P.ld_dst) = o;
+        }
+      }
+    } else if (!P.trans) {
       // the four loads of a thread go out together (unconditional, from a
       // valid address outside the block), then the stores
       double2 v[4];
@@ -109,14 +135,33 @@ __global__ __launch_bounds__(256) void k_scatter(const double2* K, typename Cplx
         if (r0 + rr < P.rows && c0 + tx < P.cols) tileb[rr][tx] = v[q];
       }
       __syncthreads();
-      for (int cc = ty; cc < 32; cc += 8) {
-        int r = r0 + tx, c = c0 + cc;
-        if (r < P.rows && c < P.cols) {
-          double2 v = tileb[tx][cc];
-          C o;
-          o.x = (T)v.x;
-          o.y = (T)v.y;
-          L[P.dst + r + (int64_t)c * P.ld_dst] = o;
+      if constexpr (sizeof(C) == 8) {
+        // row pairs with 16-byte stores, as in the untransposed case
+        const int tp = threadIdx.x & 15, c16 = threadIdx.x >> 4;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int cc = c16 + 16 * h, r = r0 + 2 * tp, c = c0 + cc;
+          if (r < P.rows && c < P.cols) {
+            const bool two = r + 1 < P.rows;
+            const double2 v0 = tileb[2 * tp][cc], v1 = tileb[2 * tp + 1][cc];
+            float4 o;
+            o.x = (float)v0.x;
+            o.y = (float)v0.y;
+            o.z = two ? (float)v1.x : 0.f;
+            o.w = two ? (float)v1.y : 0.f;
+            *reinterpret_cast<float4*>(L + P.dst + r + (int64_t)c * P.ld_dst) = o;
+          }
+        }
+      } else {
+        for (int cc = ty; cc < 32; cc += 8) {
+          int r = r0 + tx, c = c0 + cc;
+          if (r < P.rows && c < P.cols) {
+            double2 v = tileb[tx][cc];
+            C o;
+            o.x = (T)v.x;
+            o.y = (T)v.y;
+            L[P.dst + r + (int64_t)c * P.ld_dst] = o;
+          }
         }
       }
     }
