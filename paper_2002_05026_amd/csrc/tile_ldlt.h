@@ -171,6 +171,36 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
     if (gc.on) atomicMax((int*)(flags), __float_as_int(sqrtf(amax)));
   }
   __syncthreads();
+  // trailing update of block (gi, gj) by step k on the matrix cores:
+  // A_ij -= L_ik D_k L_jk^T
+  auto upd = [&](int k, int gi, int gj) {
+    const int boi = tl_blk(gi, k), boj = tl_blk(gj, k);
+    v4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kq = kk + lk;
+      const cpx<T> av = tl_mul(S[boi + kq * 16 + lr], dv[k * 16 + kq]);
+      const cpx<T> bv = S[boj + kq * 16 + lr];
+      re = mfma16(av.x, bv.x, re);
+      re = mfma16(-av.y, bv.y, re);
+      im = mfma16(av.x, bv.y, im);
+      im = mfma16(av.y, bv.x, im);
+    }
+    const int bo = tl_blk(gi, gj);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = acc_row<T>(lk, v);
+      cpx<T> x = S[bo + lr * 16 + r];
+      x.x -= re[v];
+      x.y -= im[v];
+      S[bo + lr * 16 + r] = x;
+    }
+  };
+  // Step kb: wave 0 factors diagonal block kb while waves 1..7 apply the
+  // rest of step kb-1's trailing update (columns kb+1 and beyond); then the
+  // blocks below, L_ik; then step kb's update of column kb+1 only, which the
+  // next diagonal block and its L_ik need.  Every block still receives the
+  // steps' updates in step order.
   for (int kb = 0; kb < nb; ++kb) {
     const int bkk = tl_blk(kb, kb);
     if (w == 0) {
@@ -228,6 +258,15 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
           }
         }
       }
+    } else if (kb > 0) {
+      // pairs (gi, gj), gi >= gj >= kb + 1, over waves 1..7
+      const int nt = nb - kb - 1;
+      const int npair = nt * (nt + 1) / 2;
+      for (int pr = w - 1; pr < npair; pr += kThreads / 64 - 1) {
+        int bi = 0, rem = pr;
+        while (rem > bi) { rem -= bi + 1; ++bi; }
+        upd(kb - 1, kb + 1 + bi, kb + 1 + rem);
+      }
     }
     __syncthreads();
     // L_ik = A_ik X_k^T D_k^-1 for block rows i > kb, one block per wave;
@@ -255,39 +294,11 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
       }
     }
     __syncthreads();
-    // trailing update on the matrix cores: A_ij -= L_ik D_k L_jk^T
-    {
-      const int nt = nb - kb - 1;
-      const int npair = nt * (nt + 1) / 2;
-      for (int pr = w; pr < npair; pr += kThreads / 64) {
-        int bi = 0, rem = pr;
-        while (rem > bi) { rem -= bi + 1; ++bi; }
-        const int bj = rem;  // pair (bi, bj), bi >= bj, offsets from kb+1
-        const int gi = kb + 1 + bi, gj = kb + 1 + bj;
-        const int boi = tl_blk(gi, kb), boj = tl_blk(gj, kb);
-        v4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int kq = kk + lk;
-          const cpx<T> av = tl_mul(S[boi + kq * 16 + lr], dv[kb * 16 + kq]);
-          const cpx<T> bv = S[boj + kq * 16 + lr];
-          re = mfma16(av.x, bv.x, re);
-          re = mfma16(-av.y, bv.y, re);
-          im = mfma16(av.x, bv.y, im);
-          im = mfma16(av.y, bv.x, im);
-        }
-        const int bo = tl_blk(gi, gj);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = acc_row<T>(lk, v);
-          cpx<T> x = S[bo + lr * 16 + r];
-          x.x -= re[v];
-          x.y -= im[v];
-          S[bo + lr * 16 + r] = x;
-        }
-      }
+    // step kb's update of column kb + 1: blocks (gi, kb + 1), gi >= kb + 1
+    if (kb + 1 < nb) {
+      for (int gi = kb + 1 + w; gi < nb; gi += kThreads / 64) upd(kb, gi, kb + 1);
+      __syncthreads();
     }
-    __syncthreads();
   }
   // Element loops over a row's lower triangle: the 64 rows of a wave are
   // consecutive, so one past the wave's last row bounds the columns of all
