@@ -354,6 +354,10 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
   // (in place of C), then -D^-1 P.  A level has at most 16 output blocks,
   // two per wave, so the serial depth is three levels of a few block
   // products each (X_i = Linv_ii, kept transposed in the diagonal blocks).
+  // Only the 4-block level has 16: wave w takes blocks w and 15 - w, i.e.
+  // (i, j) and its mirror in the 4 x 4 block C, whose products
+  // (a0 + 4 - j for P, i - d0 + 1 for the rest) sum to the same for every
+  // wave.
   for (int sl = 1; sl < nb; sl *= 2) {
     const int npair = (nb - sl + 2 * sl - 1) / (2 * sl);  // pairs with d0 < nb
     const int tot = npair * sl * sl;
@@ -372,7 +376,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
       re[u] = v4{0, 0, 0, 0};
       im[u] = v4{0, 0, 0, 0};
       int i, j, a0, d0;
-      if (blk(w + 8 * u, i, j, a0, d0))
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
         for (int q = j; q < a0 + sl; ++q) {
 #pragma unroll
           for (int kk = 0; kk < 16; kk += 4) {
@@ -390,7 +394,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       int i, j, a0, d0;
-      if (blk(w + 8 * u, i, j, a0, d0))
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           cpx<T> t;
@@ -406,7 +410,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
       re[u] = v4{0, 0, 0, 0};
       im[u] = v4{0, 0, 0, 0};
       int i, j, a0, d0;
-      if (blk(w + 8 * u, i, j, a0, d0))
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
         for (int q = d0; q <= i; ++q) {
 #pragma unroll
           for (int kk = 0; kk < 16; kk += 4) {
@@ -424,7 +428,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       int i, j, a0, d0;
-      if (blk(w + 8 * u, i, j, a0, d0))
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           cpx<T> t;
