@@ -4,7 +4,7 @@ X = K^{-1} B for the block-sparse complex-symmetric K given as the flat K
 buffer (see include/d3m.h).  The backward pass reuses the factors: because
 K = K^T, lambda = K^{-1} g needs no second factorization, and the gradient on
 K lives on K's block pattern (Sec. II of the paper: the dual solution step;
-the adjoint is this build's differentiation form).
+the adjoint is the library's way of differentiating it).
 
 Conventions.  The C ABI is holomorphic: for J = sum_k Re(c_k^T x_k) it takes
 G = C and returns Lambda = K^{-1} G and dK = -sym(Lambda X^T) per block.
