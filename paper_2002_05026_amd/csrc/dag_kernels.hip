@@ -276,14 +276,31 @@ __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
   const int64_t nr = cx.nrhs, stride = cx.iv->N * nr;
   D3M_GLB cpx<T>* w = gptr_mut<T>(cx.W + t.c_off * nr);
   const int64_t tot = (int64_t)t.m * nr;
-  for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
-    cpx<T> v = w[e];
-    for (int q = 1; q <= t.k; ++q) {
-      const cpx<T> u = w[q * stride + e];
-      v.x += u.x;
-      v.y += u.y;
+  // a thread's elements in batches of E, every load of a batch issued before
+  // its first add (one memory latency per batch instead of one per element);
+  // element e adds accumulators 1..t.k onto b in that order.  Loads beyond
+  // tot or t.k read element 0 of b (a valid address) and are not used.
+  constexpr int E = 8;
+  for (int64_t e0 = threadIdx.x; e0 < tot; e0 += (int64_t)E * kThreads) {
+    cpx<T> v[E], u[kSolveSlots][E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int64_t e = e0 + (int64_t)i * kThreads, ec = e < tot ? e : 0;
+      v[i] = w[ec];
+#pragma unroll
+      for (int q = 0; q < kSolveSlots; ++q) u[q][i] = w[(q < t.k ? (q + 1) * stride : 0) + ec];
     }
-    w[e] = v;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int64_t e = e0 + (int64_t)i * kThreads;
+#pragma unroll
+      for (int q = 0; q < kSolveSlots; ++q)
+        if (q < t.k) {
+          v[i].x += u[q][i].x;
+          v[i].y += u[q][i].y;
+        }
+      if (e < tot) w[e] = v[i];
+    }
   }
 }
 
