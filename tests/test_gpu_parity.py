@@ -258,3 +258,11 @@ def test_forced_fp64_fallback_of_diagonal_tiles():
     h.factorize(K)
     h.solve(B)
     assert h.status()["fallbacks"] == 0
+    # the other trigger, max|L| above its bound: every tile with a multiplier
+    # trips (a one-row tile has none), and refinement still certifies
+    q = d3m.Factor(plan, 1, nrhs_max=3, growth_lmax=1e-30)
+    q.factorize(K)
+    Xq = q.solve(B).cpu().numpy()
+    sq = q.status()
+    assert sq["status"] == 0 and 0 < sq["fallbacks"] <= plan.info["ntiles"], sq
+    assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, Xq, inst.B).max() <= 1e-10
