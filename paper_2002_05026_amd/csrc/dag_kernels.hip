@@ -411,10 +411,14 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
     // workgroup before the successors are told
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // every lane of wave 0 releases, then lane l tells successors l, l + 64,
+    // ...: their indices come in one vector load and the decrements go out
+    // together (one lane telling them in turn waits for each decrement, as
+    // atomics count among the outstanding vector-memory operations)
+    if (threadIdx.x < 64) {
       __scoped_atomic_thread_fence(__ATOMIC_RELEASE, __MEMORY_SCOPE_DEVICE);
-      if (a.trace) a.trace[4 * t + 2] = (int64_t)wall_clock64();
-      for (int s = 0; s < task.nsucc; ++s)
+      if (threadIdx.x == 0 && a.trace) a.trace[4 * t + 2] = (int64_t)wall_clock64();
+      for (int s = threadIdx.x; s < task.nsucc; s += 64)
         __hip_atomic_fetch_add(&a.counters[a.succ[task.succ_begin + s]], -1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
