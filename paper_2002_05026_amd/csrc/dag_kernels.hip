@@ -375,11 +375,11 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   for (;;) {
     if (threadIdx.x == 0) {
-      int t = -1;
-      if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        t = __hip_atomic_fetch_add(a.head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (t >= a.ntask) t = -1;
-      }
+      // the abort flag and the next ticket are fetched together (a ticket
+      // taken after an abort is simply not run)
+      const int aborted = __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int t = __hip_atomic_fetch_add(a.head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (aborted != 0 || t >= a.ntask) t = -1;
       uint64_t t0 = wall_clock64();
       if (t >= 0) {
         while (__hip_atomic_load(&a.counters[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
