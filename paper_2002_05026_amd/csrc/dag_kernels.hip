@@ -374,7 +374,12 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   __shared__ int s_ticket;
   if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   for (;;) {
-    if (threadIdx.x == 0) {
+    // In the factor DAG wave 1 takes the next ticket and waits for its
+    // dependencies while wave 0 is still releasing the previous task (below):
+    // factor 79.5 -> 79.2 ms.  The solve DAG's short tasks and chains ran
+    // slower that way (8.4 -> 8.65 ms), so there wave 0 takes it after the
+    // release.
+    if (threadIdx.x == (PHASE == 0 ? 64 : 0)) {
       // the abort flag and the next ticket are fetched together (a ticket
       // taken after an abort is simply not run)
       const int aborted = __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
