@@ -13,7 +13,9 @@
 //     waves:  L_ik = A_ik X_k^T D_k^-1 for the blocks below (one block per
 //             wave on the matrix cores)
 //     all:    A_ij -= L_ik D_k L_jk^T on the trailing blocks (one 16x16x16
-//             complex product per block pair on the matrix cores)
+//             complex product per block pair on the matrix cores): column
+//             k+1 at once, the other columns on waves 1..7 while wave 0
+//             factors diagonal block k+1 (look-ahead)
 //
 // then L (strictly below the diagonal) and D (on it) go back to the tile in
 // global memory, and the full inverse Linv = L^-1 (m x m, column-major with
