@@ -372,6 +372,7 @@ template <typename T, int PHASE>
 __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[dag_lds_bytes<T>()];
   __shared__ int s_ticket;
+  __shared__ Task s_task;  // the factor DAG's next task record, read by the ticket's taker
   if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   for (;;) {
     // In the factor DAG wave 1 takes the next ticket and waits for its
@@ -401,6 +402,7 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
       // acquire on behalf of the workgroup (its waves share the CU's caches)
       if (t >= 0) __scoped_atomic_thread_fence(__ATOMIC_ACQUIRE, __MEMORY_SCOPE_DEVICE);
       s_ticket = t;
+      if (PHASE == 0 && t >= 0) s_task = a.tasks[t];
       if (t >= 0 && a.trace) {
         a.trace[4 * t] = (int64_t)t0;
         a.trace[4 * t + 1] = (int64_t)wall_clock64();
@@ -410,7 +412,9 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: the task is read with scalar loads
     if (t < 0) break;
-    const Task task = a.tasks[t];
+    // (in the factor DAG from LDS: wave 1 read it while wave 0 released the
+    // previous task)
+    const Task task = PHASE == 0 ? uniform_task(s_task) : a.tasks[t];
     run_task<T>(task, a.inst, a.nrhs, (lds_char*)lds);
     // every wave's stores complete, then one agent-scope release for the
     // workgroup before the successors are told
