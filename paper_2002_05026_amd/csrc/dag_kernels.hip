@@ -155,7 +155,9 @@ __device__ __noinline__ void task_trsm(const Ctx<T>& cx_, const Task& t_) {
 // C -= sum over the task's sources of (L_rI D_I) L_sI^T on one tile pair
 // (TK_XUPD); t.pad0 > 1: the sources are xsrc[t.pad1 ...], else the task's
 // own operands
-template <typename T>
+// PRESRC: a merged update's source table is already in LDS (put there
+// by the executor while it released the previous task).
+template <typename T, bool PRESRC = false>
 __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
@@ -176,7 +178,7 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
     // direct-load pipeline runs over the slabs of all of them; the target's
     // loads go out with the last slab
     D3M_LDS GeSrc<T>* tab = reinterpret_cast<D3M_LDS GeSrc<T>*>(cx.lds + ge_lds_bytes_dma<T>());
-    if ((int)threadIdx.x < nsrc) {
+    if (!(PRESRC && t.pad0 > 1) && (int)threadIdx.x < nsrc) {
       const XSrc x = src(threadIdx.x);
       GeSrc<T> e;
       e.a = cx.LD + x.a_off;
@@ -332,7 +334,7 @@ __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)1, (T)0));
 }
 
-template <typename T>
+template <typename T, bool PRESRC = false>
 __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char* lds) {
   typedef typename Cplx<T>::type C;
   Ctx<T> cx;
@@ -348,7 +350,7 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
   switch (t.kind) {
     case TK_FACT: task_fact<T>(cx, t); break;
     case TK_TRSM: task_trsm<T>(cx, t); break;
-    case TK_XUPD: task_xupd<T>(cx, t); break;
+    case TK_XUPD: task_xupd<T, PRESRC>(cx, t); break;
     case TK_INV: task_inv<T>(cx, t); break;
     case TK_FTILE: task_ftile<T>(cx, t); break;
     case TK_FUPD: task_fupd<T>(cx, t); break;
@@ -409,13 +411,32 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
         a.trace[4 * t + 3] = blockIdx.x;
       }
     }
+    // complex64 factor DAG: wave 1 also puts a merged update's sources into
+    // LDS, where the update reads them (their loads overlap wave 0's release)
+    constexpr bool kPreSrc = PHASE == 0 && sizeof(typename Cplx<T>::type) == 8;
+    static_assert(kMergeSrc <= 64, "one lane of wave 1 per source");
+    if (kPreSrc && threadIdx.x >= 64 && threadIdx.x < 128) {
+      const int tq = s_ticket;  // written by lane 0 of this wave
+      if (tq >= 0 && s_task.kind == TK_XUPD && s_task.pad0 > 1 && (int)threadIdx.x - 64 < s_task.pad0) {
+        typedef typename Cplx<T>::type C;
+        const InstView* iv = a.inst + s_task.inst;
+        const XSrc x = iv->xsrc[s_task.pad1 + (int)threadIdx.x - 64];
+        GeSrc<T> e;
+        e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
+        e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
+        e.lda = e.ldb = x.lda;
+        e.k = x.k;
+        e.pad = 0;
+        ge_src_put(reinterpret_cast<D3M_LDS GeSrc<T>*>((lds_char*)lds + ge_lds_bytes_dma<T>()), (int)threadIdx.x - 64, e);
+      }
+    }
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: the task is read with scalar loads
     if (t < 0) break;
     // (in the factor DAG from LDS: wave 1 read it while wave 0 released the
     // previous task)
     const Task task = PHASE == 0 ? uniform_task(s_task) : a.tasks[t];
-    run_task<T>(task, a.inst, a.nrhs, (lds_char*)lds);
+    run_task<T, kPreSrc>(task, a.inst, a.nrhs, (lds_char*)lds);
     // every wave's stores complete, then one agent-scope release for the
     // workgroup before the successors are told
     __builtin_amdgcn_s_waitcnt(0);
