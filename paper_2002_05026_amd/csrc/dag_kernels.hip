@@ -373,84 +373,114 @@ template <typename T> constexpr int dag_lds_bytes() {
 template <typename T, int PHASE>
 __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[dag_lds_bytes<T>()];
-  __shared__ int s_ticket;
+  __shared__ int s_ticket, s_next;
   __shared__ Task s_task;  // the factor DAG's next task record, read by the ticket's taker
   if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  for (;;) {
-    // In the factor DAG wave 1 takes the next ticket and waits for its
-    // dependencies while wave 0 is still releasing the previous task (below):
-    // factor 79.5 -> 79.2 ms.  The solve DAG's short tasks and chains ran
-    // slower that way (8.4 -> 8.65 ms), so there wave 0 takes it after the
-    // release.
-    if (threadIdx.x == (PHASE == 0 ? 64 : 0)) {
-      // the abort flag and the next ticket are fetched together (a ticket
-      // taken after an abort is simply not run)
-      const int aborted = __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int t = __hip_atomic_fetch_add(a.head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (aborted != 0 || t >= a.ntask) t = -1;
-      uint64_t t0 = wall_clock64();
-      if (t >= 0) {
-        while (__hip_atomic_load(&a.counters[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
-          __builtin_amdgcn_s_sleep(2);
-          if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { t = -1; break; }
-          // wall_clock64 ticks at 100 MHz: 10 ns per tick
-          if ((int64_t)(wall_clock64() - t0) * 10 > a.spin_limit_ns) {
-            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            t = -1;
-            break;
-          }
+  // the next ticket, fetched together with the abort flag (a ticket taken
+  // after an abort is simply not run); -1: none
+  auto take = [&]() {
+    const int aborted = __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int t = __hip_atomic_fetch_add(a.head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (aborted != 0 || t >= a.ntask) ? -1 : t;
+  };
+  // wait until ticket t's predecessors are done (-1: aborted or timed out),
+  // then acquire on behalf of the workgroup (its waves share the CU's caches)
+  auto wait_ready = [&](int t) {
+    const uint64_t t0 = wall_clock64();
+    if (t >= 0) {
+      while (__hip_atomic_load(&a.counters[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+        __builtin_amdgcn_s_sleep(2);
+        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { t = -1; break; }
+        // wall_clock64 ticks at 100 MHz: 10 ns per tick
+        if ((int64_t)(wall_clock64() - t0) * 10 > a.spin_limit_ns) {
+          __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          t = -1;
+          break;
         }
       }
-      // acquire on behalf of the workgroup (its waves share the CU's caches)
-      if (t >= 0) __scoped_atomic_thread_fence(__ATOMIC_ACQUIRE, __MEMORY_SCOPE_DEVICE);
-      s_ticket = t;
-      if (PHASE == 0 && t >= 0) s_task = a.tasks[t];
-      if (t >= 0 && a.trace) {
-        a.trace[4 * t] = (int64_t)t0;
-        a.trace[4 * t + 1] = (int64_t)wall_clock64();
-        a.trace[4 * t + 3] = blockIdx.x;
-      }
     }
-    // complex64 factor DAG: wave 1 also puts a merged update's sources into
-    // LDS, where the update reads them (their loads overlap wave 0's release)
-    constexpr bool kPreSrc = PHASE == 0 && sizeof(typename Cplx<T>::type) == 8;
-    static_assert(kMergeSrc <= 64, "one lane of wave 1 per source");
-    if (kPreSrc && threadIdx.x >= 64 && threadIdx.x < 128) {
-      const int tq = s_ticket;  // written by lane 0 of this wave
-      if (tq >= 0 && s_task.kind == TK_XUPD && s_task.pad0 > 1 && (int)threadIdx.x - 64 < s_task.pad0) {
-        typedef typename Cplx<T>::type C;
-        const InstView* iv = a.inst + s_task.inst;
-        const XSrc x = iv->xsrc[s_task.pad1 + (int)threadIdx.x - 64];
-        GeSrc<T> e;
-        e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
-        e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
-        e.lda = e.ldb = x.lda;
-        e.k = x.k;
-        e.pad = 0;
-        ge_src_put(reinterpret_cast<D3M_LDS GeSrc<T>*>((lds_char*)lds + ge_lds_bytes_dma<T>()), (int)threadIdx.x - 64, e);
-      }
+    if (t >= 0) __scoped_atomic_thread_fence(__ATOMIC_ACQUIRE, __MEMORY_SCOPE_DEVICE);
+    if (t >= 0 && a.trace) {
+      a.trace[4 * t] = (int64_t)t0;
+      a.trace[4 * t + 1] = (int64_t)wall_clock64();
+      a.trace[4 * t + 3] = blockIdx.x;
     }
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: the task is read with scalar loads
-    if (t < 0) break;
-    // (in the factor DAG from LDS: wave 1 read it while wave 0 released the
-    // previous task)
-    const Task task = PHASE == 0 ? uniform_task(s_task) : a.tasks[t];
-    run_task<T, kPreSrc>(task, a.inst, a.nrhs, (lds_char*)lds);
-    // every wave's stores complete, then one agent-scope release for the
-    // workgroup before the successors are told
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    // every lane of wave 0 releases, then lane l tells successors l, l + 64,
-    // ...: their indices come in one vector load and the decrements go out
-    // together (one lane telling them in turn waits for each decrement, as
-    // atomics count among the outstanding vector-memory operations)
+    return t;
+  };
+  // every wave's stores are complete (the caller's barrier): every lane of
+  // wave 0 releases, then lane l tells successors l, l + 64, ...: their
+  // indices come in one vector load and the decrements go out together (one
+  // lane telling them in turn waits for each decrement, as atomics count
+  // among the outstanding vector-memory operations)
+  auto release = [&](const Task& task, int t) {
     if (threadIdx.x < 64) {
       __scoped_atomic_thread_fence(__ATOMIC_RELEASE, __MEMORY_SCOPE_DEVICE);
       if (threadIdx.x == 0 && a.trace) a.trace[4 * t + 2] = (int64_t)wall_clock64();
       for (int s = threadIdx.x; s < task.nsucc; s += 64)
         __hip_atomic_fetch_add(&a.counters[a.succ[task.succ_begin + s]], -1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+  if constexpr (PHASE == 0) {
+    // Factor DAG: wave 1 takes the next ticket and reads its task record
+    // (and a complex64 merged update's source table, into LDS where the
+    // update reads it) while the other waves' stores drain; after the
+    // barrier it waits for that task's predecessors while wave 0 releases
+    // the finished task.  Only read-only tables are read before the wait.
+    constexpr bool kPreSrc = sizeof(typename Cplx<T>::type) == 8;
+    static_assert(kMergeSrc <= 64, "one lane of wave 1 per source");
+    auto take_next = [&]() {
+      if (threadIdx.x == 64) {
+        const int t = take();
+        s_next = t;
+        if (t >= 0) s_task = a.tasks[t];
+      }
+      if (kPreSrc && threadIdx.x >= 64 && threadIdx.x < 128) {
+        const int q = (int)threadIdx.x - 64;
+        if (s_next >= 0 && s_task.kind == TK_XUPD && s_task.pad0 > 1 && q < s_task.pad0) {
+          typedef typename Cplx<T>::type C;
+          const InstView* iv = a.inst + s_task.inst;
+          const XSrc x = iv->xsrc[s_task.pad1 + q];
+          GeSrc<T> e;
+          e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
+          e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
+          e.lda = e.ldb = x.lda;
+          e.k = x.k;
+          e.pad = 0;
+          ge_src_put(reinterpret_cast<D3M_LDS GeSrc<T>*>((lds_char*)lds + ge_lds_bytes_dma<T>()), q, e);
+        }
+      }
+    };
+    take_next();
+    for (;;) {
+      if (threadIdx.x == 64) s_ticket = wait_ready(s_next);
+      __syncthreads();
+      const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+      if (t < 0) break;
+      const Task task = uniform_task(s_task);
+      run_task<T, kPreSrc>(task, a.inst, a.nrhs, (lds_char*)lds);
+      // (every LDS access of the task after its last barrier lies below the
+      // source table, which wave 1 may now fill for the next task)
+      __builtin_amdgcn_s_waitcnt(0);
+      take_next();
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      release(task, t);
+    }
+  } else {
+    // Solve DAG: one lane of wave 0 takes the next ticket after the release
+    // (the overlapped order above measured slower for the solve's short
+    // tasks and chains)
+    for (;;) {
+      if (threadIdx.x == 0) s_ticket = wait_ready(take());
+      __syncthreads();
+      const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: the task is read with scalar loads
+      if (t < 0) break;
+      const Task task = a.tasks[t];
+      run_task<T>(task, a.inst, a.nrhs, (lds_char*)lds);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      release(task, t);
     }
   }
 }
