@@ -421,67 +421,50 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
                                __HIP_MEMORY_SCOPE_AGENT);
     }
   };
-  if constexpr (PHASE == 0) {
-    // Factor DAG: wave 1 takes the next ticket and reads its task record
-    // (and a complex64 merged update's source table, into LDS where the
-    // update reads it) while the other waves' stores drain; after the
-    // barrier it waits for that task's predecessors while wave 0 releases
-    // the finished task.  Only read-only tables are read before the wait.
-    constexpr bool kPreSrc = sizeof(typename Cplx<T>::type) == 8;
-    static_assert(kMergeSrc <= 64, "one lane of wave 1 per source");
-    auto take_next = [&]() {
-      if (threadIdx.x == 64) {
-        const int t = take();
-        s_next = t;
-        if (t >= 0) s_task = a.tasks[t];
+  // Wave 1 takes the next ticket and reads its task record
+  // (and a complex64 merged update's source table, into LDS where the
+  // update reads it) while the other waves' stores drain; after the
+  // barrier it waits for that task's predecessors while wave 0 releases
+  // the finished task.  Only read-only tables are read before the wait.
+  constexpr bool kPreSrc = sizeof(typename Cplx<T>::type) == 8;
+  static_assert(kMergeSrc <= 64, "one lane of wave 1 per source");
+  auto take_next = [&]() {
+    if (threadIdx.x == 64) {
+      const int t = take();
+      s_next = t;
+      if (t >= 0) s_task = a.tasks[t];
+    }
+    if (kPreSrc && threadIdx.x >= 64 && threadIdx.x < 128) {
+      const int q = (int)threadIdx.x - 64;
+      if (s_next >= 0 && s_task.kind == TK_XUPD && s_task.pad0 > 1 && q < s_task.pad0) {
+        typedef typename Cplx<T>::type C;
+        const InstView* iv = a.inst + s_task.inst;
+        const XSrc x = iv->xsrc[s_task.pad1 + q];
+        GeSrc<T> e;
+        e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
+        e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
+        e.lda = e.ldb = x.lda;
+        e.k = x.k;
+        e.pad = 0;
+        ge_src_put(reinterpret_cast<D3M_LDS GeSrc<T>*>((lds_char*)lds + ge_lds_bytes_dma<T>()), q, e);
       }
-      if (kPreSrc && threadIdx.x >= 64 && threadIdx.x < 128) {
-        const int q = (int)threadIdx.x - 64;
-        if (s_next >= 0 && s_task.kind == TK_XUPD && s_task.pad0 > 1 && q < s_task.pad0) {
-          typedef typename Cplx<T>::type C;
-          const InstView* iv = a.inst + s_task.inst;
-          const XSrc x = iv->xsrc[s_task.pad1 + q];
-          GeSrc<T> e;
-          e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
-          e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
-          e.lda = e.ldb = x.lda;
-          e.k = x.k;
-          e.pad = 0;
-          ge_src_put(reinterpret_cast<D3M_LDS GeSrc<T>*>((lds_char*)lds + ge_lds_bytes_dma<T>()), q, e);
-        }
-      }
-    };
+    }
+  };
+  take_next();
+  for (;;) {
+    if (threadIdx.x == 64) s_ticket = wait_ready(s_next);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (t < 0) break;
+    const Task task = uniform_task(s_task);
+    run_task<T, kPreSrc>(task, a.inst, a.nrhs, (lds_char*)lds);
+    // (every LDS access of the task after its last barrier lies below the
+    // source table, which wave 1 may now fill for the next task)
+    __builtin_amdgcn_s_waitcnt(0);
     take_next();
-    for (;;) {
-      if (threadIdx.x == 64) s_ticket = wait_ready(s_next);
-      __syncthreads();
-      const int t = __builtin_amdgcn_readfirstlane(s_ticket);
-      if (t < 0) break;
-      const Task task = uniform_task(s_task);
-      run_task<T, kPreSrc>(task, a.inst, a.nrhs, (lds_char*)lds);
-      // (every LDS access of the task after its last barrier lies below the
-      // source table, which wave 1 may now fill for the next task)
-      __builtin_amdgcn_s_waitcnt(0);
-      take_next();
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      release(task, t);
-    }
-  } else {
-    // Solve DAG: one lane of wave 0 takes the next ticket after the release
-    // (the overlapped order above measured slower for the solve's short
-    // tasks and chains)
-    for (;;) {
-      if (threadIdx.x == 0) s_ticket = wait_ready(take());
-      __syncthreads();
-      const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: the task is read with scalar loads
-      if (t < 0) break;
-      const Task task = a.tasks[t];
-      run_task<T>(task, a.inst, a.nrhs, (lds_char*)lds);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      release(task, t);
-    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    release(task, t);
   }
 }
 
