@@ -92,6 +92,11 @@ typedef struct {
   double growth_lmax;   /* FP32 fallback trigger: max|L| > growth_lmax; 0 -> 1e2      */
   int32_t fallback;     /* 1 (default via 0): re-factor tripped blocks in FP64; -1 off */
   int32_t timing;       /* 1: record HIP events around every DAG launch (run_info times) */
+  int32_t dk_stored;    /* 1: d3m_adjoint returns dK with respect to the stored entries of
+                           the K buffer: a stored off-diagonal entry also moves its mirror
+                           (x2), a diagonal block is read from its lower triangle (strict
+                           lower x2, diagonal x1, upper 0); 0: the symmetric block gradient */
+  int32_t reserved;
 } d3m_options;
 
 typedef struct {

@@ -44,7 +44,8 @@ class AnalyzeOptions(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("ir_host_sync", ctypes.c_int32),
                 ("growth_dmin", ctypes.c_double), ("growth_lmax", ctypes.c_double),
-                ("fallback", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("timing", ctypes.c_int32), ("dk_stored", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -208,7 +209,7 @@ class Factor:
 
     def __init__(self, plan: Plan, precision: int = C128, nrhs_max: int = 1, tol: float = 1e-10,
                  max_iter: int = 10, ir_host_sync: bool = False, timing: bool = False, growth_dmin: float = 0.0,
-                 growth_lmax: float = 0.0, fallback: bool = True, device=None):
+                 growth_lmax: float = 0.0, fallback: bool = True, dk_stored: bool = False, device=None):
         import torch
         self.plan = plan
         self.precision = int(precision)
@@ -219,7 +220,7 @@ class Factor:
         base = self.ws.data_ptr()
         self._off = (-base) % 256
         opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), float(growth_dmin), float(growth_lmax),
-                       0 if fallback else -1, int(bool(timing)))
+                       0 if fallback else -1, int(bool(timing)), int(bool(dk_stored)), 0)
         h = _vp()
         _check(lib().d3m_factor_bind(plan._h, self.precision, ctypes.c_void_p(base + self._off), nbytes,
                                      self.nrhs_max, ctypes.byref(opts), ctypes.byref(h)), "d3m_factor_bind")

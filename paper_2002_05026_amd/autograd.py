@@ -10,32 +10,17 @@ Conventions.  The C ABI is holomorphic: for J = sum_k Re(c_k^T x_k) it takes
 G = C and returns Lambda = K^{-1} G and dK = -sym(Lambda X^T) per block.
 PyTorch hands backward grad_X = conj(dJ/dX) and expects conjugated
 gradients, so this wrapper passes G = conj(grad_X) and returns conj(Lambda)
-for B.  For the flat K buffer the gradient is taken with respect to the
-stored entries: a diagonal block is read from its lower triangle, so its
-strictly-lower entries carry both (i,j) and (j,i) (factor 2), its diagonal
-carries one, and its upper triangle none; a stored off-diagonal block also
-carries its mirror K_JI = K_IJ^T (factor 2).
+for B.  For the flat K buffer the library returns the gradient with respect
+to the stored entries (d3m_options.dk_stored): a diagonal block is read from
+its lower triangle, so its strictly-lower entries carry both (i,j) and (j,i),
+its diagonal one entry and its upper triangle none; a stored off-diagonal
+block also carries its mirror K_JI = K_IJ^T.  The wrapper only conjugates.
 """
 from __future__ import annotations
 
 import torch
 
-from . import C128, C64_IR, Factor, Plan
-
-
-def flat_grad_from_dK(plan: Plan, dK: torch.Tensor) -> torch.Tensor:
-    """Gradient on the stored entries from the symmetric block gradient."""
-    out = torch.empty_like(dK)
-    off = plan.k_offsets()
-    sizes = plan.sizes
-    nb = plan.nb
-    for i in range(nb):
-        n = int(sizes[i])
-        blk = dK[off[i]:off[i + 1]].view(n, n).t()  # column-major storage -> (row, col)
-        g = 2.0 * torch.tril(blk, -1) + torch.diag_embed(torch.diagonal(blk))
-        out[off[i]:off[i + 1]] = g.t().reshape(-1)
-    out[off[nb]:] = 2.0 * dK[off[nb]:]
-    return out
+from . import C128, Factor
 
 
 class D3MSolve(torch.autograd.Function):
@@ -43,11 +28,10 @@ class D3MSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, K, B, plan, precision=C128, tol=1e-10):
-        f = Factor(plan, precision, nrhs_max=B.shape[0], tol=tol)
+        f = Factor(plan, precision, nrhs_max=B.shape[0], tol=tol, dk_stored=True)
         f.factorize(K.detach())
         X = f.solve(B.detach().contiguous())
         ctx.factor = f
-        ctx.plan = plan
         ctx.save_for_backward(X)
         return X
 
@@ -59,7 +43,7 @@ class D3MSolve(torch.autograd.Function):
         want_k = ctx.needs_input_grad[0]
         Lam, dK = f.adjoint(X, G, want_dK=want_k)
         gB = torch.conj(Lam).resolve_conj() if ctx.needs_input_grad[1] else None
-        gK = torch.conj(flat_grad_from_dK(ctx.plan, dK)).resolve_conj() if want_k else None
+        gK = torch.conj(dK).resolve_conj() if want_k else None
         return gK, gB, None, None, None
 
 

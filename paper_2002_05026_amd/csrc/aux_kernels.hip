@@ -542,8 +542,13 @@ hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
 
 // ---------------------------------------------------------------- dK
 // dK(I,J) tile = -1/2 sum_k (lam_I x_J^T + x_I lam_J^T); user layout vectors.
+// stored: the gradient with respect to the stored entries of the K buffer
+// instead, i.e. each value times the number of entries of the symmetric K
+// it stands for: 2 for an off-diagonal block (K_IJ and its mirror K_JI), and
+// inside a diagonal block (read from its lower triangle) 2 below the
+// diagonal, 1 on it, 0 above.
 __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const double2* X, int64_t ld, int nrhs, double2* dK,
-                                            UserView uv, const DkTaskDev* dt) {
+                                            UserView uv, const DkTaskDev* dt, int stored) {
   __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes_dma<double>()];
   const DkTaskDev t = dt[blockIdx.x];
   const int64_t ri = uv.row0[t.I] + t.r0, rj = uv.row0[t.J] + t.c0;
@@ -559,6 +564,20 @@ __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const doubl
   A.p = X + ri;
   B.p = Lam + rj;
   gemm_acc<double, 8, GeKB<double>::KB, OP_N, true>(acc, t.m, t.n, nrhs, A, nullptr, B, (lds_char*)lds);
+  if (stored) {
+    // item (bj, v) of lane (lr, lk) in wave w is element (16w + lr, 16bj + acc_row(lk, v)) of the tile
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+    const int gi = t.r0 + 16 * w + lr;
+#pragma unroll
+    for (int bj = 0; bj < 8; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gj = t.c0 + 16 * bj + acc_row<double>(lk, v);
+        const double wgt = t.I != t.J ? 2.0 : (gi > gj ? 2.0 : (gi == gj ? 1.0 : 0.0));
+        acc.re[bj][v] *= wgt;
+        acc.im[bj][v] *= wgt;
+      }
+  }
   Out<double> o;
   const int nI = uv.n[t.I];
   o.dst = dK + t.koff + t.r0 + (int64_t)t.c0 * nI;
@@ -574,10 +593,10 @@ __global__ __launch_bounds__(kThreads) void k_dk(const double2* Lam, const doubl
 }
 
 hipError_t launch_dk(const void* Lam, const void* X, int64_t ld, int nrhs, void* dK, const UserView& uv,
-                     const DkTaskDev* dt, int ndt, hipStream_t s) {
+                     const DkTaskDev* dt, int ndt, int stored, hipStream_t s) {
   if (ndt == 0) return hipSuccess;
   hipLaunchKernelGGL(k_dk, dim3(ndt), dim3(kThreads), 0, s, (const double2*)Lam, (const double2*)X, ld, nrhs,
-                     (double2*)dK, uv, dt);
+                     (double2*)dK, uv, dt, stored);
   return hipGetLastError();
 }
 

@@ -536,7 +536,7 @@ d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const
   if (st) return st;
   if (dev_dK)
     HIPCHK(launch_dk(dev_Lambda, dev_X, ld, nrhs, dev_dK, f->uv(), f->at<DkTaskDev>(f->lay.dkt),
-                     (int)f->tab.dkt.size(), s));
+                     (int)f->tab.dkt.size(), f->opt.dk_stored, s));
   f->last = s;
   return D3M_OK;
 }

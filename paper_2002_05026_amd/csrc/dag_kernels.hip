@@ -373,8 +373,13 @@ template <typename T> constexpr int dag_lds_bytes() {
 template <typename T, int PHASE>
 __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[dag_lds_bytes<T>()];
-  __shared__ int s_ticket, s_next;
-  __shared__ Task s_task;  // the factor DAG's next task record, read by the ticket's taker
+  // The next ticket and its task record, double-buffered by loop parity:
+  // wave 1 fills slot b ^ 1 while the current task (read from slot b) may
+  // still be running on other waves, so a task body without any barrier
+  // (TK_RED) cannot have its record overwritten before a slow wave copied it.
+  // Slot b ^ 1 was last read in the previous iteration, before two barriers.
+  __shared__ int s_ticket, s_next[2];
+  __shared__ Task s_task[2];
   if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   // the next ticket, fetched together with the abort flag (a ticket taken
   // after an abort is simply not run); -1: none
@@ -428,18 +433,19 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   // the finished task.  Only read-only tables are read before the wait.
   constexpr bool kPreSrc = sizeof(typename Cplx<T>::type) == 8;
   static_assert(kMergeSrc <= 64, "one lane of wave 1 per source");
-  auto take_next = [&]() {
+  auto take_next = [&](int b) {
     if (threadIdx.x == 64) {
       const int t = take();
-      s_next = t;
-      if (t >= 0) s_task = a.tasks[t];
+      s_next[b] = t;
+      if (t >= 0) s_task[b] = a.tasks[t];
     }
     if (kPreSrc && threadIdx.x >= 64 && threadIdx.x < 128) {
       const int q = (int)threadIdx.x - 64;
-      if (s_next >= 0 && s_task.kind == TK_XUPD && s_task.pad0 > 1 && q < s_task.pad0) {
+      const Task& nt = s_task[b];
+      if (s_next[b] >= 0 && nt.kind == TK_XUPD && nt.pad0 > 1 && q < nt.pad0) {
         typedef typename Cplx<T>::type C;
-        const InstView* iv = a.inst + s_task.inst;
-        const XSrc x = iv->xsrc[s_task.pad1 + q];
+        const InstView* iv = a.inst + nt.inst;
+        const XSrc x = iv->xsrc[nt.pad1 + q];
         GeSrc<T> e;
         e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
         e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
@@ -450,21 +456,25 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
       }
     }
   };
-  take_next();
+  int b = 0;
+  take_next(b);
   for (;;) {
-    if (threadIdx.x == 64) s_ticket = wait_ready(s_next);
+    if (threadIdx.x == 64) s_ticket = wait_ready(s_next[b]);
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_ticket);
     if (t < 0) break;
-    const Task task = uniform_task(s_task);
+    const Task task = uniform_task(s_task[b]);
     run_task<T, kPreSrc>(task, a.inst, a.nrhs, (lds_char*)lds);
-    // (every LDS access of the task after its last barrier lies below the
-    // source table, which wave 1 may now fill for the next task)
+    // The source table is single-buffered: the only task that reads it (a
+    // merged XUPD) ends with a barrier after its last read, and every LDS
+    // access of any task after its last barrier lies below the table, so
+    // wave 1 may now fill it for the next task.
     __builtin_amdgcn_s_waitcnt(0);
-    take_next();
+    take_next(b ^ 1);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     release(task, t);
+    b ^= 1;
   }
 }
 

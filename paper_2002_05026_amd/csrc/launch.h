@@ -88,7 +88,7 @@ hipError_t launch_cvt_up(const void* W32, void* X64, int64_t n, hipStream_t s);
 hipError_t launch_axpy_up(const void* W32, void* X64, int64_t n, const int32_t* skip, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 hipError_t launch_dk(const void* Lam, const void* X, int64_t ld, int nrhs, void* dK, const UserView& uv,
-                     const DkTaskDev* dt, int ndt, hipStream_t s);
+                     const DkTaskDev* dt, int ndt, int stored, hipStream_t s);
 hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t s);
 hipError_t launch_all_stop(IrCtrl* const* ctrls, int n, int32_t* out, hipStream_t s);
 hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, const void* A, int64_t lda,

@@ -5,8 +5,8 @@ face-adjacent domains, the block pattern of K (block (I,J) is nonzero when
 interfaces I and J border a common domain, Sec. II and Fig. 1(b) of the
 paper), the interface sizes and the random values of K, B and C.  It holds
 none of the method's arithmetic (no ordering, fill, factorization or solve):
-both the CPU oracle and the GPU library receive what it returns and compute
-everything else on their own.
+both the CPU reference solver of the tests and the GPU library receive what
+it returns and compute everything else on their own.
 
 Recipe (the paper's experiment, Sec. III, used a FEM-reduced K that is not
 available; these synthetic matrices stand in for it):
@@ -241,12 +241,13 @@ def config_precision(nrhs: int = 64, with_c: bool = False) -> Instance:
 BATCH_GRIDS = ((2, 2, 2), (3, 3, 2), (4, 4, 2))
 
 
-def config_batch(count: int = 32, nrhs: int = 16, size_range=(100, 500)) -> list:
+def config_batch(count: int = 32, nrhs: int = 16, size_range=(100, 500), indices=None) -> list:
     """Frequency sweep: instance k has f_k = 0.5 + 1.5 k/31 and a grid drawn
-    uniformly from BATCH_GRIDS."""
+    uniformly from BATCH_GRIDS.  indices: build only these instances of the
+    32 (else the first count)."""
     seqs = np.random.SeedSequence(3).spawn(32)
     out = []
-    for k in range(count):
+    for k in (range(count) if indices is None else [int(i) for i in indices]):
         rng = np.random.Generator(np.random.PCG64(seqs[k]))
         g = BATCH_GRIDS[int(rng.integers(0, len(BATCH_GRIDS)))]
         f = 0.5 + 1.5 * k / 31.0

@@ -197,6 +197,37 @@ def test_matvec_and_knorm_match_dense():
         np.abs(A).sum(axis=1).max(), rel=1e-14)
 
 
+def test_backward_error_against_dense_definition():
+    # eta_inf = ||b - K x||_inf / (||K||_inf ||x||_inf + ||b||_inf) per column
+    # (the normwise backward error that certifies every solution), evaluated
+    # by hand on the dense assembled K with a residual planted exactly: x is
+    # random, b = K x + r with a known r per column, so the expected value is
+    # fixed before the oracle runs.  An inflated or deflated numerator or
+    # denominator (a wrong norm of K, x or b) moves eta by far more than the
+    # tolerance.
+    inst = _small((3, 3, 2), 3, 9, 41, nrhs=4)
+    A = dense_ref.dense_K(inst.sizes, inst.pairs, inst.K)
+    rng = np.random.default_rng(17)
+    X = (rng.standard_normal(inst.B.shape) + 1j * rng.standard_normal(inst.B.shape)) / np.sqrt(2)
+    R = np.zeros_like(X)
+    for j in range(X.shape[0]):
+        R[j, rng.integers(inst.N)] = (0.05 + 0.1 * j) * np.exp(1j * rng.uniform(0, 2 * np.pi))
+    B = (A @ X.T).T + R
+    knorm = np.linalg.norm(A, np.inf)
+    want = np.abs(R).max(axis=1) / (knorm * np.abs(X).max(axis=1) + np.abs(B).max(axis=1))
+    got = oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, B)
+    assert np.allclose(got, want, rtol=1e-12, atol=0), (got, want)
+    # the planted eta is far from the values a wrong denominator would give
+    alt = np.abs(R).max(axis=1) / (2 * knorm * np.abs(X).max(axis=1) + np.abs(B).max(axis=1))
+    assert np.all(np.abs(alt / want - 1) > 1e-3)
+    # a given ||K||_inf is used as given
+    got2 = oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, B, knorm_inf=2 * knorm)
+    assert np.allclose(got2, alt, rtol=1e-12, atol=0)
+    # an exact solution has eta at rounding level
+    Xe = np.linalg.solve(A, inst.B.T).T
+    assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, Xe, inst.B).max() <= 1e-15
+
+
 def test_special_single_interface():
     # one interface: the method is a dense LDL^T of one block
     inst = gen.make_instance((2, 1, 1), 40, gen.COEF_PLAIN, 1, 5)
