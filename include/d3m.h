@@ -96,7 +96,10 @@ typedef struct {
                            the K buffer: a stored off-diagonal entry also moves its mirror
                            (x2), a diagonal block is read from its lower triangle (strict
                            lower x2, diagonal x1, upper 0); 0: the symmetric block gradient */
-  int32_t reserved;
+  int32_t pivot;        /* 1: Bunch-Kaufman pivoting (1x1 and 2x2 pivots, the sytrf of Sec. II)
+                           inside each diagonal tile of at most `tile` unknowns; the block
+                           pattern and the task DAG are unchanged.  No FP64 re-factoring of
+                           tiles then.  0: no pivoting (the stated method) */
 } d3m_options;
 
 typedef struct {
@@ -164,25 +167,51 @@ d3m_status d3m_workspace_bytes(d3m_plan plan, d3m_precision prec, int32_t nrhs_m
 d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size_t bytes,
                            int32_t nrhs_max, const d3m_options* opt, d3m_factor* out);
 /* Factor K (c128 layout above) on the stream: scatter/convert, then one
- * persistent launch of the elimination DAG. */
+ * persistent launch of the elimination DAG -- Sec. II, the dual
+ * factorization: per nonzero block of K a dense factorization of the
+ * diagonal block (the sytrf-like LDL^T, here without pivoting), dense
+ * triangular solves (triSolve) of the blocks below it and dense updates
+ * (GEMM) of the blocks it reaches, ordered by the task graph of Fig. 1(c).
+ * Numerical outcomes (a zero or non-finite pivot) go to d3m_status_sync. */
 d3m_status d3m_factorize(d3m_factor f, const void* dev_K, d3m_stream stream);
-/* X = K^{-1} B for nrhs <= nrhs_max columns.  D3M_C64_IR: FP32 solves with
- * FP64 residuals r = B - K X on the original K and FP64 updates until
- * eta_inf <= tol; D3M_C128: FP64 solve plus one certifying residual. */
+/* X = K^{-1} B for nrhs <= nrhs_max columns -- Sec. II, the dual solution
+ * with the factors (block forward, diagonal and backward solves).
+ * D3M_C128: FP64 solve plus one certifying FP64 residual.  D3M_C64_IR (not
+ * in the paper; classical mixed-precision iterative refinement): FP32 solves
+ * with FP64 residuals r = B - K X on the original K and FP64 updates until
+ * the normwise backward error eta_inf = ||r||/(||K|| ||x|| + ||b||) of every
+ * column is <= tol.  B and X are caller device buffers (layout above, may
+ * not overlap); errors as for every call. */
 d3m_status d3m_solve(d3m_factor f, const void* dev_K, const void* dev_B, void* dev_X,
                      int32_t nrhs, int64_t ld, d3m_stream stream);
-/* Adjoint with the same factors (K = K^T): Lambda = K^{-1} G and
- * dK = -sym(Lambda X^T) on K's block pattern, summed over columns, with
- * sym(A) = (A + A^T)/2 (holomorphic convention: for J = sum_k Re(c_k^T x_k)
- * pass G = C).  X is the solution of the forward solve. */
+/* Adjoint with the same factors.  Not in the paper (which differentiates
+ * nothing): it is the adjoint of the linear solve x = K^{-1} b.  For a real
+ * objective J(x), dJ/db = K^{-T} G = K^{-1} G because K = K^T, so the solve
+ * above yields Lambda = K^{-1} G with no second factorization, and
+ * dJ/dK = -Lambda X^T restricted to K's block pattern and symmetrized:
+ * dK = -sym(Lambda X^T), sym(A) = (A + A^T)/2, summed over columns
+ * (holomorphic convention: for J = sum_k Re(c_k^T x_k) pass G = C).  With
+ * d3m_options.dk_stored the values are weighted per stored entry instead.
+ * X is the solution of the forward solve; dK (K's layout) may be NULL. */
 d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const void* dev_G,
                        void* dev_Lambda, void* dev_dK, int32_t nrhs, int64_t ld, d3m_stream stream);
-/* Wait for the factor's last stream and report numerical outcomes. */
+/* Wait for the factor's last stream and report numerical outcomes, in the
+ * manner of LAPACK's info argument (not from the paper): the first bad
+ * pivot's user row, refinement steps and eta, FP64 re-factors, DAG times. */
 d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out);
 /* Copy one factor block to host memory as c128, column-major: (J == I) the
  * diagonal block of I (L strictly below the diagonal, D on it), otherwise
  * L_JI (n_J x n_I) for J in S_I.  Synchronous; for tests and inspection. */
 d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out);
+/* With d3m_options.pivot: the interchanges of user interface I after
+ * d3m_factorize -- perm[i] (n_I) is the original index inside I of the
+ * unknown at position i (each diagonal tile permuted inside itself) -- and
+ * D's off-diagonal entries as c128 (doff[i] = D(i+1, i) when a 2x2 pivot
+ * starts at i, else 0).  Synchronous; for tests and inspection.  The factor
+ * blocks (d3m_factor_block) hold the factor in LAPACK's product form: rows
+ * of a tile in columns left of it keep their original order, and a 2x2
+ * pivot at i keeps D(i+1, i) in the slot of L(i+1, i), which is zero. */
+d3m_status d3m_factor_pivots(d3m_factor f, int32_t I, int32_t* perm, void* doff_host);
 /* Diagnostics: record, for every ticket of the following DAG launches, four
  * int64 values {taken, dependencies met, done, workgroup} (times on the
  * device's 100 MHz constant clock) into dev_buf: factor launches in the
@@ -197,8 +226,10 @@ d3m_status d3m_factor_tasks(d3m_factor f, int32_t solve, int32_t* kinds, int32_t
 void d3m_factor_destroy(d3m_factor f);
 
 /* Batching: many bound factors (their own plans and workspaces) run as one
- * persistent launch per phase.  The batch keeps its merged task tables in
- * dev_ws (size from d3m_batch_workspace_bytes). */
+ * persistent launch per phase -- the task graphs of independent problems
+ * (a frequency sweep) merged and list-scheduled together, as Sec. II
+ * schedules one weighted B-DAG onto the processors.  The batch keeps its
+ * merged task tables in dev_ws (size from d3m_batch_workspace_bytes). */
 d3m_status d3m_batch_workspace_bytes(int32_t ninst, const d3m_factor* f, size_t* bytes);
 d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, size_t bytes,
                             d3m_batch* out);

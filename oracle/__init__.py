@@ -48,6 +48,10 @@ def _lib():
         lib.orc_factor.argtypes = [ctypes.c_void_p, _f64p]
         lib.orc_get_block.restype = ctypes.c_int32
         lib.orc_get_block.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _f64p]
+        lib.orc_factor_bk.restype = ctypes.c_int64
+        lib.orc_factor_bk.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int32]
+        lib.orc_get_pivots.restype = ctypes.c_int32
+        lib.orc_get_pivots.argtypes = [ctypes.c_void_p, ctypes.c_int32, _i32p, _f64p]
         lib.orc_solve.restype = None
         lib.orc_solve.argtypes = [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int32]
         lib.orc_matvec.restype = None
@@ -138,6 +142,26 @@ class OraclePlan:
         r = int(_lib().orc_factor(self._h, _p(K.view(np.float64), _f64p)))
         self.pivot_index = None if r < 0 else r
         return r
+
+    def factor_bk(self, K, tile: int = 128) -> int:
+        """Factor with Bunch-Kaufman pivoting restricted to segments of `tile`
+        unknowns of each interface.  Returns -1, or the global row of the
+        first zero pivot column."""
+        K = _c128(K)
+        r = int(_lib().orc_factor_bk(self._h, _p(K.view(np.float64), _f64p), int(tile)))
+        self.pivot_index = None if r < 0 else r
+        return r
+
+    def pivots(self, I: int):
+        """(perm, doff) of interface I after factor_bk: internal position ->
+        original index inside I, and D's off-diagonal entries (doff[k] =
+        D(k+1, k) when a 2x2 pivot starts at k, else 0)."""
+        n = int(self.sizes[I])
+        perm = np.zeros(n, dtype=np.int32)
+        doff = np.zeros(n, dtype=np.complex128)
+        if _lib().orc_get_pivots(self._h, int(I), _p(perm, _i32p), _p(doff.view(np.float64), _f64p)) != 0:
+            raise ValueError("no pivots: factor with factor_bk")
+        return perm, doff
 
     def block(self, J: int, I: int) -> np.ndarray:
         nJ, nI = int(self.sizes[J]), int(self.sizes[I])

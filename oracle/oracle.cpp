@@ -106,6 +106,13 @@ struct Plan {
   std::vector<std::vector<cplx>> Ld;
   std::vector<std::vector<std::vector<cplx>>> Lo;
   bool factored = false;
+  // with in-block pivoting (orc_factor_bk): segment length, and per
+  // interface the permutation (internal position -> original index inside
+  // the interface) and D's off-diagonal entries (doff[k] = D(k+1, k) when a
+  // 2x2 pivot starts at k, else 0)
+  int pivot_tile = 0;
+  std::vector<std::vector<int32_t>> perm;
+  std::vector<std::vector<cplx>> doff;
 };
 
 }  // namespace
@@ -389,8 +396,14 @@ int32_t orc_get_block(void* h, int32_t J, int32_t I, double* out) {
 // Block solve with the factor (Sec. II, dual solution): forward
 // y = L^{-1} P b, diagonal z = D^{-1} y, backward x = P^T L^{-T} z.
 // B and X hold m right-hand sides, each a contiguous N-vector.
+void orc_solve_bk(Plan* p, const double* Bd, double* Xd, int32_t m);
+
 void orc_solve(void* h, const double* Bd, double* Xd, int32_t m) {
   Plan* p = (Plan*)h;
+  if (p->pivot_tile > 0) {
+    orc_solve_bk(p, Bd, Xd, m);
+    return;
+  }
   int nb = p->nb;
   auto& n = p->n;
   const int64_t N = p->row0[nb];
@@ -509,3 +522,374 @@ void orc_grad_K(int32_t nb, const int32_t* sizes, int64_t npair, const int32_t* 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- in-block pivoting
+// The dense factorization named in Sec. II is LAPACK's sytrf: a symmetric
+// indefinite LDL^T with Bunch-Kaufman pivoting (1x1 and 2x2 pivots chosen
+// by comparing magnitudes, Bunch & Kaufman 1977, alpha = (1 + sqrt(17))/8).
+// Here the pivot search is restricted to segments of `tile` consecutive
+// unknowns of one interface (the last segment shorter), so the block pattern
+// and the elimination order are unchanged.  Per interface I, in elimination
+// order, and per segment c of I in order:
+//   (i)   Bunch-Kaufman on the segment's diagonal block A_cc, with symmetric
+//         interchanges inside the segment (rows of the segment's already
+//         computed columns included):  P_c A_cc P_c^T = L_cc D_c L_cc^T;
+//   (ii)  every row r below the segment in the block column (later segments
+//         of I and the blocks J in S_I) has its columns permuted by P_c, then
+//         W_rc = A_rc L_cc^{-T} and L_rc = W_rc D_c^{-1};
+//   (iii) the later columns of the block column: A_rs -= W_rc L_sc^T;
+// then the Schur update of the later blocks, A_JK -= W_JI L_KI^T with
+// W_JI = L_JI D_I.  Rows of a segment in columns left of it keep their
+// original order (LAPACK's product form P(1) L(1) P(2) L(2) ...): the solve
+// permutes the vector when it reaches the segment.  Magnitudes are compared
+// as |re| + |im|, as LAPACK's complex sytrf does.
+namespace {
+
+double cabs1(cplx z) { return std::fabs(z.real()) + std::fabs(z.imag()); }
+
+// one interface's block column: the diagonal block A (n x n, lower triangle
+// used) and the blocks below it; element (r, c) of block u at blk[u][r + c*rows[u]]
+struct Column {
+  int n;
+  cplx* A;
+  std::vector<cplx*> blk;
+  std::vector<int> rows;
+};
+
+// symmetric interchange of positions a < b inside the segment [t0, t1) of
+// the diagonal block, lower storage; only the segment's rows and columns
+// (and the columns of the rows below it) move.
+void seg_swap(Column& col, int t0, int t1, int a, int b, std::vector<int32_t>& perm) {
+  const int n = col.n;
+  cplx* A = col.A;
+  auto at = [&](int i, int j) -> cplx& { return A[i + (size_t)j * n]; };
+  for (int j = t0; j < a; ++j) std::swap(at(a, j), at(b, j));        // computed columns of the segment
+  for (int j = a + 1; j < b; ++j) std::swap(at(j, a), at(b, j));     // between a and b
+  for (int i = b + 1; i < t1; ++i) std::swap(at(i, a), at(i, b));    // below b inside the segment
+  std::swap(at(a, a), at(b, b));
+  for (int i = t1; i < n; ++i) std::swap(at(i, a), at(i, b));        // rows below: columns a, b
+  for (size_t u = 0; u < col.blk.size(); ++u)
+    for (int r = 0; r < col.rows[u]; ++r)
+      std::swap(col.blk[u][r + (size_t)a * col.rows[u]], col.blk[u][r + (size_t)b * col.rows[u]]);
+  std::swap(perm[a], perm[b]);
+}
+
+// Factor one block column with segment-restricted Bunch-Kaufman; returns -1
+// or the position (inside the interface) of a pivot column that is zero.
+int factor_column_bk(Column& col, int tile, std::vector<int32_t>& perm, std::vector<cplx>& doff) {
+  const int n = col.n;
+  const double alpha = (1.0 + std::sqrt(17.0)) / 8.0;
+  cplx* A = col.A;
+  auto at = [&](int i, int j) -> cplx& { return A[i + (size_t)j * n]; };
+  perm.resize(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  doff.assign(n, cplx(0));
+  int bad = -1;
+  for (int t0 = 0; t0 < n; t0 += tile) {
+    const int t1 = std::min(n, t0 + tile);
+    // (i) the segment's diagonal block; L_cc overwrites its strict lower part
+    std::vector<int> step(t1 - t0, 0);  // 1 or 2 at the first column of a pivot
+    int k = t0;
+    while (k < t1) {
+      const double akk = cabs1(at(k, k));
+      int imax = k;
+      double colmax = 0;
+      for (int i = k + 1; i < t1; ++i)
+        if (cabs1(at(i, k)) > colmax) { colmax = cabs1(at(i, k)); imax = i; }
+      int kstep = 1, kp = k;
+      if (std::max(akk, colmax) == 0.0) {
+        if (bad < 0) bad = k;   // a zero column: recorded, factorization goes on
+      } else if (akk >= alpha * colmax) {
+      } else {
+        double rowmax = 0;
+        for (int j = k; j < imax; ++j) rowmax = std::max(rowmax, cabs1(at(imax, j)));
+        for (int i = imax + 1; i < t1; ++i) rowmax = std::max(rowmax, cabs1(at(i, imax)));
+        if (akk >= alpha * colmax * (colmax / rowmax)) {
+        } else if (cabs1(at(imax, imax)) >= alpha * rowmax) {
+          kp = imax;
+        } else {
+          kp = imax;
+          kstep = 2;
+        }
+      }
+      const int kk = k + kstep - 1;
+      if (kp != kk) seg_swap(col, t0, t1, kk, kp, perm);
+      step[k - t0] = kstep;
+      if (kstep == 1) {
+        const cplx d = at(k, k);
+        if (d == cplx(0) || !std::isfinite(d.real()) || !std::isfinite(d.imag())) {
+          if (bad < 0) bad = k;
+          k += 1;
+          continue;
+        }
+        // trailing block of the segment: A_ij -= A_ik A_jk / d, then l_ik = A_ik / d
+        for (int j = k + 1; j < t1; ++j)
+          for (int i = j; i < t1; ++i) at(i, j) -= at(i, k) * at(j, k) / d;
+        for (int i = k + 1; i < t1; ++i) at(i, k) /= d;
+      } else {
+        // 2x2 pivot [a b; b c]: [l_ik l_i,k+1] = [A_ik A_i,k+1] D^{-1}
+        const cplx a = at(k, k), b = at(k + 1, k), c = at(k + 1, k + 1);
+        const cplx det = a * c - b * b;
+        if (det == cplx(0) || !std::isfinite(det.real()) || !std::isfinite(det.imag())) {
+          if (bad < 0) bad = k;
+        } else {
+          const cplx i11 = c / det, i12 = -b / det, i22 = a / det;
+          for (int j = k + 2; j < t1; ++j)
+            for (int i = j; i < t1; ++i) {
+              const cplx li0 = at(i, k) * i11 + at(i, k + 1) * i12, li1 = at(i, k) * i12 + at(i, k + 1) * i22;
+              at(i, j) -= li0 * at(j, k) + li1 * at(j, k + 1);
+            }
+          for (int i = k + 2; i < t1; ++i) {
+            const cplx w0 = at(i, k), w1 = at(i, k + 1);
+            at(i, k) = w0 * i11 + w1 * i12;
+            at(i, k + 1) = w0 * i12 + w1 * i22;
+          }
+          doff[k] = b;   // D(k+1, k); L(k+1, k) = 0 (the slot keeps b)
+        }
+      }
+      k += kstep;
+    }
+    // (ii) rows below the segment: w solves w L_cc^T = a (forward over the
+    // segment's columns), then l = w D_c^{-1}; w kept for (iii)
+    auto below = [&](cplx* row, int64_t stride, cplx* wout) {
+      for (int c2 = t0; c2 < t1; ++c2) {
+        cplx t = row[(size_t)c2 * stride];
+        for (int q = t0; q < c2; ++q)
+          if (!(q + 1 == c2 && step[q - t0] == 2)) t -= wout[q - t0] * at(c2, q);  // (k+1, k) of a 2x2 holds D
+        wout[c2 - t0] = t;
+      }
+      for (int c2 = t0; c2 < t1;) {
+        if (step[c2 - t0] == 2) {
+          const cplx a = at(c2, c2), b = doff[c2], c = at(c2 + 1, c2 + 1), det = a * c - b * b;
+          const cplx w0 = wout[c2 - t0], w1 = wout[c2 + 1 - t0];
+          row[(size_t)c2 * stride] = (w0 * c - w1 * b) / det;
+          row[(size_t)(c2 + 1) * stride] = (w1 * a - w0 * b) / det;
+          c2 += 2;
+        } else {
+          row[(size_t)c2 * stride] = wout[c2 - t0] / at(c2, c2);
+          c2 += 1;
+        }
+      }
+    };
+    const int ts = t1 - t0;
+    std::vector<cplx> Wd((size_t)(n - t1) * ts);  // rows t1..n of the diagonal block
+    std::vector<std::vector<cplx>> Wb(col.blk.size());
+#pragma omp parallel for schedule(static)
+    for (int i = t1; i < n; ++i) below(&at(i, 0), n, &Wd[(size_t)(i - t1) * ts]);
+    for (size_t u = 0; u < col.blk.size(); ++u) {
+      Wb[u].resize((size_t)col.rows[u] * ts);
+#pragma omp parallel for schedule(static)
+      for (int r = 0; r < col.rows[u]; ++r) below(col.blk[u] + r, col.rows[u], &Wb[u][(size_t)r * ts]);
+    }
+    // (iii) later columns of the block column: A_rs -= W_rc L_sc^T (lower part
+    // of the diagonal block, all rows of the blocks below)
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int j = t1; j < n; ++j) {
+      for (int i = j; i < n; ++i) {
+        cplx t = 0;
+        for (int q = 0; q < ts; ++q) t += Wd[(size_t)(i - t1) * ts + q] * at(j, t0 + q);
+        at(i, j) -= t;
+      }
+      for (size_t u = 0; u < col.blk.size(); ++u)
+        for (int r = 0; r < col.rows[u]; ++r) {
+          cplx t = 0;
+          for (int q = 0; q < ts; ++q) t += Wb[u][(size_t)r * ts + q] * at(j, t0 + q);
+          col.blk[u][r + (size_t)j * col.rows[u]] -= t;
+        }
+    }
+  }
+  return bad;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Numeric factorization with segment-restricted Bunch-Kaufman pivoting (see
+// above).  Returns -1, or the global row (user numbering, original index
+// inside the interface) of the first zero pivot column.
+int64_t orc_factor_bk(void* h, const double* Kd, int32_t tile) {
+  Plan* p = (Plan*)h;
+  const cplx* K = reinterpret_cast<const cplx*>(Kd);
+  const int nb = p->nb;
+  auto& n = p->n;
+  p->pivot_tile = tile;
+  p->perm.assign(nb, {});
+  p->doff.assign(nb, {});
+  p->Ld.assign(nb, {});
+  p->Lo.assign(nb, {});
+  for (int I = 0; I < nb; ++I) {
+    p->Ld[I].assign((size_t)n[I] * n[I], cplx(0));
+    const cplx* src = K + p->koff[I];
+    for (int c = 0; c < n[I]; ++c)
+      for (int r = c; r < n[I]; ++r) p->Ld[I][r + (size_t)c * n[I]] = src[r + (size_t)c * n[I]];
+    p->Lo[I].resize(p->S[I].size());
+    for (size_t u = 0; u < p->S[I].size(); ++u) p->Lo[I][u].assign((size_t)n[p->S[I][u]] * n[I], cplx(0));
+  }
+  auto find_slot = [&](int I, int J) -> int {
+    for (size_t u = 0; u < p->S[I].size(); ++u)
+      if (p->S[I][u] == J) return (int)u;
+    return -1;
+  };
+  for (size_t k = 0; k < p->pairs.size(); ++k) {
+    int a = p->pairs[k][0], b = p->pairs[k][1];
+    const cplx* src = K + p->koff[nb + k];
+    if (p->pos[a] > p->pos[b]) {
+      auto& dst = p->Lo[b][find_slot(b, a)];
+      for (size_t e = 0; e < (size_t)n[a] * n[b]; ++e) dst[e] = src[e];
+    } else {
+      auto& dst = p->Lo[a][find_slot(a, b)];
+      for (int c = 0; c < n[b]; ++c)
+        for (int r = 0; r < n[a]; ++r) dst[c + (size_t)r * n[b]] = src[r + (size_t)c * n[a]];
+    }
+  }
+  for (int k = 0; k < nb; ++k) {
+    const int I = p->order[k], nI = n[I];
+    Column col;
+    col.n = nI;
+    col.A = p->Ld[I].data();
+    for (size_t u = 0; u < p->S[I].size(); ++u) {
+      col.blk.push_back(p->Lo[I][u].data());
+      col.rows.push_back(n[p->S[I][u]]);
+    }
+    const int bad = factor_column_bk(col, tile, p->perm[I], p->doff[I]);
+    if (bad >= 0) return p->row0[I] + p->perm[I][bad];
+    // W_JI = L_JI D_I (D block diagonal with 1x1 and 2x2 blocks)
+    auto& S = p->S[I];
+    const std::vector<cplx>& A = p->Ld[I];
+    std::vector<std::vector<cplx>> W(S.size());
+    for (size_t u = 0; u < S.size(); ++u) {
+      const int nJ = n[S[u]];
+      const std::vector<cplx>& Lb = p->Lo[I][u];
+      W[u].assign((size_t)nJ * nI, cplx(0));
+      for (int c = 0; c < nI; ++c) {
+        const cplx dcc = A[c + (size_t)c * nI];
+        const cplx lo = c > 0 ? p->doff[I][c - 1] : cplx(0);   // D(c, c-1)
+        const cplx hi = c + 1 < nI ? p->doff[I][c] : cplx(0);  // D(c+1, c)
+        for (int r = 0; r < nJ; ++r) {
+          cplx t = Lb[r + (size_t)c * nJ] * dcc;
+          if (lo != cplx(0)) t += Lb[r + (size_t)(c - 1) * nJ] * lo;
+          if (hi != cplx(0)) t += Lb[r + (size_t)(c + 1) * nJ] * hi;
+          W[u][r + (size_t)c * nJ] = t;
+        }
+      }
+    }
+    // Schur update A_JK -= W_JI L_KI^T, J, K in S_I, pos(J) >= pos(K)
+    for (size_t u = 0; u < S.size(); ++u) {
+      const int J = S[u], nJ = n[J];
+      for (size_t v = 0; v <= u; ++v) {
+        const int Kb = S[v], nK = n[Kb];
+        const std::vector<cplx>& Lk = p->Lo[I][v];
+        cplx* dst = (u == v) ? p->Ld[J].data() : p->Lo[Kb][find_slot(Kb, J)].data();
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int c = 0; c < nK; ++c) {
+          const int r0 = (u == v) ? c : 0;
+          for (int q = 0; q < nI; ++q) {
+            const cplx l = Lk[c + (size_t)q * nK];
+            const cplx* w = W[u].data() + (size_t)q * nJ;
+            cplx* d = dst + (size_t)c * nJ;
+            for (int r = r0; r < nJ; ++r) d[r] -= w[r] * l;
+          }
+        }
+      }
+    }
+  }
+  p->factored = true;
+  return -1;
+}
+
+// Pivots of interface I after orc_factor_bk: perm (n_I: internal position ->
+// original index inside I) and D's off-diagonal entries (n_I complex,
+// doff[k] = D(k+1, k) when a 2x2 pivot starts at k).  Returns 0, or -1 when
+// the factor has no pivots.
+int32_t orc_get_pivots(void* h, int32_t I, int32_t* perm, double* doff) {
+  Plan* p = (Plan*)h;
+  if (p->pivot_tile <= 0 || I < 0 || I >= p->nb) return -1;
+  std::memcpy(perm, p->perm[I].data(), sizeof(int32_t) * p->n[I]);
+  std::memcpy(doff, p->doff[I].data(), sizeof(cplx) * p->n[I]);
+  return 0;
+}
+
+}  // extern "C"
+
+// Solve with the pivoted factor: the segments' permutations are applied to
+// the vector when the forward pass reaches a segment and undone when the
+// backward pass leaves it (the product form of the factor).
+void orc_solve_bk(Plan* p, const double* Bd, double* Xd, int32_t m) {
+  const int nb = p->nb;
+  auto& n = p->n;
+  const int64_t N = p->row0[nb];
+  const int tile = p->pivot_tile;
+  const cplx* B = reinterpret_cast<const cplx*>(Bd);
+  cplx* X = reinterpret_cast<cplx*>(Xd);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int rhs = 0; rhs < m; ++rhs) {
+    std::vector<cplx> b(B + (size_t)rhs * N, B + (size_t)(rhs + 1) * N);
+    // forward: y = L^{-1} (P b), segment by segment
+    for (int k = 0; k < nb; ++k) {
+      const int I = p->order[k], nI = n[I];
+      cplx* bi = b.data() + p->row0[I];
+      const std::vector<cplx>& A = p->Ld[I];
+      const std::vector<int32_t>& pm = p->perm[I];
+      for (int t0 = 0; t0 < nI; t0 += tile) {
+        const int t1 = std::min(nI, t0 + tile);
+        std::vector<cplx> tmp(bi + t0, bi + t1);
+        for (int i = t0; i < t1; ++i) bi[i] = tmp[pm[i] - t0];
+        for (int q = t0; q < t1; ++q)
+          for (int r = q + 1; r < nI; ++r)
+            if (!(r == q + 1 && p->doff[I][q] != cplx(0))) bi[r] -= A[r + (size_t)q * nI] * bi[q];
+      }
+      for (size_t u = 0; u < p->S[I].size(); ++u) {
+        const int J = p->S[I][u], nJ = n[J];
+        cplx* bj = b.data() + p->row0[J];
+        const std::vector<cplx>& L = p->Lo[I][u];
+        for (int q = 0; q < nI; ++q)
+          for (int r = 0; r < nJ; ++r) bj[r] -= L[r + (size_t)q * nJ] * bi[q];
+      }
+    }
+    // diagonal: z = D^{-1} y with 1x1 and 2x2 blocks
+    for (int I = 0; I < nb; ++I) {
+      cplx* bi = b.data() + p->row0[I];
+      const std::vector<cplx>& A = p->Ld[I];
+      for (int r = 0; r < n[I];) {
+        if (p->doff[I][r] != cplx(0)) {
+          const cplx a = A[r + (size_t)r * n[I]], bb = p->doff[I][r], c = A[(r + 1) + (size_t)(r + 1) * n[I]];
+          const cplx det = a * c - bb * bb, y0 = bi[r], y1 = bi[r + 1];
+          bi[r] = (c * y0 - bb * y1) / det;
+          bi[r + 1] = (a * y1 - bb * y0) / det;
+          r += 2;
+        } else {
+          bi[r] /= A[r + (size_t)r * n[I]];
+          r += 1;
+        }
+      }
+    }
+    // backward: x = P^T L^{-T} z, segments in reverse
+    for (int k = nb - 1; k >= 0; --k) {
+      const int I = p->order[k], nI = n[I];
+      cplx* bi = b.data() + p->row0[I];
+      for (size_t u = 0; u < p->S[I].size(); ++u) {
+        const int J = p->S[I][u], nJ = n[J];
+        const cplx* xj = b.data() + p->row0[J];
+        const std::vector<cplx>& L = p->Lo[I][u];
+        for (int q = 0; q < nI; ++q)
+          for (int r = 0; r < nJ; ++r) bi[q] -= L[r + (size_t)q * nJ] * xj[r];
+      }
+      const std::vector<cplx>& A = p->Ld[I];
+      const std::vector<int32_t>& pm = p->perm[I];
+      const int nseg = (nI + tile - 1) / tile;
+      for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int t0 = sgi * tile, t1 = std::min(nI, t0 + tile);
+        // later segments are final (original order): t_c -= L_rc^T x_r
+        for (int q = t0; q < t1; ++q)
+          for (int r = t1; r < nI; ++r) bi[q] -= A[r + (size_t)q * nI] * bi[r];
+        for (int q = t1 - 1; q >= t0; --q)
+          for (int r = q + 1; r < t1; ++r)
+            if (!(r == q + 1 && p->doff[I][q] != cplx(0))) bi[q] -= A[r + (size_t)q * nI] * bi[r];
+        std::vector<cplx> tmp(bi + t0, bi + t1);
+        for (int i = t0; i < t1; ++i) bi[pm[i]] = tmp[i - t0];
+      }
+    }
+    std::memcpy(X + (size_t)rhs * N, b.data(), sizeof(cplx) * N);
+  }
+}

@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("ir_host_sync", ctypes.c_int32),
                 ("growth_dmin", ctypes.c_double), ("growth_lmax", ctypes.c_double),
                 ("fallback", ctypes.c_int32), ("timing", ctypes.c_int32), ("dk_stored", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("pivot", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -87,6 +87,7 @@ SIGNATURES = {
     "d3m_status_sync": (_i32, [_vp, ctypes.POINTER(RunInfo)]),
     "d3m_factor_block": (_i32, [_vp, _i32, _i32, _vp]),
     "d3m_factor_destroy": (None, [_vp]),
+    "d3m_factor_pivots": (_i32, [_vp, _i32, _i32p, _vp]),
     "d3m_factor_set_trace": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "d3m_factor_tasks": (_i32, [_vp, _i32, _i32p, _i32p, _i32p, _i32p]),
     "d3m_batch_workspace_bytes": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]),
@@ -209,19 +210,20 @@ class Factor:
 
     def __init__(self, plan: Plan, precision: int = C128, nrhs_max: int = 1, tol: float = 1e-10,
                  max_iter: int = 10, ir_host_sync: bool = False, timing: bool = False, growth_dmin: float = 0.0,
-                 growth_lmax: float = 0.0, fallback: bool = True, dk_stored: bool = False, device=None):
+                 growth_lmax: float = 0.0, fallback: bool = True, dk_stored: bool = False, device=None,
+                 pivot: bool = False):
         import torch
         self.plan = plan
         self.precision = int(precision)
         self.nrhs_max = int(nrhs_max)
+        opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), float(growth_dmin), float(growth_lmax),
+                       0 if fallback else -1, int(bool(timing)), int(bool(dk_stored)), int(bool(pivot)))
+        h = _vp()
         nbytes = plan.workspace_bytes(precision, nrhs_max)
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
         self._off = (-base) % 256
-        opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), float(growth_dmin), float(growth_lmax),
-                       0 if fallback else -1, int(bool(timing)), int(bool(dk_stored)), 0)
-        h = _vp()
         _check(lib().d3m_factor_bind(plan._h, self.precision, ctypes.c_void_p(base + self._off), nbytes,
                                      self.nrhs_max, ctypes.byref(opts), ctypes.byref(h)), "d3m_factor_bind")
         self._h = h
@@ -310,6 +312,15 @@ class Factor:
                "d3m_factor_tasks")
         return {"kind": kinds, "panel": panels, "mnk": mnk.reshape(n, 3)}
 
+    def pivots(self, I: int):
+        """(perm, doff) of user interface I of a pivoted factor (see d3m_factor_pivots)."""
+        n = int(self.plan.sizes[I])
+        perm = np.zeros(n, dtype=np.int32)
+        doff = np.zeros(n, dtype=np.complex128)
+        _check(lib().d3m_factor_pivots(self._h, int(I), _p32(perm), ctypes.c_void_p(doff.ctypes.data)),
+               "d3m_factor_pivots")
+        return perm, doff
+
     def block(self, J: int, I: int) -> np.ndarray:
         nJ, nI = int(self.plan.sizes[J]), int(self.plan.sizes[I])
         out = np.zeros(nJ * nI, dtype=np.complex128)
@@ -352,7 +363,7 @@ class Batch:
         arr = (_vp * n)(*[f._h for f in self.factors])
         b = ctypes.c_size_t()
         _check(lib().d3m_batch_workspace_bytes(n, arr, ctypes.byref(b)), "d3m_batch_workspace_bytes")
-        self.ws = torch.empty(b.value + 256, dtype=torch.uint8, device=self.factors[0].ws.device)
+        self.ws = torch.empty(b.value + 256, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
         off = (-self.ws.data_ptr()) % 256
         h = _vp()
         _check(lib().d3m_batch_create(n, arr, ctypes.c_void_p(self.ws.data_ptr() + off), b.value, ctypes.byref(h)),

@@ -26,7 +26,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout of one factor.
 struct Layout {
-  size_t L, LD, D, Linv, W, Z, X64, R64, P64, norms, ctrl, status, growth, counters, flags;
+  size_t L, LD, D, Linv, Ginv, Doff, ipiv, W, Z, X64, R64, P64, norms, ctrl, status, growth, counters, flags;
   size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, xsrc, iv;
   size_t kp, fills, rt, rptr, rblk, rsplit, nI, row0, prow0, perm, dkt;
   size_t total;
@@ -111,6 +111,9 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.LD = take(p.L_elems * es);
   l.D = take(p.N * es);
   l.Linv = take(p.Linv_elems * es);
+  l.Ginv = take(p.Linv_elems * es);  // used with pivoting only
+  l.Doff = take(p.N * es);
+  l.ipiv = take(p.N * sizeof(int32_t));
   l.W = take((size_t)p.N * nrhs_max * es * (1 + kSolveSlots));  // b and its extra accumulators
   l.Z = take((size_t)p.N * nrhs_max * es);
   l.X64 = take((size_t)p.N * nrhs_max * 16);
@@ -405,7 +408,11 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
   iv.N = p.N;
   iv.gdmin = (float)f->opt.growth_dmin;
   iv.glmax = (float)f->opt.growth_lmax;
-  iv.fallback = f->opt.fallback < 0 ? 0 : 1;
+  iv.pivot = f->opt.pivot ? 1 : 0;
+  iv.fallback = (f->opt.fallback < 0 || iv.pivot) ? 0 : 1;
+  iv.Ginv = f->ws + f->lay.Ginv;
+  iv.Doff = f->ws + f->lay.Doff;
+  iv.ipiv = f->at<int32_t>(f->lay.ipiv);
   bool ok = up(f->lay.ftasks, p.fdag.tasks.data(), p.fdag.tasks.size() * sizeof(Task)) &&
             up(f->lay.fsucc, p.fdag.succ.data(), p.fdag.succ.size() * 4) &&
             up(f->lay.fcnt, p.fdag.npred.data(), p.fdag.npred.size() * 4) &&
@@ -612,6 +619,35 @@ d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out) 
       o[2 * ((size_t)r + (size_t)c * nJ)] = re;
       o[2 * ((size_t)r + (size_t)c * nJ) + 1] = im;
     }
+  return D3M_OK;
+}
+
+d3m_status d3m_factor_pivots(d3m_factor f, int32_t I, int32_t* perm, void* doff_host) {
+  if (!f || !perm || !doff_host) return D3M_ERR_ARG;
+  const PlanImpl& p = f->plan->p;
+  if (I < 0 || I >= p.nb) return D3M_ERR_ARG;
+  if (!f->opt.pivot || !f->factored) return D3M_ERR_STATE;
+  HIPCHK(hipStreamSynchronize(f->last));
+  const Panel& P = p.panels[p.pos[I]];
+  const size_t es = f->prec == 0 ? 16 : 8;
+  std::vector<int32_t> ip(P.n);
+  std::vector<char> dof((size_t)P.n * es);
+  HIPCHK(hipMemcpy(ip.data(), f->at<int32_t>(f->lay.ipiv) + P.prow0, P.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(dof.data(), f->ws + f->lay.Doff + (size_t)P.prow0 * es, dof.size(), hipMemcpyDeviceToHost));
+  double* o = static_cast<double*>(doff_host);
+  for (int c = 0; c < P.nt; ++c) {
+    const Tile& T = p.tiles[P.tile0 + c];
+    for (int i = 0; i < T.sz; ++i) perm[T.r0 + i] = T.r0 + ip[T.r0 + i];
+  }
+  for (int i = 0; i < P.n; ++i) {
+    if (es == 16) {
+      o[2 * i] = reinterpret_cast<double*>(dof.data())[2 * i];
+      o[2 * i + 1] = reinterpret_cast<double*>(dof.data())[2 * i + 1];
+    } else {
+      o[2 * i] = reinterpret_cast<float*>(dof.data())[2 * i];
+      o[2 * i + 1] = reinterpret_cast<float*>(dof.data())[2 * i + 1];
+    }
+  }
   return D3M_OK;
 }
 

@@ -51,7 +51,7 @@ struct Task {
   int32_t aux;       // kind-specific (row tile / column tile index)
   int64_t a_off, b_off, c_off;
   int32_t succ_begin, nsucc;
-  int32_t pad0, pad1;
+  int32_t pad0, pad1;  // XUPD/FUPD: merged sources (count, first); FTILE/BTILE: end/start of the factor tile
 };
 static_assert(sizeof(Task) == 80, "Task layout");
 
@@ -104,7 +104,14 @@ struct InstView {
   int64_t N;
   float gdmin, glmax;  // fallback trigger (complex64 factor): |d| < gdmin max|A|, |l| > glmax
   int32_t fallback;    // 1: re-factor tripped diagonal tiles in FP64
-  int32_t pad;
+  int32_t pivot;       // 1: Bunch-Kaufman pivoting inside each diagonal tile
+  // with pivoting: Linv holds F = L^-1 P of each panel's diagonal block and
+  // Ginv holds D^-1 F (the same layout); Doff[r] = D(r+1, r) when a 2x2
+  // pivot starts at internal row r; ipiv[r] = original position inside the
+  // tile of the unknown at internal row r
+  void* Ginv;
+  void* Doff;
+  int32_t* ipiv;
 };
 
 // Arguments of one persistent DAG launch.

@@ -18,6 +18,7 @@
 #include "d3m_internal.h"
 #include "gemm_engine.h"
 #include "launch.h"
+#include "tile_bk.h"
 #include "tile_ldlt.h"
 
 namespace d3m {
@@ -29,6 +30,7 @@ template <typename T> struct Ctx {
   C* LD;  // L_rc D_c (written by the TRSM tasks)
   C* D;
   C* Li;
+  C* Gi;  // with pivoting: D^-1 L^-1 P of each diagonal block (Li then holds L^-1 P)
   C* W;
   C* Z;
   const InstView* iv;
@@ -76,6 +78,7 @@ template <typename T> __device__ __forceinline__ Ctx<T> uniform_ctx(const Ctx<T>
   c.LD = ufirst_ptr(a.LD);
   c.D = ufirst_ptr(a.D);
   c.Li = ufirst_ptr(a.Li);
+  c.Gi = ufirst_ptr(a.Gi);
   c.W = ufirst_ptr(a.W);
   c.Z = ufirst_ptr(a.Z);
   c.iv = ufirst_ptr(a.iv);
@@ -120,8 +123,15 @@ __device__ __noinline__ void task_fact(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
   const Tile tc = cx.iv->tiles[t.aux];
-  float* gr = cx.iv->growth ? cx.iv->growth + 2 * t.panel : nullptr;
   const Panel P = cx.iv->panels[t.panel];
+  if (cx.iv->pivot) {
+    typedef typename Cplx<T>::type C;
+    tile_bk<T, T>(cx.L + t.a_off, t.lda, t.m, cx.D + t.dofs, reinterpret_cast<C*>(cx.iv->Doff) + t.dofs,
+                  cx.iv->ipiv + t.dofs, cx.Li + tc.linv_off, cx.Gi + tc.linv_off, P.n, t.dofs, cx.iv->status,
+                  cx.lds);
+    return;
+  }
+  float* gr = cx.iv->growth ? cx.iv->growth + 2 * t.panel : nullptr;
   GrowthCheck gc;
   gc.on = sizeof(T) == 4 && cx.iv->fallback != 0;
   gc.dmin = cx.iv->gdmin;
@@ -138,12 +148,24 @@ __device__ __noinline__ void task_fact(const Ctx<T>& cx_, const Task& t_) {
 
 // L_rc = A_rc Linv_c^T D_c^-1, in place, and L_rc D_c = A_rc Linv_c^T into
 // LD at the same place (TK_TRSM)
+// With pivoting (F_c = L_cc^-1 P_c, G_c = D_c^-1 F_c, D_c with 2x2 blocks):
+// LD_rc = A_rc F_c^T and L_rc = A_rc G_c^T, two products of the same A.
 template <typename T>
 __device__ __noinline__ void task_trsm(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
   Acc<T, true> acc;
   acc.zero();
+  if (cx.iv->pivot) {
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
+                                        opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
+    gemm_store<T>(acc, t.m, t.n, outp<T>(cx.LD + t.a_off, 1, t.lda, (T)1, (T)0), cx.lds);
+    acc.zero();
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
+                                        opn<T>(cx.Gi + t.b_off, t.ldc), cx.lds);
+    gemm_store<T>(acc, t.m, t.n, outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0), cx.lds);
+    return;
+  }
   gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, t.k, opn<T>(cx.L + t.a_off, t.lda), nullptr,
                                       opn<T>(cx.Li + t.b_off, t.ldc), cx.lds);
   Out<T> o = outp<T>(cx.L + t.a_off, 1, t.lda, (T)1, (T)0);
@@ -232,9 +254,19 @@ __device__ __noinline__ void task_inv(const Ctx<T>& cx_, const Task& t_) {
                                     opn<T>(stage, n),
               cx.lds);
   gemm_store<T>(acc, tr.sz, tc.sz, outp<T>(Lb + tr.r0 + (int64_t)tc.r0 * n, 1, n, (T)-1, (T)0));
+  if (cx.iv->pivot) {
+    // G_rc = -G_rr Y (G = D^-1 F with F in place of Linv)
+    C* Gb = cx.Gi + P.ioff;
+    acc.zero();
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, tr.sz, tc.sz, tr.sz, opn<T>(Gb + tr.r0 + (int64_t)tr.r0 * n, n),
+                                        nullptr, opn<T>(stage, n), cx.lds);
+    gemm_store<T>(acc, tr.sz, tc.sz, outp<T>(Gb + tr.r0 + (int64_t)tc.r0 * n, 1, n, (T)-1, (T)0));
+  }
 }
 
-// forward, one tile: z_c = D_c^-1 sum_{p < r0_c + sz_c} Linv_II(c, p) b_p
+// forward, one tile: z_c = D_c^-1 sum_{p < r0_c + sz_c} Linv_II(c, p) b_p;
+// with pivoting z_c = sum_p G_II(c, p) b_p up to the end of the factor tile
+// (t.pad0 columns more: G's diagonal tiles are full)
 template <typename T>
 __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
@@ -242,6 +274,12 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
+  if (cx.iv->pivot) {
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, nr, t.k + t.pad0, opn<T>(cx.Gi + t.a_off, t.lda), nullptr,
+                                        opn<T>(cx.W + t.b_off * nr, nr), cx.lds);
+    gemm_store<T>(acc, t.m, nr, outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)1, (T)0));
+    return;
+  }
   gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda), nullptr,
                                     opn<T>(cx.W + t.b_off * nr, nr),
               cx.lds);
@@ -320,7 +358,9 @@ __device__ __noinline__ void task_bupd(const Ctx<T>& cx_, const Task& t_) {
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)-1, (T)1));
 }
 
-// backward, one tile: x_c = sum_{p >= r0_c} Linv_II(p, c) t_p
+// backward, one tile: x_c = sum_{p >= r0_c} Linv_II(p, c) t_p; with
+// pivoting (Linv holds F = L^-1 P, full in its diagonal tiles) the sum
+// starts t.pad0 rows earlier, at the factor tile's first row
 template <typename T>
 __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
@@ -328,8 +368,9 @@ __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   const int nr = cx.nrhs;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda, OP_T), nullptr,
-                                    opn<T>(cx.Z + t.b_off * nr, nr),
+  const int back = cx.iv->pivot ? t.pad0 : 0;
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, t.m, nr, t.k + back, opn<T>(cx.Li + t.a_off - back, t.lda, OP_T), nullptr,
+                                    opn<T>(cx.Z + (t.b_off - back) * nr, nr),
               cx.lds);
   gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)1, (T)0));
 }
@@ -343,6 +384,7 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
   cx.LD = reinterpret_cast<C*>(cx.iv->LD);
   cx.D = reinterpret_cast<C*>(cx.iv->D);
   cx.Li = reinterpret_cast<C*>(cx.iv->Linv);
+  cx.Gi = reinterpret_cast<C*>(cx.iv->Ginv);
   cx.W = reinterpret_cast<C*>(cx.iv->W);
   cx.Z = reinterpret_cast<C*>(cx.iv->Z);
   cx.lds = lds;
@@ -363,8 +405,8 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
 
 // the complex64 kernel also holds the FP64 re-factor of a tile
 template <typename T> constexpr int dag_lds_bytes() {
-  constexpr int a = tile_ldlt_lds_bytes<double>(), b = ge_lds_bytes_dma<T>();
-  return a > b ? a : b;
+  constexpr int a = tile_ldlt_lds_bytes<double>(), b = ge_lds_bytes_dma<T>(), c = tile_bk_lds_bytes<T>();
+  return (a > b ? a : b) > c ? (a > b ? a : b) : c;
 }
 
 // ---------------------------------------------------------------- the executor

@@ -651,6 +651,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   constexpr int kSolveTile = 64;
   std::vector<int> st0(nb + 1, 0);  // solve tiles of panel I: st0[I] .. st0[I+1]-1
   std::vector<std::pair<int, int>> stl;  // (r0, sz)
+  std::vector<std::pair<int, int>> stf;  // (first row, end) of the factor tile holding each solve tile
   for (int I = 0; I < nb; ++I) {
     const Panel& P = p.panels[I];
     for (int c = 0; c < P.nt; ++c) {
@@ -660,6 +661,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
         // even starts (16-byte aligned operand columns, as for the factor tiles)
         const int r0 = (T.sz * q / nt) & ~1, r1 = q + 1 == nt ? T.sz : (T.sz * (q + 1) / nt) & ~1;
         stl.push_back({T.r0 + r0, r1 - r0});
+        stf.push_back({T.r0, T.r0 + T.sz});
       }
     }
     st0[I + 1] = (int)stl.size();
@@ -748,6 +750,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       t.b_off = P.prow0;
       t.c_off = P.prow0 + r0;
       t.dofs = P.prow0 + r0;
+      t.pad0 = stf[c].second - (r0 + sz);  // with pivoting the sum runs to the factor tile's end
       std::vector<Access> ac{{kZKey | c, true}};
       for (int q = st0[I]; q < st0[I + 1]; ++q) ac.push_back({wkey(0, q), false});
       int id = sg.add(t, inpr, w_solve(sz, r0 + sz));
@@ -805,6 +808,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       t.a_off = PJ.ioff + r0 + (int64_t)r0 * PJ.n;
       t.b_off = PJ.prow0 + r0;
       t.c_off = PJ.prow0 + r0;
+      t.pad0 = r0 - stf[c].first;  // with pivoting the sum starts at the factor tile's first row
       std::vector<Access> ac{{wkey(0, c), true}};
       for (int q = st0[J]; q < st0[J + 1]; ++q) ac.push_back({kZKey | q, false});
       int id = sg.add(t, zpr, w_solve(sz, PJ.n - r0));

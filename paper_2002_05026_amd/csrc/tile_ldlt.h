@@ -113,6 +113,161 @@ template <typename T> __device__ __forceinline__ int tl_at(int i, int j) {
   return tl_blk(i >> 4, j >> 4) + (j & 15) * 16 + (i & 15);
 }
 
+// Linv = L^-1 of the unit lower tile held in S (lower block triangle; the
+// inverse X_b of each diagonal 16-block kept transposed in that block's
+// upper part, see tl_x), formed in place of L, then written out:
+//   linv(i, col(j)) = Linv(i, j),   col(j) = perm ? perm[j] : j,
+// zeros above the block diagonal.  With ginv (and D^-1 of the pivots: row
+// i of D^-1 holds dinv[i] at column i and dpart[i] at column prt[i], the
+// other row of a 2x2 pivot, or prt[i] = -1) also
+//   ginv(i, col(j)) = sum_i' D^-1(i, i') Linv(i', j).
+// Every thread of the workgroup calls.
+template <typename T, typename TS>
+__device__ __forceinline__ void tl_invert_store(D3M_LDS cpx<T>* S, int m, D3M_GLB cpx<TS>* linv, int64_t ldl,
+                                                const D3M_LDS int* perm, D3M_GLB cpx<TS>* ginv,
+                                                const D3M_LDS cpx<T>* dinv, const D3M_LDS cpx<T>* dpart,
+                                                const D3M_LDS int* prt) {
+  typedef typename V4<T>::type v4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nb = (m + 15) >> 4;
+  constexpr int kColStep = kThreads / kTileMax;
+  const int ri = tid % kTileMax, cj = tid / kTileMax;
+  const int cjs = __builtin_amdgcn_readfirstlane(cj);
+  // Linv in place of L by recursive doubling.  At level s = 1, 2, 4 (in
+  // 16-blocks), pairs of already inverted diagonal super-blocks A = blocks
+  // [a0, a0 + s) and D = [d0, min(d0 + s, nb)), d0 = a0 + s, turn the block
+  // C = L(D, A) below them into Linv(D, A) = -D^-1 C A^-1: first P = C A^-1
+  // (in place of C), then -D^-1 P.  A level has at most 16 output blocks,
+  // two per wave, so the serial depth is three levels of a few block
+  // products each (X_i = Linv_ii, kept transposed in the diagonal blocks).
+  // Only the 4-block level has 16: wave w takes blocks w and 15 - w, i.e.
+  // (i, j) and its mirror in the 4 x 4 block C, whose products
+  // (a0 + 4 - j for P, i - d0 + 1 for the rest) sum to the same for every
+  // wave.
+  for (int sl = 1; sl < nb; sl *= 2) {
+    const int npair = (nb - sl + 2 * sl - 1) / (2 * sl);  // pairs with d0 < nb
+    const int tot = npair * sl * sl;
+    auto blk = [&](int e, int& i, int& j, int& a0, int& d0) {
+      const int q = e / (sl * sl), r = e - q * sl * sl;
+      a0 = 2 * sl * q;
+      d0 = a0 + sl;
+      i = d0 + r / sl;
+      j = a0 + r % sl;
+      return e < tot && i < nb;
+    };
+    v4 re[2], im[2];
+    // P(i, j) = sum_{j <= q < a0 + s} C(i, q) A^-1(q, j)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      re[u] = v4{0, 0, 0, 0};
+      im[u] = v4{0, 0, 0, 0};
+      int i, j, a0, d0;
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
+        for (int q = j; q < a0 + sl; ++q) {
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const int kq = kk + lk;
+            const cpx<T> av = S[tl_blk(i, q) + kq * 16 + lr];                              // C(i,q)(lr, kq)
+            const cpx<T> bv = (q == j) ? tl_x(S, j, kq, lr) : S[tl_blk(q, j) + lr * 16 + kq];  // A^-1(q,j)(kq, lr)
+            re[u] = mfma16(av.x, bv.x, re[u]);
+            re[u] = mfma16(-av.y, bv.y, re[u]);
+            im[u] = mfma16(av.x, bv.y, im[u]);
+            im[u] = mfma16(av.y, bv.x, im[u]);
+          }
+        }
+    }
+    __syncthreads();  // every C read
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int i, j, a0, d0;
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cpx<T> t;
+          t.x = re[u][v];
+          t.y = im[u][v];
+          S[tl_blk(i, j) + lr * 16 + acc_row<T>(lk, v)] = t;
+        }
+    }
+    __syncthreads();  // P in place
+    // Linv(i, j) = -sum_{d0 <= q <= i} D^-1(i, q) P(q, j)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      re[u] = v4{0, 0, 0, 0};
+      im[u] = v4{0, 0, 0, 0};
+      int i, j, a0, d0;
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
+        for (int q = d0; q <= i; ++q) {
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const int kq = kk + lk;
+            const cpx<T> av = (q == i) ? tl_x(S, i, lr, kq) : S[tl_blk(i, q) + kq * 16 + lr];  // D^-1(i,q)(lr, kq)
+            const cpx<T> bv = S[tl_blk(q, j) + lr * 16 + kq];                                  // P(q,j)(kq, lr)
+            re[u] = mfma16(av.x, bv.x, re[u]);
+            re[u] = mfma16(-av.y, bv.y, re[u]);
+            im[u] = mfma16(av.x, bv.y, im[u]);
+            im[u] = mfma16(av.y, bv.x, im[u]);
+          }
+        }
+    }
+    __syncthreads();  // every P read
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int i, j, a0, d0;
+      if (blk(u ? 15 - w : w, i, j, a0, d0))
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cpx<T> t;
+          t.x = -re[u][v];
+          t.y = -im[u][v];
+          S[tl_blk(i, j) + lr * 16 + acc_row<T>(lk, v)] = t;
+        }
+    }
+    __syncthreads();
+  }
+  // Linv out: zeros above the block diagonal, X_i on it, the blocks below
+  // (each read at an address inside the lower block triangle, then selected)
+  auto lval = [&](int i, int j, cpx<T> e) {
+    const int bi = i >> 4, bj = j >> 4;
+    cpx<T> v;
+    const bool keep = bi > bj || (bi == bj && (i & 15) > (j & 15));
+    v.x = keep ? e.x : ((i == j) ? (T)1 : (T)0);
+    v.y = keep ? e.y : (T)0;
+    return v;
+  };
+  auto laddr = [&](int i, int j) {
+    const int bi = i >> 4, bj = j >> 4;
+    return (bi > bj) ? tl_at<T>(i, j)
+                     : (bi == bj) ? tl_blk(bi, bi) + max(i & 15, j & 15) * 16 + min(i & 15, j & 15) : tl_at<T>(i, i);
+  };
+  for (int j0 = cjs; j0 < m; j0 += 8 * kColStep) {
+    cpx<T> e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = S[laddr(ri, j0 + kColStep * u)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + kColStep * u;
+      if (!(ri < m && j < m)) continue;
+      const cpx<T> v = lval(ri, j, e[u]);
+      const int64_t col = perm ? perm[j] : j;
+      linv[ri + col * ldl] = cvt_cpx<TS>(v);
+      if (ginv) {
+        cpx<T> g = tl_mul(dinv[ri], v);
+        const int q = prt[ri];
+        if (q >= 0) {
+          const cpx<T> eq = S[laddr(q, j)];
+          const cpx<T> vq = lval(q, j, eq);
+          const cpx<T> t = tl_mul(dpart[ri], vq);
+          g.x += t.x;
+          g.y += t.y;
+        }
+        ginv[ri + col * ldl] = cvt_cpx<TS>(g);
+      }
+    }
+  }
+}
+
 // T: arithmetic precision; TS: storage precision of the tile, D and Linv.
 // Returns true (and writes nothing back) when the growth check is on and
 // trips; bad pivots are only recorded when the check is off.
@@ -349,121 +504,7 @@ __device__ bool tile_ldlt(typename Cplx<TS>::type* a_, int64_t lda, int m, typen
     }
     if (gmax_l) atomicMax(reinterpret_cast<int*>(gmax_l), __float_as_int(sqrtf(lmax)));
   }
-  // Linv in place of L by recursive doubling.  At level s = 1, 2, 4 (in
-  // 16-blocks), pairs of already inverted diagonal super-blocks A = blocks
-  // [a0, a0 + s) and D = [d0, min(d0 + s, nb)), d0 = a0 + s, turn the block
-  // C = L(D, A) below them into Linv(D, A) = -D^-1 C A^-1: first P = C A^-1
-  // (in place of C), then -D^-1 P.  A level has at most 16 output blocks,
-  // two per wave, so the serial depth is three levels of a few block
-  // products each (X_i = Linv_ii, kept transposed in the diagonal blocks).
-  // Only the 4-block level has 16: wave w takes blocks w and 15 - w, i.e.
-  // (i, j) and its mirror in the 4 x 4 block C, whose products
-  // (a0 + 4 - j for P, i - d0 + 1 for the rest) sum to the same for every
-  // wave.
-  for (int sl = 1; sl < nb; sl *= 2) {
-    const int npair = (nb - sl + 2 * sl - 1) / (2 * sl);  // pairs with d0 < nb
-    const int tot = npair * sl * sl;
-    auto blk = [&](int e, int& i, int& j, int& a0, int& d0) {
-      const int q = e / (sl * sl), r = e - q * sl * sl;
-      a0 = 2 * sl * q;
-      d0 = a0 + sl;
-      i = d0 + r / sl;
-      j = a0 + r % sl;
-      return e < tot && i < nb;
-    };
-    v4 re[2], im[2];
-    // P(i, j) = sum_{j <= q < a0 + s} C(i, q) A^-1(q, j)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      re[u] = v4{0, 0, 0, 0};
-      im[u] = v4{0, 0, 0, 0};
-      int i, j, a0, d0;
-      if (blk(u ? 15 - w : w, i, j, a0, d0))
-        for (int q = j; q < a0 + sl; ++q) {
-#pragma unroll
-          for (int kk = 0; kk < 16; kk += 4) {
-            const int kq = kk + lk;
-            const cpx<T> av = S[tl_blk(i, q) + kq * 16 + lr];                              // C(i,q)(lr, kq)
-            const cpx<T> bv = (q == j) ? tl_x(S, j, kq, lr) : S[tl_blk(q, j) + lr * 16 + kq];  // A^-1(q,j)(kq, lr)
-            re[u] = mfma16(av.x, bv.x, re[u]);
-            re[u] = mfma16(-av.y, bv.y, re[u]);
-            im[u] = mfma16(av.x, bv.y, im[u]);
-            im[u] = mfma16(av.y, bv.x, im[u]);
-          }
-        }
-    }
-    __syncthreads();  // every C read
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      int i, j, a0, d0;
-      if (blk(u ? 15 - w : w, i, j, a0, d0))
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          cpx<T> t;
-          t.x = re[u][v];
-          t.y = im[u][v];
-          S[tl_blk(i, j) + lr * 16 + acc_row<T>(lk, v)] = t;
-        }
-    }
-    __syncthreads();  // P in place
-    // Linv(i, j) = -sum_{d0 <= q <= i} D^-1(i, q) P(q, j)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      re[u] = v4{0, 0, 0, 0};
-      im[u] = v4{0, 0, 0, 0};
-      int i, j, a0, d0;
-      if (blk(u ? 15 - w : w, i, j, a0, d0))
-        for (int q = d0; q <= i; ++q) {
-#pragma unroll
-          for (int kk = 0; kk < 16; kk += 4) {
-            const int kq = kk + lk;
-            const cpx<T> av = (q == i) ? tl_x(S, i, lr, kq) : S[tl_blk(i, q) + kq * 16 + lr];  // D^-1(i,q)(lr, kq)
-            const cpx<T> bv = S[tl_blk(q, j) + lr * 16 + kq];                                  // P(q,j)(kq, lr)
-            re[u] = mfma16(av.x, bv.x, re[u]);
-            re[u] = mfma16(-av.y, bv.y, re[u]);
-            im[u] = mfma16(av.x, bv.y, im[u]);
-            im[u] = mfma16(av.y, bv.x, im[u]);
-          }
-        }
-    }
-    __syncthreads();  // every P read
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      int i, j, a0, d0;
-      if (blk(u ? 15 - w : w, i, j, a0, d0))
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          cpx<T> t;
-          t.x = -re[u][v];
-          t.y = -im[u][v];
-          S[tl_blk(i, j) + lr * 16 + acc_row<T>(lk, v)] = t;
-        }
-    }
-    __syncthreads();
-  }
-  // Linv out: zeros above the block diagonal, X_i on it, the blocks below
-  // (each read at an address inside the lower block triangle, then selected)
-  for (int j0 = cjs; j0 < m; j0 += 8 * kColStep) {
-    cpx<T> e[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = j0 + kColStep * u, bi = ri >> 4, bj = j >> 4;
-      const int ad = (bi > bj) ? tl_at<T>(ri, j)
-                               : (bi == bj) ? tl_blk(bi, bi) + max(ri & 15, j & 15) * 16 + min(ri & 15, j & 15)
-                                            : tl_at<T>(ri, ri);
-      e[u] = S[ad];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = j0 + kColStep * u, bi = ri >> 4, bj = j >> 4;
-      if (!(ri < m && j < m)) continue;
-      cpx<T> v;
-      const bool keep = bi > bj || (bi == bj && (ri & 15) > (j & 15));
-      v.x = keep ? e[u].x : ((ri == j) ? (T)1 : (T)0);
-      v.y = keep ? e[u].y : (T)0;
-      linv[ri + (int64_t)j * ldl] = cvt_cpx<TS>(v);
-    }
-  }
+  tl_invert_store<T, TS>(S, m, linv, ldl, nullptr, nullptr, nullptr, nullptr, nullptr);
   wg_sync_global();
   return false;
 }

@@ -77,8 +77,9 @@ def kappa_inf_estimate(inst, p, iters=5):
 
 
 def _mixed_bound(kappa, eta):
-    ke = kappa * eta
-    assert ke < 0.5
+    """Per column: 4 * 2 kappa eta / (1 - kappa eta)."""
+    ke = kappa * np.asarray(eta)
+    assert np.all(ke < 0.5)
     return 4.0 * 2.0 * ke / (1.0 - ke)
 
 
