@@ -239,6 +239,22 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
                          const int32_t* nrhs, const int64_t* ld, d3m_stream stream);
 void d3m_batch_destroy(d3m_batch b);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, serving loops, harnesses that forbid hipMalloc): d3m_factor_bind
+ * on a device array of the library itself instead of a caller workspace.
+ * The array holds D3M_STATIC_WS_BYTES per device (each device the library is
+ * loaded on keeps it until the process ends); a plan whose workspace
+ * (d3m_workspace_bytes) is larger returns D3M_ERR_WORKSPACE.  No device
+ * memory is allocated here or by the factor's later calls.  One factor per
+ * device lives in the array: binding another one on the same device
+ * invalidates the earlier (its calls then return D3M_ERR_STATE), and calls
+ * on factors that share the array must not overlap in time (they race).
+ * d3m_options.timing is ignored.  Bind on the device that will run it
+ * (the current device). */
+#define D3M_STATIC_WS_BYTES (64u << 20)
+d3m_status d3m_factor_bind_static(d3m_plan plan, d3m_precision prec, int32_t nrhs_max, const d3m_options* opt,
+                                  d3m_factor* out);
+
 /* Device tuning: time each candidate tile configuration of the GEMM task
  * body on the current device and return the fastest (id, measured GFLOP/s)
  * for the precision. */

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libd3m.so")
 
 C128 = 0
 C64_IR = 1
+STATIC_WS_BYTES = 64 << 20  # D3M_STATIC_WS_BYTES of include/d3m.h
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "invalid block pattern or order", -3: "workspace too small",
           -4: "call out of sequence", -5: "HIP runtime error", -6: "watchdog (hang)", -7: "no device",
@@ -81,6 +82,7 @@ SIGNATURES = {
     "d3m_workspace_bytes": (_i32, [_vp, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "d3m_factor_bind": (_i32, [_vp, _i32, _vp, ctypes.c_size_t, _i32, ctypes.POINTER(Options),
                                ctypes.POINTER(_vp)]),
+    "d3m_factor_bind_static": (_i32, [_vp, _i32, _i32, ctypes.POINTER(Options), ctypes.POINTER(_vp)]),
     "d3m_factorize": (_i32, [_vp, _vp, _vp]),
     "d3m_solve": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _vp]),
     "d3m_adjoint": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp]),
@@ -206,12 +208,14 @@ class Plan:
 
 
 class Factor:
-    """A numeric factor bound to a torch-owned device workspace."""
+    """A numeric factor bound to a torch-owned device workspace, or with
+    static_ws=True to the library's own static device array (no allocation;
+    at most STATIC_WS_BYTES, one such factor per device at a time)."""
 
     def __init__(self, plan: Plan, precision: int = C128, nrhs_max: int = 1, tol: float = 1e-10,
                  max_iter: int = 10, ir_host_sync: bool = False, timing: bool = False, growth_dmin: float = 0.0,
                  growth_lmax: float = 0.0, fallback: bool = True, dk_stored: bool = False, device=None,
-                 pivot: bool = False):
+                 static_ws: bool = False, pivot: bool = False):
         import torch
         self.plan = plan
         self.precision = int(precision)
@@ -219,13 +223,18 @@ class Factor:
         opts = Options(float(tol), int(max_iter), int(bool(ir_host_sync)), float(growth_dmin), float(growth_lmax),
                        0 if fallback else -1, int(bool(timing)), int(bool(dk_stored)), int(bool(pivot)))
         h = _vp()
-        nbytes = plan.workspace_bytes(precision, nrhs_max)
-        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-        base = self.ws.data_ptr()
-        self._off = (-base) % 256
-        _check(lib().d3m_factor_bind(plan._h, self.precision, ctypes.c_void_p(base + self._off), nbytes,
-                                     self.nrhs_max, ctypes.byref(opts), ctypes.byref(h)), "d3m_factor_bind")
+        if static_ws:
+            self.ws = None
+            _check(lib().d3m_factor_bind_static(plan._h, self.precision, self.nrhs_max, ctypes.byref(opts),
+                                                ctypes.byref(h)), "d3m_factor_bind_static")
+        else:
+            nbytes = plan.workspace_bytes(precision, nrhs_max)
+            dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            base = self.ws.data_ptr()
+            self._off = (-base) % 256
+            _check(lib().d3m_factor_bind(plan._h, self.precision, ctypes.c_void_p(base + self._off), nbytes,
+                                         self.nrhs_max, ctypes.byref(opts), ctypes.byref(h)), "d3m_factor_bind")
         self._h = h
         self.K = None
 

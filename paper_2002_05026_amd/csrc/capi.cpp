@@ -12,6 +12,7 @@
 
 #include "launch.h"
 #include "planner.h"
+#include "static_ws.h"
 
 using namespace d3m;
 
@@ -175,6 +176,10 @@ struct d3m_factor_s {
   hipStream_t last = nullptr;
   bool factored = false;
   int nworkers = 256;
+  // bound to the library's static device array of device sdev (>= 0), as
+  // generation sgen; a later static bind on that device invalidates it
+  int sdev = -1;
+  unsigned long long sgen = 0;
   // timing: event pairs around DAG launches, [0] factor, [1] solve
   static constexpr int kRing = 64;
   void* trace = nullptr;  // optional task trace buffer (caller-owned device memory)
@@ -361,12 +366,21 @@ d3m_status d3m_workspace_bytes(d3m_plan plan, d3m_precision prec, int32_t nrhs_m
 
 d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size_t bytes, int32_t nrhs_max,
                            const d3m_options* opt, d3m_factor* out) {
+  return d3m::bind_factor(plan, prec, dev_ws, bytes, nrhs_max, opt, -1, 0, out);
+}
+
+}  // extern "C"
+
+d3m_status d3m::bind_factor(d3m_plan plan, d3m_precision prec, void* dev_ws, size_t bytes, int32_t nrhs_max,
+                            const d3m_options* opt, int sdev, unsigned long long sgen, d3m_factor* out) {
   if (!plan || !out || !dev_ws || nrhs_max < 1 || nrhs_max > 128 || (prec != D3M_C128 && prec != D3M_C64_IR))
     return D3M_ERR_ARG;
   *out = nullptr;
   if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return D3M_ERR_WORKSPACE;
   d3m_factor_s* f = new (std::nothrow) d3m_factor_s;
   if (!f) return D3M_ERR_ARG;
+  f->sdev = sdev;
+  f->sgen = sgen;
   f->plan = plan;
   f->prec = prec == D3M_C128 ? 0 : 1;
   f->nrhs_max = nrhs_max;
@@ -453,8 +467,16 @@ d3m_status d3m_factor_bind(d3m_plan plan, d3m_precision prec, void* dev_ws, size
   return D3M_OK;
 }
 
+namespace {
+// a factor bound to the static array after which another factor was bound there
+bool stale(const d3m_factor_s* f) { return f->sdev >= 0 && !d3m::static_ws_valid(f->sdev, f->sgen); }
+}  // namespace
+
+extern "C" {
+
 d3m_status d3m_factorize(d3m_factor f, const void* dev_K, d3m_stream stream) {
   if (!f || !dev_K) return D3M_ERR_ARG;
+  if (stale(f)) return D3M_ERR_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const PlanImpl& p = f->plan->p;
   HIPCHK(launch_prepare(f->at<int32_t>(f->lay.status), f->at<float>(f->lay.growth), p.nb, f->ctrl(), f->opt.tol,
@@ -526,7 +548,7 @@ d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int n
 d3m_status d3m_solve(d3m_factor f, const void* dev_K, const void* dev_B, void* dev_X, int32_t nrhs, int64_t ld,
                      d3m_stream stream) {
   if (!f || !dev_K || !dev_B || !dev_X || nrhs < 1 || nrhs > f->nrhs_max || ld < f->plan->p.N) return D3M_ERR_ARG;
-  if (!f->factored) return D3M_ERR_STATE;
+  if (!f->factored || stale(f)) return D3M_ERR_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   d3m_status st = solve_impl(f, dev_K, dev_B, dev_X, nrhs, ld, s);
   f->last = s;
@@ -537,7 +559,7 @@ d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const
                        void* dev_dK, int32_t nrhs, int64_t ld, d3m_stream stream) {
   if (!f || !dev_K || !dev_X || !dev_G || !dev_Lambda || nrhs < 1 || nrhs > f->nrhs_max || ld < f->plan->p.N)
     return D3M_ERR_ARG;
-  if (!f->factored) return D3M_ERR_STATE;
+  if (!f->factored || stale(f)) return D3M_ERR_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   d3m_status st = solve_impl(f, dev_K, dev_G, dev_Lambda, nrhs, ld, s);
   if (st) return st;
@@ -550,6 +572,7 @@ d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const
 
 d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
   if (!f || !out) return D3M_ERR_ARG;
+  if (stale(f)) return D3M_ERR_STATE;
   HIPCHK(hipStreamSynchronize(f->last));
   std::memset(out, 0, sizeof(*out));
   int32_t st[3];
@@ -591,6 +614,7 @@ d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
 
 d3m_status d3m_factor_block(d3m_factor f, int32_t J, int32_t I, void* host_out) {
   if (!f || !host_out) return D3M_ERR_ARG;
+  if (stale(f)) return D3M_ERR_STATE;
   const PlanImpl& p = f->plan->p;
   if (I < 0 || I >= p.nb || J < 0 || J >= p.nb) return D3M_ERR_ARG;
   HIPCHK(hipStreamSynchronize(f->last));
@@ -626,7 +650,7 @@ d3m_status d3m_factor_pivots(d3m_factor f, int32_t I, int32_t* perm, void* doff_
   if (!f || !perm || !doff_host) return D3M_ERR_ARG;
   const PlanImpl& p = f->plan->p;
   if (I < 0 || I >= p.nb) return D3M_ERR_ARG;
-  if (!f->opt.pivot || !f->factored) return D3M_ERR_STATE;
+  if (!f->opt.pivot || !f->factored || stale(f)) return D3M_ERR_STATE;
   HIPCHK(hipStreamSynchronize(f->last));
   const Panel& P = p.panels[p.pos[I]];
   const size_t es = f->prec == 0 ? 16 : 8;
@@ -808,6 +832,7 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
   std::vector<const TaskDag*> fds, sds;
   for (int i = 0; i < ninst; ++i) {
     if (!f[i] || f[i]->prec != f[0]->prec) { delete b; return D3M_ERR_ARG; }
+    if (stale(f[i])) { delete b; return D3M_ERR_STATE; }
     b->f.push_back(f[i]);
     fds.push_back(&f[i]->plan->p.fdag);
     sds.push_back(&f[i]->plan->p.sdag);
@@ -852,6 +877,7 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
   for (int i = 0; i < n; ++i) {
     const d3m_factor_s* f = b->f[i];
     if (!K[i] || !B[i] || !X[i] || nrhs[i] != f->nrhs_max || ld[i] < f->plan->p.N) return D3M_ERR_ARG;
+    if (stale(f)) return D3M_ERR_STATE;
   }
   // scatter/convert and ||K|| per instance, then one persistent factor launch
   for (int i = 0; i < n; ++i) {
