@@ -475,26 +475,37 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   // the finished task.  Only read-only tables are read before the wait.
   constexpr bool kPreSrc = sizeof(typename Cplx<T>::type) == 8;
   static_assert(kMergeSrc <= 64, "one lane of wave 1 per source");
+  // Lanes of wave 1 learn the ticket from lane 0 by a cross-lane read, not
+  // through LDS: lane 0's LDS store and the other lanes' loads would be
+  // unsynchronized accesses, which the compiler may reorder (the other
+  // lanes would then see an old s_next, e.g. the -1 an earlier launch left,
+  // and leave their table entries stale).  Each lane then reads the fields
+  // of the task record it needs from global memory.
   auto take_next = [&](int b) {
-    if (threadIdx.x == 64) {
-      const int t = take();
-      s_next[b] = t;
-      if (t >= 0) s_task[b] = a.tasks[t];
-    }
-    if (kPreSrc && threadIdx.x >= 64 && threadIdx.x < 128) {
-      const int q = (int)threadIdx.x - 64;
-      const Task& nt = s_task[b];
-      if (s_next[b] >= 0 && nt.kind == TK_XUPD && nt.pad0 > 1 && q < nt.pad0) {
-        typedef typename Cplx<T>::type C;
-        const InstView* iv = a.inst + nt.inst;
-        const XSrc x = iv->xsrc[nt.pad1 + q];
-        GeSrc<T> e;
-        e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
-        e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
-        e.lda = e.ldb = x.lda;
-        e.k = x.k;
-        e.pad = 0;
-        ge_src_put(reinterpret_cast<D3M_LDS GeSrc<T>*>((lds_char*)lds + ge_lds_bytes_dma<T>()), q, e);
+    if (threadIdx.x >= 64 && threadIdx.x < 128) {
+      int t = -1;
+      if (threadIdx.x == 64) t = take();
+      t = __builtin_amdgcn_readlane(t, 0);
+      if (threadIdx.x == 64) {
+        s_next[b] = t;
+        if (t >= 0) s_task[b] = a.tasks[t];
+      }
+      if (kPreSrc && t >= 0) {
+        const int q = (int)threadIdx.x - 64;
+        const Task* nt = a.tasks + t;
+        const int kind = nt->kind, pad0 = nt->pad0;
+        if ((kind & 0xff) == TK_XUPD && pad0 > 1 && q < pad0) {
+          typedef typename Cplx<T>::type C;
+          const InstView* iv = a.inst + nt->inst;
+          const XSrc x = iv->xsrc[nt->pad1 + q];
+          GeSrc<T> e;
+          e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
+          e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
+          e.lda = e.ldb = x.lda;
+          e.k = x.k;
+          e.pad = 0;
+          ge_src_put(reinterpret_cast<D3M_LDS GeSrc<T>*>((lds_char*)lds + ge_lds_bytes_dma<T>()), q, e);
+        }
       }
     }
   };
