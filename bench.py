@@ -9,7 +9,8 @@ solve, then FP64 residuals and refinement until eta_inf <= 1e-10, including
 the certifying residual.  The FP64 path (complex128 factor + solve + one
 certifying residual) is timed on the same K for the mixed-vs-FP64 speedup.
 
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line: the metric, the whole-step rate, the roofline of the
+factor DAG, the oracle's CPU baseline and the per-phase timings.
 """
 import argparse
 import json
@@ -124,7 +125,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--nrhs", type=int, default=64)
-    ap.add_argument("--workload", default="precision", choices=["precision", "fp64", "batch", "diff"],
+    ap.add_argument("--no-tune", action="store_true", help="default plan knobs instead of the autotuner's")
+    ap.add_argument("--knobs", default=None,
+                    help='fixed plan knobs instead of the autotuner, JSON for both precisions or '
+                         '{"c64": {...}, "c128": {...}} (e.g. to profile a tuned configuration)')
+    ap.add_argument("--workload", default="precision", choices=["precision", "fp64", "batch", "diff", "pivot", "primal"],
                     help="precision (default): the metric's workload; the others measure the remaining "
                          "configurations and print their own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -135,8 +140,8 @@ def main():
         one_thread_sample()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
-              "(see DESIGN.md) and is not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); a sharded multi-GPU path is "
+              "not built.", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calibration:
@@ -171,7 +176,21 @@ def main():
     t0 = time.perf_counter()
     inst = gen.config_precision(nrhs=args.nrhs)
     print(f"[bench] instance N={inst.N} generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid)
+    from paper_2002_05026_amd import tune
+    tuned = {}
+    for prec in ((d3m.C64_IR,) if args.no_fp64 else (d3m.C64_IR, d3m.C128)):
+        if args.knobs:
+            kn = json.loads(args.knobs)
+            kn = kn.get("c64" if prec == d3m.C64_IR else "c128", kn) if ("c64" in kn or "c128" in kn) else kn
+            tuned[prec] = {"config": dict(tune.DEFAULT, **kn), "timings": None}
+        elif args.no_tune:
+            tuned[prec] = {"config": dict(tune.DEFAULT), "timings": None}
+        else:
+            t0 = time.perf_counter()
+            tuned[prec] = tune.tune(inst, prec, nrhs=args.nrhs, reps=2, save=False)
+            print(f"[bench] tuned precision {prec} in {time.perf_counter() - t0:.0f}s: {tuned[prec]}",
+                  file=sys.stderr, flush=True)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, **tuned[d3m.C64_IR]["config"])
     flops = plan.info["flops_factor"]
     K = torch.from_numpy(inst.K).cuda()
     B = torch.from_numpy(inst.B).cuda()
@@ -203,16 +222,25 @@ def main():
     if st_mixed["status"] != 0:
         raise SystemExit(f"mixed path status {st_mixed}")
     dag_ms = st_mixed["t_factor_dag_ms"] / max(1, st_mixed["n_factor_dag"])
+    # every solve launch is timed, also the refinement steps that return at
+    # once after convergence (a few microseconds each): per solve pass that
+    # ran, the total over the (ir_iters + 1) passes of each step
+    solve_ms = st_mixed["t_solve_dag_ms"] / (args.steps * (st_mixed["ir_iters"] + 1))
+    solve_bytes = 2.0 * plan.info["nnz_L"] * 8
     del f32
     torch.cuda.empty_cache()
 
     fp64 = None
     if not args.no_fp64:
-        f64 = d3m.Factor(plan, d3m.C128, nrhs_max=args.nrhs, timing=True)
+        plan64 = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, **tuned[d3m.C128]["config"])
+        f64 = d3m.Factor(plan64, d3m.C128, nrhs_max=args.nrhs, timing=True)
         ms64, st64 = timed(f64, max(2, args.steps // 2), 1)
         dag64 = st64["t_factor_dag_ms"] / max(1, st64["n_factor_dag"])
+        s64 = st64["t_solve_dag_ms"] / max(1, st64["n_solve_dag"])
         fp64 = {"time_to_solve_ms": ms64, "factor_dag_ms": dag64, "factor_tflops": flops / dag64 / 1e9,
-                "frac_fp64_peak": flops / dag64 / 1e9 / PEAK_FP64_MFMA, "eta": st64["eta"]}
+                "frac_fp64_peak": flops / dag64 / 1e9 / PEAK_FP64_MFMA, "eta": st64["eta"],
+                "solve_dag_ms": s64, "solve_GBps": 2.0 * plan64.info["nnz_L"] * 16 / s64 / 1e6,
+                "tuned": tuned[d3m.C128]["config"]}
         print(f"[bench] fp64: {ms64:.2f} ms/step, status {st64}", file=sys.stderr, flush=True)
         del f64
         torch.cuda.empty_cache()
@@ -243,7 +271,10 @@ def main():
         "time_to_solve_ms": {"mixed_ir": ms_mixed, "fp64": fp64["time_to_solve_ms"] if fp64 else None},
         "speedup_mixed_vs_fp64": (fp64["time_to_solve_ms"] / ms_mixed) if fp64 else None,
         "mixed": {"eta": st_mixed["eta"], "eta_hist": st_mixed["eta_hist"], "ir_iters": st_mixed["ir_iters"],
-                  "factor_dag_ms": dag_ms, "factor_tflops": achieved},
+                  "factor_dag_ms": dag_ms, "factor_tflops": achieved, "solve_dag_ms": solve_ms,
+                  "solve_GBps": solve_bytes / solve_ms / 1e6,
+                  "solve_tflops": plan.info["solve_flops_per_rhs"] * args.nrhs / solve_ms / 1e9},
+        "tuned": {"config": tuned[d3m.C64_IR]["config"], "timings_ms": tuned[d3m.C64_IR]["timings"]},
         "fp64": fp64,
         "roofline": {"kernel": "k_dag<float> (complex64 factor DAG)", "bound": "mfma", "achieved": achieved,
                      "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,

@@ -80,6 +80,17 @@ typedef struct {
   int32_t tile;      /* largest tile edge, a multiple of 16 in [16,128]; 0 -> 128 */
   int32_t nworkers;  /* persistent workgroups assumed by the list scheduler; 0 -> 256 */
   int32_t sched;     /* 0 = list scheduling by bottom level, 1 = plain sequential order */
+  int32_t nelim;     /* 0: eliminate every block.  > 0: a partial elimination for the
+                        primal reduction (d3m_reduce / d3m_recover): only the first nelim
+                        blocks of the order are eliminated; the others must be the user ids
+                        0..nred-1 (nred = nblk - nelim), the pairs between them must come
+                        first in the pair list, and eliminating the first nelim blocks must
+                                                fill no block between them that is not such a pair */
+  int32_t solve_tile; /* rows of a solve task, a multiple of 16 in [16,128]; 0 -> 64 */
+  int32_t merge;      /* source panels per merged Schur update task, [1,16]; 0 -> 8 */
+  int32_t rhs_groups; /* also build a solve DAG that splits the right-hand sides into this
+                         many column groups (independent copies, twice the parallelism at two
+                         groups); used by solves with >= 16 columns per group.  [1,8]; 0 -> 1 */
   int32_t reserved;
 } d3m_analyze_options;
 
@@ -195,6 +206,33 @@ d3m_status d3m_solve(d3m_factor f, const void* dev_K, const void* dev_B, void* d
  * X is the solution of the forward solve; dK (K's layout) may be NULL. */
 d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const void* dev_G,
                        void* dev_Lambda, void* dev_dK, int32_t nrhs, int64_t ld, d3m_stream stream);
+/* Primal reduction (Sec. II, the first part of the task graph: per domain
+ * the factorization of the regularized domain matrix and its map onto its
+ * interfaces, assembled into the reduced matrix).  The factor's plan is a
+ * partial elimination (d3m_analyze_options.nelim) of a primal matrix A in
+ * block form, given in the K layout of that plan: the eliminated blocks are
+ * the domains' interior unknowns, the blocks left (user ids 0..nred-1) the
+ * interfaces.  Computes, with a complex128 factor:
+ *   Kred = A_GG - A_Gi A_ii^-1 A_iG   (the Schur complement on the blocks
+ *          left, written whole in the K layout of those blocks and of the
+ *          first npair_red pairs; may be NULL),
+ *   Gred = F_G - A_Gi A_ii^-1 F_i     (nrhs columns, ldg >= their rows;
+ *          with F == NULL nothing is solved and d3m_recover cannot follow).
+ * F: nrhs <= nrhs_max primal right-hand sides (ldf >= N).  Kred, Gred are
+ * then the input of an ordinary factor of the reduced matrix.  Numerical
+ * outcomes (a zero pivot of an interior block) go to d3m_status_sync. */
+d3m_status d3m_reduce(d3m_factor f, const void* dev_A, const void* dev_F, int64_t ldf, void* dev_Kred,
+                      void* dev_Gred, int64_t ldg, int32_t nrhs, d3m_stream stream);
+/* Primal recovery (Sec. II, the third part: per domain the recovery of the
+ * primal unknowns and, optionally, the scattering matrix S).  After
+ * d3m_reduce with the same nrhs and the solution Xred of the reduced system
+ * (ldx >= its rows): U = the full primal solution, the interior unknowns
+ * u_i = A_ii^-1 (F_i - A_iG Xred) and Xred itself in the rows of the blocks
+ * left (ldu >= N).  With nports > 0 also S (nports x nrhs, column-major),
+ * S_pq = sum_r M(r, p) U(r, q), bilinear, for the port modes M (N x nports,
+ * ldm >= N). */
+d3m_status d3m_recover(d3m_factor f, const void* dev_Xred, int64_t ldx, void* dev_U, int64_t ldu, int32_t nrhs,
+                       const void* dev_M, int64_t ldm, int32_t nports, void* dev_S, d3m_stream stream);
 /* Wait for the factor's last stream and report numerical outcomes, in the
  * manner of LAPACK's info argument (not from the paper): the first bad
  * pivot's user row, refinement steps and eta, FP64 re-factors, DAG times. */

@@ -39,7 +39,8 @@ class D3MError(RuntimeError):
 
 class AnalyzeOptions(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("nworkers", ctypes.c_int32), ("sched", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("nelim", ctypes.c_int32), ("solve_tile", ctypes.c_int32), ("merge", ctypes.c_int32),
+                ("rhs_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Options(ctypes.Structure):
@@ -86,6 +87,8 @@ SIGNATURES = {
     "d3m_factorize": (_i32, [_vp, _vp, _vp]),
     "d3m_solve": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _vp]),
     "d3m_adjoint": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp]),
+    "d3m_reduce": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _i64, _i32, _vp]),
+    "d3m_recover": (_i32, [_vp, _vp, _i64, _vp, _i64, _i32, _vp, _i64, _i32, _vp, _vp]),
     "d3m_status_sync": (_i32, [_vp, ctypes.POINTER(RunInfo)]),
     "d3m_factor_block": (_i32, [_vp, _i32, _i32, _vp]),
     "d3m_factor_destroy": (None, [_vp]),
@@ -151,12 +154,14 @@ class Plan:
     """Symbolic analysis: elimination order, block fill, tile DAGs (host only)."""
 
     def __init__(self, sizes, pairs, order=None, grid=None, tile: int = 0, nworkers: int = 0,
-                 sched: int = 0):
+                 sched: int = 0, nelim: int = 0, solve_tile: int = 0, merge: int = 0, rhs_groups: int = 0):
         self.sizes = _arr32(sizes)
         self.pairs = _arr32(np.asarray(pairs).reshape(-1, 2))
         o = None if order is None else _arr32(order)
         g = None if grid is None else _arr32(grid)
-        opts = AnalyzeOptions(int(tile), int(nworkers), int(sched), 0)
+        self.nelim = int(nelim)
+        opts = AnalyzeOptions(int(tile), int(nworkers), int(sched), self.nelim, int(solve_tile), int(merge),
+                              int(rhs_groups), 0)
         h = _vp()
         _check(lib().d3m_analyze(self.sizes.shape[0], _p32(self.sizes), self.pairs.shape[0], _p32(self.pairs),
                                  _p32(o) if o is not None else None, _p32(g) if g is not None else None,
@@ -290,6 +295,48 @@ class Factor:
                                  _ptr(dK) if want_dK else None, G.shape[0], G.stride(0), _stream(stream)),
                "d3m_adjoint")
         return Lam, dK
+
+    def reduce(self, A, F=None, stream=None):
+        """Primal reduction with a partial-elimination plan: returns (Kred,
+        Gred), the Schur complement on the blocks left (K layout of those
+        blocks and the leading pairs) and, given F (nrhs, N), the reduced
+        right-hand sides (nrhs, N_left)."""
+        import torch
+        self._checkK(A)
+        nred = self.plan.nb - self.plan.nelim
+        rows = int(self.plan.sizes[:nred].astype(np.int64).sum())
+        npr = 0
+        while npr < self.plan.pairs.shape[0] and self.plan.pairs[npr].max() < nred:
+            npr += 1
+        klen = int((self.plan.sizes[:nred].astype(np.int64) ** 2).sum() +
+                   sum(int(self.plan.sizes[a]) * int(self.plan.sizes[b]) for a, b in self.plan.pairs[:npr].tolist()))
+        Kred = torch.empty(klen, dtype=torch.complex128, device=A.device)
+        G = None
+        if F is not None:
+            self._checkB(F)
+            G = torch.empty((F.shape[0], rows), dtype=torch.complex128, device=A.device)
+        self.K = A
+        _check(lib().d3m_reduce(self._h, _ptr(A), _ptr(F) if F is not None else None,
+                                F.stride(0) if F is not None else 0, _ptr(Kred),
+                                _ptr(G) if G is not None else None, G.stride(0) if G is not None else 0,
+                                F.shape[0] if F is not None else 1, _stream(stream)), "d3m_reduce")
+        return Kred, G
+
+    def recover(self, Xred, M=None, stream=None):
+        """Primal recovery after reduce(A, F): the full primal solution U
+        (nrhs, N) and, with port modes M (nports, N), S (nports, nrhs)."""
+        import torch
+        nr = Xred.shape[0]
+        U = torch.empty((nr, self.plan.N), dtype=torch.complex128, device=Xred.device)
+        S = None
+        npt = 0
+        if M is not None:
+            npt = M.shape[0]
+            S = torch.empty((nr, npt), dtype=torch.complex128, device=Xred.device)  # column-major nports x nrhs
+        _check(lib().d3m_recover(self._h, _ptr(Xred), Xred.stride(0), _ptr(U), U.stride(0), nr,
+                                 _ptr(M) if M is not None else None, M.stride(0) if M is not None else 0, npt,
+                                 _ptr(S) if S is not None else None, _stream(stream)), "d3m_recover")
+        return (U, S.t()) if M is not None else U
 
     def status(self) -> dict:
         ri = RunInfo()

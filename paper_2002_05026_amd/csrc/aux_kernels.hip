@@ -226,6 +226,88 @@ hipError_t launch_perm_out(const void* W, void* X, int64_t ld, const UserView& u
   return hipGetLastError();
 }
 
+// Rows [q0, q1) (internal order) only: W[q*nrhs + j] = B[j*ld + perm[q]]
+// (in) or X[j*ld + perm[q]] = W[q*nrhs + j] (out), complex128.
+__global__ void k_perm_rows(const double2* src, int64_t lds, double2* dst, int64_t ldd, const int32_t* perm,
+                            int64_t q0, int64_t q1, int nrhs, int out) {
+  const int64_t tot = (q1 - q0) * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = q0 + e / nrhs;
+    const int j = (int)(e % nrhs);
+    if (out) dst[(int64_t)j * ldd + perm[q]] = src[q * nrhs + j];
+    else dst[q * nrhs + j] = src[(int64_t)j * lds + perm[q]];
+  }
+}
+
+hipError_t launch_perm_rows(const void* src, int64_t lds, void* dst, int64_t ldd, const UserView& uv, int64_t q0,
+                            int64_t q1, int nrhs, int out, hipStream_t s) {
+  const int64_t tot = (q1 - q0) * nrhs;
+  if (tot <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_perm_rows, dim3(blocks), dim3(256), 0, s, (const double2*)src, lds, (double2*)dst, ldd,
+                     uv.perm, q0, q1, nrhs, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reduced matrix out
+// Blocks of the reduced matrix from panel storage (complex128), one block
+// per blockIdx.y: K(i, j) = panel(i, j) (trans 0) or panel(j, i) (trans 1);
+// a diagonal block (rows == cols, trans 0, the first nred entries) is read
+// from its lower triangle and written whole, symmetric.
+__global__ __launch_bounds__(256) void k_gather_red(const double2* L, double2* K, const KPlaceDev* kg, int ndiag) {
+  const int b = blockIdx.y;
+  const KPlaceDev P = kg[b];
+  const int Kr = P.trans ? P.cols : P.rows, Kc = P.trans ? P.rows : P.cols;  // K block is Kr x Kc
+  const int64_t tot = (int64_t)Kr * Kc;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % Kr), j = (int)(e / Kr);
+    int r = P.trans ? j : i, c = P.trans ? i : j;  // panel (r, c)
+    if (b < ndiag && r < c) { const int t = r; r = c; c = t; }
+    K[P.dst + e] = L[P.src + r + (int64_t)c * P.ld_dst];
+  }
+}
+
+hipError_t launch_gather_red(const void* L, void* K, const KPlaceDev* kg, int nkg, int ndiag, int maxelems,
+                             hipStream_t s) {
+  if (nkg == 0) return hipSuccess;
+  const int bx = std::max(1, std::min(64, (maxelems + 255) / 256));
+  hipLaunchKernelGGL(k_gather_red, dim3(bx, nkg), dim3(256), 0, s, (const double2*)L, (double2*)K, kg, ndiag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- port projections
+// S[p + q*nports] = sum_i M[i + p*ldm] U[i + q*ldu] (bilinear), one
+// workgroup per (p, q); fixed-order partial sums, then a fixed tree.
+__global__ __launch_bounds__(256) void k_ports(const double2* M, int64_t ldm, const double2* U, int64_t ldu,
+                                               int64_t N, int nports, double2* S) {
+  __shared__ double2 red[256];
+  const int p = blockIdx.x, q = blockIdx.y;
+  double2 acc = {0, 0};
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const double2 m = M[i + p * ldm], u = U[i + q * ldu];
+    acc.x += m.x * u.x - m.y * u.y;
+    acc.y += m.x * u.y + m.y * u.x;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x].x += red[threadIdx.x + w].x;
+      red[threadIdx.x].y += red[threadIdx.x + w].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) S[p + (int64_t)q * nports] = red[0];
+}
+
+hipError_t launch_ports(const void* M, int64_t ldm, const void* U, int64_t ldu, int64_t N, int nports, int nrhs,
+                        void* S, hipStream_t s) {
+  if (nports <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ports, dim3(nports, nrhs), dim3(256), 0, s, (const double2*)M, ldm, (const double2*)U, ldu, N,
+                     nports, (double2*)S);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- residual
 __device__ __forceinline__ void atomic_max_pos(double* p, double v) {
   // non-negative doubles order like their bit patterns

@@ -28,8 +28,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Workspace layout of one factor.
 struct Layout {
   size_t L, LD, D, Linv, Ginv, Doff, ipiv, W, Z, X64, R64, P64, norms, ctrl, status, growth, counters, flags;
-  size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, panels, pblocks, tiles, xsrc, iv;
-  size_t kp, fills, rt, rptr, rblk, rsplit, nI, row0, prow0, perm, dkt;
+    size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, s2tasks, s2succ, s2cnt, sgtasks, sgsucc, sgcnt;
+  size_t panels, pblocks, tiles, xsrc, iv;
+  size_t kp, fills, rt, rptr, rblk, rsplit, nI, row0, prow0, perm, dkt, kg;
   size_t total;
 };
 
@@ -43,11 +44,13 @@ struct Tables {
   std::vector<int64_t> row0, prow0;
   std::vector<int32_t> perm;
   std::vector<DkTaskDev> dkt;
+  std::vector<KPlaceDev> kg;  // reduced matrix out of panel storage (partial elimination)
 };
 
 void make_tables(const PlanImpl& p, Tables& t) {
   for (auto& k : p.kplace) t.kp.push_back({k.src, k.dst, k.rows, k.cols, k.ld_dst, k.trans});
   for (auto& f : p.fills) t.fills.push_back({0, f.dst, f.rows, f.cols, f.ld_dst, 0});
+  for (auto& k : p.kgather) t.kg.push_back({k.src, k.dst, k.rows, k.cols, k.ld_dst, k.trans});
   t.nI = p.n;
   t.row0.assign(p.nb + 1, 0);
   for (int i = 0; i < p.nb; ++i) t.row0[i + 1] = t.row0[i] + p.n[i];
@@ -124,7 +127,8 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.ctrl = take(sizeof(IrCtrl));
   l.status = take(4 * sizeof(int32_t));
   l.growth = take(2 * p.nb * sizeof(float));
-  l.counters = take(std::max(p.fdag.tasks.size(), p.sdag.tasks.size()) * sizeof(int32_t));
+    l.counters = take(std::max({p.fdag.tasks.size(), p.sdag.tasks.size(), p.sdag2.tasks.size(), p.sdagg.tasks.size()}) *
+                    sizeof(int32_t));
   l.flags = take(4 * sizeof(int32_t));
   l.ftasks = take(p.fdag.tasks.size() * sizeof(Task));
   l.fsucc = take(p.fdag.succ.size() * sizeof(int32_t));
@@ -132,6 +136,12 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.stasks = take(p.sdag.tasks.size() * sizeof(Task));
   l.ssucc = take(p.sdag.succ.size() * sizeof(int32_t));
   l.scnt = take(p.sdag.npred.size() * sizeof(int32_t));
+  l.s2tasks = take(p.sdag2.tasks.size() * sizeof(Task));
+  l.s2succ = take(p.sdag2.succ.size() * sizeof(int32_t));
+    l.s2cnt = take(p.sdag2.npred.size() * sizeof(int32_t));
+  l.sgtasks = take(p.sdagg.tasks.size() * sizeof(Task));
+  l.sgsucc = take(p.sdagg.succ.size() * sizeof(int32_t));
+  l.sgcnt = take(p.sdagg.npred.size() * sizeof(int32_t));
   l.panels = take(p.panels.size() * sizeof(Panel));
   l.pblocks = take(p.pblocks.size() * sizeof(PBlock));
   l.tiles = take(p.tiles.size() * sizeof(Tile));
@@ -148,6 +158,7 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.prow0 = take(t.prow0.size() * sizeof(int64_t));
   l.perm = take(t.perm.size() * sizeof(int32_t));
   l.dkt = take(t.dkt.size() * sizeof(DkTaskDev));
+  l.kg = take(t.kg.size() * sizeof(KPlaceDev));
   l.total = o;
   return l;
 }
@@ -176,6 +187,7 @@ struct d3m_factor_s {
   hipStream_t last = nullptr;
   bool factored = false;
   int nworkers = 256;
+  int red_nrhs = 0;  // right-hand sides of the last d3m_reduce's forward part (d3m_recover continues it)
   // bound to the library's static device array of device sdev (>= 0), as
   // generation sgen; a later static bind on that device invalidates it
   int sdev = -1;
@@ -213,12 +225,22 @@ struct d3m_factor_s {
 
 namespace {
 
-d3m_status run_dag(d3m_factor_s* f, bool solve, int nrhs, const int32_t* skip, hipStream_t s) {
+// which: 0 the factor DAG, 1 the solve DAG (with a partial elimination its
+// forward part), 2 the backward part of a partial elimination's solve.  A
+// solve whose right-hand sides give every group of the plan's grouped solve
+// DAG at least 16 columns runs that one (3).
+d3m_status run_dag(d3m_factor_s* f, int which, int nrhs, const int32_t* skip, hipStream_t s) {
   const PlanImpl& p = f->plan->p;
-  const TaskDag& dag = solve ? p.sdag : p.fdag;
+  const bool solve = which != 0;
+  if (which == 1 && p.rhs_groups > 1 && !p.sdagg.tasks.empty() && nrhs >= 16 * p.rhs_groups) which = 3;
+  const TaskDag& dag = which == 0 ? p.fdag : (which == 1 ? p.sdag : (which == 2 ? p.sdag2 : p.sdagg));
+  const size_t tk[4] = {f->lay.ftasks, f->lay.stasks, f->lay.s2tasks, f->lay.sgtasks};
+  const size_t sc[4] = {f->lay.fsucc, f->lay.ssucc, f->lay.s2succ, f->lay.sgsucc};
+  const size_t cn[4] = {f->lay.fcnt, f->lay.scnt, f->lay.s2cnt, f->lay.sgcnt};
   DagArgs a;
-  a.tasks = f->at<Task>(solve ? f->lay.stasks : f->lay.ftasks);
-  a.succ = f->at<int32_t>(solve ? f->lay.ssucc : f->lay.fsucc);
+  a.tasks = f->at<Task>(tk[which]);
+  a.succ = f->at<int32_t>(sc[which]);
+  a.rhs_groups = which == 3 ? p.rhs_groups : 1;
   a.counters = f->at<int32_t>(f->lay.counters);
   int32_t* flags = f->at<int32_t>(f->lay.flags);
   a.head = flags;
@@ -231,8 +253,7 @@ d3m_status run_dag(d3m_factor_s* f, bool solve, int nrhs, const int32_t* skip, h
   a.trace = nullptr;
   if (f->trace && (size_t)a.ntask * 32 <= f->trace_bytes / 2)
     a.trace = reinterpret_cast<int64_t*>(static_cast<char*>(f->trace) + (solve ? f->trace_bytes / 2 : 0));
-  HIPCHK(launch_reset(a.counters, f->at<int32_t>(solve ? f->lay.scnt : f->lay.fcnt), a.ntask, a.head,
-                      a.abort_flag, skip, s));
+    HIPCHK(launch_reset(a.counters, f->at<int32_t>(cn[which]), a.ntask, a.head, a.abort_flag, skip, s));
   const int w = solve ? 1 : 0;
   const bool timed = f->opt.timing && !skip && f->nev[w] < d3m_factor_s::kRing;
   if (timed) HIPCHK(hipEventRecord(f->ev[w][2 * f->nev[w]], s));
@@ -284,7 +305,8 @@ d3m_status d3m_analyze(int32_t nblk, const int32_t* blk_size, int64_t npair, con
   d3m_plan_s* pl = new (std::nothrow) d3m_plan_s;
   if (!pl) return D3M_ERR_ARG;
   int err = 0;
-  std::string msg = build_plan(pl->p, nblk, blk_size, npair, pairs, order, grid, o.tile, o.nworkers, o.sched, &err);
+    std::string msg = build_plan(pl->p, nblk, blk_size, npair, pairs, order, grid, o.tile, o.nworkers, o.sched,
+                               o.nelim, o.solve_tile, o.merge, o.rhs_groups, &err);
   if (!msg.empty()) {
     delete pl;
     return (d3m_status)err;
@@ -345,6 +367,16 @@ d3m_status d3m_plan_check(d3m_plan plan, int64_t* nviolations) {
   const PlanImpl& p = plan->p;
   if (p.facc.empty() || p.sacc.empty()) return D3M_ERR_STATE;  // too large to check
   int64_t a = check_dag(p.fdag, p.facc), b = check_dag(p.sdag, p.sacc);
+    if (p.nelim > 0) {
+    const int64_t c = p.sacc2.empty() ? -1 : check_dag(p.sdag2, p.sacc2);
+    if (c < 0) b = -1;
+    else b += c;
+  }
+  if (p.rhs_groups > 1) {
+    const int64_t c = p.saccg.empty() ? -1 : check_dag(p.sdagg, p.saccg);
+    if (c < 0) b = -1;
+    else b += c;
+  }
   if (a < 0 || b < 0) {
     *nviolations = -1;
     return D3M_ERR_STATE;
@@ -433,6 +465,13 @@ d3m_status d3m::bind_factor(d3m_plan plan, d3m_precision prec, void* dev_ws, siz
             up(f->lay.stasks, p.sdag.tasks.data(), p.sdag.tasks.size() * sizeof(Task)) &&
             up(f->lay.ssucc, p.sdag.succ.data(), p.sdag.succ.size() * 4) &&
             up(f->lay.scnt, p.sdag.npred.data(), p.sdag.npred.size() * 4) &&
+            up(f->lay.s2tasks, p.sdag2.tasks.data(), p.sdag2.tasks.size() * sizeof(Task)) &&
+            up(f->lay.s2succ, p.sdag2.succ.data(), p.sdag2.succ.size() * 4) &&
+                        up(f->lay.s2cnt, p.sdag2.npred.data(), p.sdag2.npred.size() * 4) &&
+            up(f->lay.sgtasks, p.sdagg.tasks.data(), p.sdagg.tasks.size() * sizeof(Task)) &&
+            up(f->lay.sgsucc, p.sdagg.succ.data(), p.sdagg.succ.size() * 4) &&
+            up(f->lay.sgcnt, p.sdagg.npred.data(), p.sdagg.npred.size() * 4) &&
+            up(f->lay.kg, f->tab.kg.data(), f->tab.kg.size() * sizeof(KPlaceDev)) &&
             up(f->lay.panels, p.panels.data(), p.panels.size() * sizeof(Panel)) &&
             up(f->lay.pblocks, p.pblocks.data(), p.pblocks.size() * sizeof(PBlock)) &&
             up(f->lay.tiles, p.tiles.data(), p.tiles.size() * sizeof(Tile)) &&
@@ -476,6 +515,7 @@ extern "C" {
 
 d3m_status d3m_factorize(d3m_factor f, const void* dev_K, d3m_stream stream) {
   if (!f || !dev_K) return D3M_ERR_ARG;
+  if (f->plan->p.nelim > 0) return D3M_ERR_STATE;  // a partial elimination: d3m_reduce
   if (stale(f)) return D3M_ERR_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const PlanImpl& p = f->plan->p;
@@ -483,7 +523,7 @@ d3m_status d3m_factorize(d3m_factor f, const void* dev_K, d3m_stream stream) {
                         f->opt.max_iter, s));
   HIPCHK(launch_scatter(dev_K, f->ws + f->lay.L, f->at<KPlaceDev>(f->lay.kp), (int)f->tab.kp.size(),
                         f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->prec, s));
-  d3m_status st = run_dag(f, false, f->nrhs_max, nullptr, s);
+  d3m_status st = run_dag(f, 0, f->nrhs_max, nullptr, s);
   if (st != D3M_OK) return st;
   HIPCHK(launch_knorm(dev_K, f->uv(), f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), f->ctrl(), s));
   f->last = s;
@@ -509,7 +549,7 @@ d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int n
   void* R64 = f->ws + f->lay.R64;
   if (f->prec == 0) {
     HIPCHK(launch_perm_in(B, ld, W, 0, uv, nrhs, nullptr, s));
-    d3m_status st = run_dag(f, true, nrhs, nullptr, s);
+    d3m_status st = run_dag(f, 1, nrhs, nullptr, s);
     if (st) return st;
     HIPCHK(launch_residual(K, B, ld, W, R64, f->ws + f->lay.P64, f->rmax(), uv, rt, nrt, nrhs, nullptr, s));
     HIPCHK(launch_colmax(W, N, nrhs, 0, 1, f->xmax(), nullptr, s));
@@ -519,7 +559,7 @@ d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int n
   }
   const int64_t nel = N * nrhs;
   HIPCHK(launch_perm_in(B, ld, W, 1, uv, nrhs, nullptr, s));
-  d3m_status st = run_dag(f, true, nrhs, nullptr, s);
+  d3m_status st = run_dag(f, 1, nrhs, nullptr, s);
   if (st) return st;
   HIPCHK(launch_cvt_up(W, X64, nel, s));
   const int32_t* stop = f->stop();
@@ -535,7 +575,7 @@ d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int n
     }
     if (it == f->opt.max_iter) break;
     HIPCHK(launch_cvt_down(R64, W, nel, stop, s));
-    st = run_dag(f, true, nrhs, stop, s);
+    st = run_dag(f, 1, nrhs, stop, s);
     if (st) return st;
     HIPCHK(launch_axpy_up(W, X64, nel, stop, s));
   }
@@ -548,7 +588,7 @@ d3m_status solve_impl(d3m_factor f, const void* K, const void* B, void* X, int n
 d3m_status d3m_solve(d3m_factor f, const void* dev_K, const void* dev_B, void* dev_X, int32_t nrhs, int64_t ld,
                      d3m_stream stream) {
   if (!f || !dev_K || !dev_B || !dev_X || nrhs < 1 || nrhs > f->nrhs_max || ld < f->plan->p.N) return D3M_ERR_ARG;
-  if (!f->factored || stale(f)) return D3M_ERR_STATE;
+  if (!f->factored || stale(f) || f->plan->p.nelim > 0) return D3M_ERR_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   d3m_status st = solve_impl(f, dev_K, dev_B, dev_X, nrhs, ld, s);
   f->last = s;
@@ -559,13 +599,69 @@ d3m_status d3m_adjoint(d3m_factor f, const void* dev_K, const void* dev_X, const
                        void* dev_dK, int32_t nrhs, int64_t ld, d3m_stream stream) {
   if (!f || !dev_K || !dev_X || !dev_G || !dev_Lambda || nrhs < 1 || nrhs > f->nrhs_max || ld < f->plan->p.N)
     return D3M_ERR_ARG;
-  if (!f->factored || stale(f)) return D3M_ERR_STATE;
+  if (!f->factored || stale(f) || f->plan->p.nelim > 0) return D3M_ERR_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   d3m_status st = solve_impl(f, dev_K, dev_G, dev_Lambda, nrhs, ld, s);
   if (st) return st;
   if (dev_dK)
     HIPCHK(launch_dk(dev_Lambda, dev_X, ld, nrhs, dev_dK, f->uv(), f->at<DkTaskDev>(f->lay.dkt),
                      (int)f->tab.dkt.size(), f->opt.dk_stored, s));
+  f->last = s;
+  return D3M_OK;
+}
+
+d3m_status d3m_reduce(d3m_factor f, const void* dev_A, const void* dev_F, int64_t ldf, void* dev_Kred,
+                      void* dev_Gred, int64_t ldg, int32_t nrhs, d3m_stream stream) {
+  if (!f || !dev_A || nrhs < 1 || nrhs > f->nrhs_max) return D3M_ERR_ARG;
+  const PlanImpl& p = f->plan->p;
+  if (p.nelim <= 0 || f->prec != 0) return D3M_ERR_STATE;  // needs a partial plan and a complex128 factor
+  if (dev_F && (ldf < p.N || !dev_Gred || ldg < p.N - p.N_elim)) return D3M_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the eliminated blocks' factor, their Schur complement on the others
+  HIPCHK(launch_prepare(f->at<int32_t>(f->lay.status), f->at<float>(f->lay.growth), p.nb, f->ctrl(), f->opt.tol,
+                        f->opt.max_iter, s));
+  HIPCHK(launch_scatter(dev_A, f->ws + f->lay.L, f->at<KPlaceDev>(f->lay.kp), (int)f->tab.kp.size(),
+                        f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->prec, s));
+  d3m_status st = run_dag(f, 0, f->nrhs_max, nullptr, s);
+  if (st != D3M_OK) return st;
+  if (dev_Kred) {
+    int maxe = 1;
+    for (const auto& k : f->tab.kg) maxe = std::max(maxe, k.rows * k.cols);
+    HIPCHK(launch_gather_red(f->ws + f->lay.L, dev_Kred, f->at<KPlaceDev>(f->lay.kg), (int)f->tab.kg.size(), p.nred,
+                             maxe, s));
+  }
+  // the forward part of the solve: the reduced right-hand sides are left in
+  // the rows of the blocks not eliminated (internal rows N_elim..N)
+  if (dev_F) {
+    HIPCHK(launch_perm_in(dev_F, ldf, f->ws + f->lay.W, 0, f->uv(), nrhs, nullptr, s));
+    st = run_dag(f, 1, nrhs, nullptr, s);
+    if (st != D3M_OK) return st;
+    HIPCHK(launch_perm_rows(f->ws + f->lay.W, 0, dev_Gred, ldg, f->uv(), p.N_elim, p.N, nrhs, 1, s));
+    f->red_nrhs = nrhs;
+  } else {
+    f->red_nrhs = 0;
+  }
+  f->last = s;
+  f->factored = true;
+  return D3M_OK;
+}
+
+d3m_status d3m_recover(d3m_factor f, const void* dev_Xred, int64_t ldx, void* dev_U, int64_t ldu, int32_t nrhs,
+                       const void* dev_M, int64_t ldm, int32_t nports, void* dev_S, d3m_stream stream) {
+  if (!f || !dev_Xred || !dev_U || nrhs < 1) return D3M_ERR_ARG;
+  const PlanImpl& p = f->plan->p;
+  if (p.nelim <= 0 || !f->factored || f->red_nrhs != nrhs) return D3M_ERR_STATE;  // after d3m_reduce with F
+  if (ldx < p.N - p.N_elim || ldu < p.N || (nports > 0 && (!dev_M || !dev_S || ldm < p.N)) || nports < 0)
+    return D3M_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the given solution of the blocks left into their rows, then the backward
+  // part of the solve over the eliminated blocks
+  HIPCHK(launch_perm_rows(dev_Xred, ldx, f->ws + f->lay.W, 0, f->uv(), p.N_elim, p.N, nrhs, 0, s));
+  d3m_status st = run_dag(f, 2, nrhs, nullptr, s);
+  if (st != D3M_OK) return st;
+  HIPCHK(launch_perm_out(f->ws + f->lay.W, dev_U, ldu, f->uv(), nrhs, s));
+  if (nports > 0) HIPCHK(launch_ports(dev_M, ldm, dev_U, ldu, p.N, nports, nrhs, dev_S, s));
+  f->red_nrhs = 0;  // the forward part's z is used up
   f->last = s;
   return D3M_OK;
 }
@@ -584,7 +680,19 @@ d3m_status d3m_status_sync(d3m_factor f, d3m_run_info* out) {
   out->pivot_row = -1;
   out->status = D3M_OK;
   if (st[0] != 0x7fffffff) {
-    out->pivot_row = f->tab.perm[st[0]];
+    int64_t q = st[0];
+    if (f->opt.pivot) {
+      // st[0] is a position inside a pivoted tile: the unknown there is the
+      // tile's ipiv[q]-th
+      const PlanImpl& p = f->plan->p;
+      int32_t ip = 0;
+      HIPCHK(hipMemcpy(&ip, f->at<int32_t>(f->lay.ipiv) + q, 4, hipMemcpyDeviceToHost));
+      for (const Tile& T : p.tiles) {
+        const int64_t t0 = p.panels[T.panel].prow0 + T.r0;
+        if (q >= t0 && q < t0 + T.sz) { q = t0 + ip; break; }
+      }
+    }
+    out->pivot_row = f->tab.perm[q];
     out->status = D3M_ZERO_PIVOT;
   }
   out->ir_iters = c.iters;
@@ -688,7 +796,7 @@ d3m_status d3m_factor_tasks(d3m_factor f, int32_t solve, int32_t* kinds, int32_t
   const int n = (int)dag.tasks.size();
   if (kinds && panels && mnk)
     for (int i = 0; i < n; ++i) {
-      kinds[i] = dag.tasks[i].kind;
+            kinds[i] = dag.tasks[i].kind & 0xff;
       panels[i] = dag.tasks[i].panel;
       mnk[3 * i] = dag.tasks[i].m;
       mnk[3 * i + 1] = dag.tasks[i].n;
@@ -797,8 +905,9 @@ d3m_status batch_dag(d3m_batch_s* b, bool solve, const int32_t* skip, hipStream_
   a.abort_flag = flags + 1;
   a.skip = skip;
   a.inst = b->at<InstView>(b->lay.iv);
-  a.ntask = (int32_t)dag.tasks.size();
+    a.ntask = (int32_t)dag.tasks.size();
   a.nrhs = 0;
+  a.rhs_groups = 1;
   a.spin_limit_ns = 20LL * 1000 * 1000 * 1000;
   a.trace = nullptr;
   HIPCHK(launch_reset(a.counters, b->at<int32_t>(solve ? b->lay.scnt : b->lay.fcnt), a.ntask, a.head, a.abort_flag,

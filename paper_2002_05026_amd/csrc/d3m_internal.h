@@ -35,8 +35,9 @@ struct XSrc {
   int32_t k, lda;
 };
 
-// Sources of one merged update task at most (factor, forward solve).
-constexpr int kMergeSrc = 8;
+// Sources of one merged update task at most (factor, forward solve); the
+// plan's merge option picks the count up to this bound.
+constexpr int kMergeSrc = 16;
 constexpr int kMergeSolve = 1;
 
 // One task, in ticket order.  Offsets are in complex elements, relative to
@@ -125,6 +126,7 @@ struct DagArgs {
   const InstView* inst;
   int32_t ntask;
   int32_t nrhs;          // right-hand sides of a solve launch (0: the instance's own)
+  int32_t rhs_groups;    // groups of right-hand-side columns of the launched solve DAG (task kind >> 8)
   int64_t spin_limit_ns; // watchdog bound on one dependency wait
   int64_t* trace;        // optional: per ticket {taken, ready, done, workgroup} (100 MHz clock)
 };

@@ -33,9 +33,11 @@ template <typename T> struct Ctx {
   C* Gi;  // with pivoting: D^-1 L^-1 P of each diagonal block (Li then holds L^-1 P)
   C* W;
   C* Z;
-  const InstView* iv;
+    const InstView* iv;
   lds_char* lds;
-  int nrhs;
+  int nrhs;   // right-hand sides of the launch: the row stride of W and Z
+  int j0;     // solve tasks: first column of the task's right-hand-side group
+  int ncols;  // and its column count
 };
 
 // Task bodies are separate functions (each gets its own register
@@ -83,7 +85,9 @@ template <typename T> __device__ __forceinline__ Ctx<T> uniform_ctx(const Ctx<T>
   c.Z = ufirst_ptr(a.Z);
   c.iv = ufirst_ptr(a.iv);
   c.lds = (lds_char*)(uintptr_t)(uint32_t)ufirst((int32_t)(uint32_t)(uintptr_t)a.lds);
-  c.nrhs = ufirst(a.nrhs);
+    c.nrhs = ufirst(a.nrhs);
+  c.j0 = ufirst(a.j0);
+  c.ncols = ufirst(a.ncols);
   return c;
 }
 
@@ -271,21 +275,22 @@ template <typename T>
 __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-  const int nr = cx.nrhs;
+    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   Acc<T> acc;
   acc.zero();
   if (cx.iv->pivot) {
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, nr, t.k + t.pad0, opn<T>(cx.Gi + t.a_off, t.lda), nullptr,
-                                        opn<T>(cx.W + t.b_off * nr, nr), cx.lds);
-    gemm_store<T>(acc, t.m, nr, outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)1, (T)0));
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, t.k + t.pad0,
+                                                               opn<T>(cx.Gi + t.a_off, t.lda), nullptr,
+                                                               opn<T>(cx.W + t.b_off * nr + j0, nr), cx.lds);
+    gemm_store<T>(acc, t.m, nc, outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0));
     return;
   }
-  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, nr, t.k, opn<T>(cx.Li + t.a_off, t.lda), nullptr,
-                                    opn<T>(cx.W + t.b_off * nr, nr),
-              cx.lds);
-  Out<T> o = outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)1, (T)0);
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, t.k, opn<T>(cx.Li + t.a_off, t.lda),
+                                                             nullptr, opn<T>(cx.W + t.b_off * nr + j0, nr),
+                                                             cx.lds);
+  Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
   o.rowdiv = cx.D + t.dofs;
-  gemm_store<T>(acc, t.m, nr, o);
+  gemm_store<T>(acc, t.m, nc, o);
 }
 
 // forward update: b_r -= sum over the task's sources of (L_rI D_I) z_I
@@ -293,19 +298,20 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
 // operands); t.n = 1: the target is an extra accumulator written first
 template <typename T>
 __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
-  const int nr = cx.nrhs;
+    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   Acc<T> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
   for (int q = 0; q < nsrc; ++q) {
     XSrc x{t.a_off, t.b_off, t.k, t.lda};
     if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, nr, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
-                                      opn<T>(cx.Z + x.b_off * nr, nr), cx.lds);
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, x.k, opn<T>(cx.LD + x.a_off, x.lda),
+                                                               nullptr, opn<T>(cx.Z + x.b_off * nr + j0, nr),
+                                                               cx.lds);
   }
   // two stores with a constant beta each, so neither has a per-element branch
-  if (t.n) gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)0));
-  else gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)-1, (T)1));
+  if (t.n) gemm_store<T>(acc, t.m, nc, outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)0));
+  else gemm_store<T>(acc, t.m, nc, outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)1));
 }
 
 // b_r += the t.k extra accumulators of tile r (N rows apart) (TK_RED)
@@ -313,9 +319,10 @@ template <typename T>
 __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-  const int64_t nr = cx.nrhs, stride = cx.iv->N * nr;
-  D3M_GLB cpx<T>* w = gptr_mut<T>(cx.W + t.c_off * nr);
-  const int64_t tot = (int64_t)t.m * nr;
+    const int64_t nr = cx.nrhs, stride = cx.iv->N * nr, nc = cx.ncols;
+  D3M_GLB cpx<T>* w = gptr_mut<T>(cx.W + t.c_off * nr + cx.j0);
+  const int64_t tot = (int64_t)t.m * nc;
+  auto at = [&](int64_t e) { return (e / nc) * nr + e % nc; };  // element e: row e / nc, group column e % nc
   // a thread's elements in batches of E, every load of a batch issued before
   // its first add (one memory latency per batch instead of one per element);
   // element e adds accumulators 1..t.k onto b in that order.  Loads beyond
@@ -325,7 +332,7 @@ __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
     cpx<T> v[E], u[kSolveSlots][E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const int64_t e = e0 + (int64_t)i * kThreads, ec = e < tot ? e : 0;
+            const int64_t e = e0 + (int64_t)i * kThreads, ec = e < tot ? at(e) : 0;
       v[i] = w[ec];
 #pragma unroll
       for (int q = 0; q < kSolveSlots; ++q) u[q][i] = w[(q < t.k ? (q + 1) * stride : 0) + ec];
@@ -339,7 +346,7 @@ __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
           v[i].x += u[q][i].x;
           v[i].y += u[q][i].y;
         }
-      if (e < tot) w[e] = v[i];
+            if (e < tot) w[at(e)] = v[i];
     }
   }
 }
@@ -349,13 +356,12 @@ template <typename T>
 __device__ __noinline__ void task_bupd(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-  const int nr = cx.nrhs;
+    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, t.m, nr, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T), nullptr,
-                                    opn<T>(cx.W + t.b_off * nr, nr),
-              cx.lds);
-  gemm_store<T>(acc, t.m, nr, outp<T>(cx.Z + t.c_off * nr, nr, 1, (T)-1, (T)1));
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(acc, t.m, nc, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T),
+                                                              nullptr, opn<T>(cx.W + t.b_off * nr + j0, nr), cx.lds);
+  gemm_store<T>(acc, t.m, nc, outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)-1, (T)1));
 }
 
 // backward, one tile: x_c = sum_{p >= r0_c} Linv_II(p, c) t_p; with
@@ -365,18 +371,18 @@ template <typename T>
 __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-  const int nr = cx.nrhs;
+    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   Acc<T> acc;
   acc.zero();
   const int back = cx.iv->pivot ? t.pad0 : 0;
-  gemm_acc<T, 8, GeKB<T>::KB, OP_T>(acc, t.m, nr, t.k + back, opn<T>(cx.Li + t.a_off - back, t.lda, OP_T), nullptr,
-                                    opn<T>(cx.Z + (t.b_off - back) * nr, nr),
-              cx.lds);
-  gemm_store<T>(acc, t.m, nr, outp<T>(cx.W + t.c_off * nr, nr, 1, (T)1, (T)0));
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(
+      acc, t.m, nc, t.k + back, opn<T>(cx.Li + t.a_off - back, t.lda, OP_T), nullptr,
+      opn<T>(cx.Z + (t.b_off - back) * nr + j0, nr), cx.lds);
+  gemm_store<T>(acc, t.m, nc, outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)1, (T)0));
 }
 
 template <typename T, bool PRESRC = false>
-__device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char* lds) {
+__device__ void run_task(const Task& t, const InstView* ivs, int nrhs, int groups, lds_char* lds) {
   typedef typename Cplx<T>::type C;
   Ctx<T> cx;
   cx.iv = ivs + t.inst;
@@ -388,8 +394,13 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, lds_char*
   cx.W = reinterpret_cast<C*>(cx.iv->W);
   cx.Z = reinterpret_cast<C*>(cx.iv->Z);
   cx.lds = lds;
-  cx.nrhs = nrhs > 0 ? nrhs : cx.iv->nrhs;
-  switch (t.kind) {
+    cx.nrhs = nrhs > 0 ? nrhs : cx.iv->nrhs;
+  // the right-hand-side group of a solve task (bits 8.. of the kind)
+  const int grp = t.kind >> 8, per = (cx.nrhs + groups - 1) / groups;
+  cx.j0 = grp * per;
+  cx.ncols = min(cx.nrhs, cx.j0 + per) - cx.j0;
+  if (cx.ncols <= 0) return;
+  switch (t.kind & 0xff) {
     case TK_FACT: task_fact<T>(cx, t); break;
     case TK_TRSM: task_trsm<T>(cx, t); break;
     case TK_XUPD: task_xupd<T, PRESRC>(cx, t); break;
@@ -517,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
     const int t = __builtin_amdgcn_readfirstlane(s_ticket);
     if (t < 0) break;
     const Task task = uniform_task(s_task[b]);
-    run_task<T, kPreSrc>(task, a.inst, a.nrhs, (lds_char*)lds);
+        run_task<T, kPreSrc>(task, a.inst, a.nrhs, a.rhs_groups > 0 ? a.rhs_groups : 1, (lds_char*)lds);
     // The source table is single-buffered: the only task that reads it (a
     // merged XUPD) ends with a barrier after its last read, and every LDS
     // access of any task after its last barrier lies below the table, so
@@ -539,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const Task* tasks, int begin
   int t = begin + blockIdx.x;
   if (t >= end) return;
   const Task task = tasks[t];
-  run_task<T>(task, iv, 0, (lds_char*)lds);
+    run_task<T>(task, iv, 0, 1, (lds_char*)lds);
 }
 
 __global__ void k_reset(int32_t* counters, const int32_t* init, int n, int32_t* head, int32_t* abort_flag,

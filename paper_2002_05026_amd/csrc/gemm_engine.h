@@ -453,7 +453,9 @@ __device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Ou
 // PRE: the store's beta term goes out at the start of the last slab (the
 // last slab is peeled off so that those values are live only there).
 // Starts and ends with a barrier.
-template <typename T, int NBMAX, bool PRE, bool TR, typename SRC>
+// W2: a two-block accumulator width too (n in 17..32), for callers whose n
+// is the right-hand-side count of a solve (the factor keeps three widths).
+template <typename T, int NBMAX, bool PRE, bool TR, bool W2 = false, typename SRC>
 __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc, const SRC& src, lds_char* lds,
                                         GePre<T>* pre, const Out<T>* po) {
   constexpr int KD = GeDma<T>::KB, NB = GeDma<T>::NBUF, SL = 2 * KD * GE_LDP;
@@ -553,6 +555,7 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
     }
   };
   if (NBMAX > 4 && nbj > 4) run(std::integral_constant<int, (NBMAX > 4 ? 8 : 1)>());
+  else if (W2 && NBMAX > 1 && nbj == 2) run(std::integral_constant<int, (NBMAX > 1 ? 2 : 1)>());
   else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
   else run(std::integral_constant<int, 1>());
 }
@@ -571,8 +574,9 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
 // into *pre at the start of the last slab's products, so that its latency
 // overlaps them (pre->ok tells the store).  A flag rather than a null test:
 // a null test of a pointer to a local keeps the local out of registers.
+// W2: see ge_pipe.
 template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool PRE = false,
-          bool TR = false>
+          bool TR = false, bool W2 = false>
 __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds,
                          GePre<T>* pre = nullptr, const Out<T>* po = nullptr) {
@@ -603,7 +607,7 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
         e.a = A.p; e.b = B.p; e.lda = A.ld; e.ldb = B.ld; e.k = k; e.pad = 0;
         return e;
       };
-      ge_pipe<T, NBMAX, PRE, TR>(acc, m, n, 1, one, lds, pre, po);
+      ge_pipe<T, NBMAX, PRE, TR, W2>(acc, m, n, 1, one, lds, pre, po);
       return;
     }
   }
@@ -661,6 +665,7 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
   }
   };
   if (NBMAX > 4 && nbj > 4) run(std::integral_constant<int, (NBMAX > 4 ? 8 : 1)>());
+  else if (W2 && NBMAX > 1 && nbj == 2) run(std::integral_constant<int, (NBMAX > 1 ? 2 : 1)>());
   else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
   else run(std::integral_constant<int, 1>());
 }

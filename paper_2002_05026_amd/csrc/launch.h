@@ -73,6 +73,15 @@ hipError_t launch_knorm(const void* K, const UserView& uv, const RTaskDev* rt, i
 hipError_t launch_perm_in(const void* B, int64_t ld, void* W, int prec, const UserView& uv, int nrhs,
                           const int32_t* skip, hipStream_t s);
 hipError_t launch_perm_out(const void* W, void* X, int64_t ld, const UserView& uv, int nrhs, hipStream_t s);
+// complex128 rows [q0, q1) of the internal order only; out = 0: user -> internal, 1: internal -> user
+hipError_t launch_perm_rows(const void* src, int64_t lds, void* dst, int64_t ldd, const UserView& uv, int64_t q0,
+                            int64_t q1, int nrhs, int out, hipStream_t s);
+// reduced matrix out of panel storage (the first ndiag entries are diagonal blocks)
+hipError_t launch_gather_red(const void* L, void* K, const KPlaceDev* kg, int nkg, int ndiag, int maxelems,
+                             hipStream_t s);
+// S = M^T U over N rows (bilinear), nports x nrhs, complex128
+hipError_t launch_ports(const void* M, int64_t ldm, const void* U, int64_t ldu, int64_t N, int nports, int nrhs,
+                        void* S, hipStream_t s);
 // R = B - K X (internal order, RHS fastest) and the column maxima of |R|;
 // P: kResSplit * N * nrhs complex128 of scratch for the partial products.
 hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64, void* P,

@@ -219,13 +219,22 @@ int64_t key3(int64_t panel, int64_t g, int64_t c) { return (panel << 40) | (g <<
 
 // ----------------------------------------------------------------- the plan
 std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair, const int32_t* pairs,
-                       const int32_t* order, const int32_t* grid, int tile, int nworkers, int sched,
-                       int* err) {
+                       const int32_t* order, const int32_t* grid, int tile, int nworkers, int sched, int nelim,
+                       int solve_tile, int merge, int rhs_groups, int* err) {
   *err = -1;  // D3M_ERR_ARG
   if (nb <= 0 || !sizes || npair < 0 || (npair > 0 && !pairs)) return "bad sizes or pairs";
   if (tile == 0) tile = 128;
   if (tile < 16 || tile > kTileMax || tile % 16) return "tile must be a multiple of 16 in [16,128]";
   p.tile = tile;
+  if (solve_tile == 0) solve_tile = 64;
+  if (solve_tile < 16 || solve_tile > kTileMax || solve_tile % 16) return "solve_tile must be a multiple of 16 in [16,128]";
+  p.solve_tile = solve_tile;
+  if (merge == 0) merge = 8;
+  if (merge < 1 || merge > kMergeSrc) return "merge must be in [1, 16]";
+  p.merge = merge;
+  if (rhs_groups == 0) rhs_groups = 1;
+  if (rhs_groups < 1 || rhs_groups > 8) return "rhs_groups must be in [1, 8]";
+  p.rhs_groups = rhs_groups;
   p.nworkers = nworkers > 0 ? nworkers : 256;
   p.sched = sched;
   p.nb = nb;
@@ -265,6 +274,24 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   p.order = ord;
   p.pos.assign(nb, 0);
   for (int k = 0; k < nb; ++k) p.pos[ord[k]] = k;
+  // partial elimination: the first nelim blocks of the order are eliminated,
+  // the others must be the user ids 0..nred-1, and the pairs between them
+  // must come first in the pair list
+  if (nelim < 0 || nelim >= nb) {
+    if (nelim != 0) return "nelim must be in [0, nblk)";
+  }
+  p.nelim = nelim;
+  p.nred = nelim > 0 ? nb - nelim : 0;
+  if (nelim > 0) {
+    for (int k = nelim; k < nb; ++k)
+      if (ord[k] >= p.nred) return "the blocks left after a partial elimination must be the user ids 0..nred-1";
+    int64_t npr = 0;
+    while (npr < npair && p.pairs[npr][0] < p.nred && p.pairs[npr][1] < p.nred) ++npr;
+    for (int64_t k = npr; k < npair; ++k)
+      if (p.pairs[k][0] < p.nred && p.pairs[k][1] < p.nred)
+        return "the pairs between the blocks left must come first";
+    p.npair_red = (int)npr;
+  }
   // block fill by elimination in position space
   std::vector<std::set<int>> adj(nb);
   for (auto& pr : p.pairs) {
@@ -284,6 +311,20 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       }
     p.S[I] = later;  // std::set iteration is sorted
   }
+  if (nelim > 0) {
+    // eliminating the leading blocks must create no block between the others
+    // that is not in the pair list (the reduced matrix keeps K's layout)
+    std::set<std::pair<int, int>> red;
+    for (int k = 0; k < p.npair_red; ++k) red.insert({p.pairs[k][0], p.pairs[k][1]});
+    for (int I = 0; I < nelim; ++I)
+      for (size_t u = 0; u < p.S[I].size(); ++u)
+        for (size_t v = 0; v < u; ++v) {
+          const int a = p.order[p.S[I][u]], b = p.order[p.S[I][v]];
+          if (a >= p.nred || b >= p.nred) continue;
+          if (!red.count({std::max(a, b), std::min(a, b)}))
+            return "a partial elimination fills a block between the blocks left that is not a pair";
+        }
+  }
   // counts and flops (8 real flops per complex multiply-add)
   p.L_blocks = 0;
   p.nnz_L = 0;
@@ -292,9 +333,11 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   p.etree_height = 0;
   p.max_S = 0;
   auto nn = [&](int position) { return (double)p.n[p.order[position]]; };
+  const int nfac = nelim > 0 ? nelim : nb;  // panels eliminated
   for (int I = 0; I < nb; ++I) {
     double nI = nn(I);
     p.nnz_L += (int64_t)nI * ((int64_t)nI + 1) / 2;
+    if (I >= nfac) continue;
     p.flops_diag += 4.0 / 3.0 * nI * nI * nI;
     p.L_blocks += p.S[I].size();
     p.max_S = std::max(p.max_S, (int)p.S[I].size());
@@ -308,7 +351,14 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
     p.etree_height = std::max(p.etree_height, height[I]);
     if (!p.S[I].empty()) height[p.S[I][0]] = std::max(height[p.S[I][0]], height[I] + 1);
   }
-  p.fill_blocks = p.L_blocks - npair;
+  if (nelim > 0) {
+    int64_t orig_in = 0;  // pairs stored in an eliminated panel
+    for (auto& pr : p.pairs)
+      if (std::min(p.pos[pr[0]], p.pos[pr[1]]) < nelim) ++orig_in;
+    p.fill_blocks = p.L_blocks - orig_in;
+  } else {
+    p.fill_blocks = p.L_blocks - npair;
+  }
   for (int i = 0; i < nb; ++i) p.nnz_K += (int64_t)p.n[i] * (p.n[i] + 1) / 2;
   for (auto& pr : p.pairs) p.nnz_K += (int64_t)p.n[pr[0]] * p.n[pr[1]];
 
@@ -465,6 +515,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       pend.erase(it);
     }
     pend_of[I].clear();
+    if (I >= nfac) continue;  // left with its Schur complement (partial elimination)
     // row tiles of the panel: (global tile index, row offset in panel)
     std::vector<std::pair<int, int>> rows;
     for (int b = 0; b < P.npb; ++b) {
@@ -628,7 +679,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
                 pu.ac.push_back({key3(I, PK.tile0 + s2, c), false});
                 pu.ac.push_back({kDKey | (P.tile0 + c), false});
               }
-            if ((int)pu.src.size() >= kMergeSrc) {
+            if ((int)pu.src.size() >= p.merge) {
               emit_upd(tk, pu);
               pend.erase(it);
             }
@@ -642,13 +693,13 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   // ---- solve DAG: forward (elimination order), then backward (reverse).
   // W holds b (then x), Z holds z = D^-1 L^-1 b (then t); the diagonal
   // blocks are applied through their precomputed inverses.  The solve cuts
-  // each factor tile into row tiles of at most kSolveTile rows: a solve task
+  // each factor tile into row tiles of at most solve_tile rows: a solve task
   // has only nrhs columns, and a 64-row task keeps one wave per SIMD busy in
   // about half the time of a 128-row one, which shortens the chains of
   // updates into one tile that bound the solve.  Solve tiles never cross a
   // factor tile: the tile rows of Linv_II are only valid left of the end of
   // their factor tile (the upper tiles serve the INV tasks as staging).
-  constexpr int kSolveTile = 64;
+  const int kSolveTile = p.solve_tile;
   std::vector<int> st0(nb + 1, 0);  // solve tiles of panel I: st0[I] .. st0[I+1]-1
   std::vector<std::pair<int, int>> stl;  // (r0, sz)
   std::vector<std::pair<int, int>> stf;  // (first row, end) of the factor tile holding each solve tile
@@ -666,183 +717,268 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
     }
     st0[I + 1] = (int)stl.size();
   }
-  GenDag sg;
-  std::vector<std::vector<Access>> sacc;
-  std::vector<int> lastb(stl.size(), -1), lastz(stl.size(), -1);
-  std::vector<std::vector<int>> ftile(nb), btile(nb);
-  const int64_t kWKey = 1LL << 60, kZKey = 1LL << 58;
-  auto wkey = [&](int slot, int r) { return kWKey | ((int64_t)slot << 40) | r; };
-  // forward updates into tile r: groups of up to kMergeSolve consecutive
-  // sources form one task; groups go round-robin to b and its extra
-  // accumulators (count of groups so far, last task per extra slot)
-  std::vector<int> nupd(stl.size(), 0);
-  std::vector<std::array<int, kSolveSlots + 1>> lastx(stl.size());
-  for (auto& a : lastx) a.fill(-1);
-  struct PendF {
-    Task t;
-    std::vector<int32_t> pr;
-    std::vector<Access> ac;
-    std::vector<XSrc> src;
-    double w = 22.0;
-  };
-  std::vector<PendF> pendf(stl.size());
-  auto emit_fupd = [&](int r) {
-    PendF& pf = pendf[r];
-    if (pf.src.empty()) return;
-    const int slot = nupd[r]++ % (kSolveSlots + 1);
-    Task u = pf.t;
-    u.c_off += (int64_t)slot * p.N;                     // rows of b_r (or a copy) in W
-    u.n = (slot > 0 && lastx[r][slot] < 0) ? 1 : 0;     // first into a copy: overwrite
-    if (pf.src.size() > 1) {
-      u.pad0 = (int32_t)pf.src.size();
-      u.pad1 = (int32_t)p.xsrc.size();
-      u.k = 0;
-      for (auto& x : pf.src) {
-        p.xsrc.push_back(x);
-        u.k += x.k;
-      }
-    }
-    std::vector<int32_t> pr = pf.pr;
-    pr.push_back(slot == 0 ? lastb[r] : lastx[r][slot]);
-    std::vector<Access> ac = pf.ac;
-    ac[0] = {wkey(slot, r), true};
-    int uid = sg.add(u, pr, pf.w);
-    if (slot == 0) lastb[r] = uid;
-    else lastx[r][slot] = uid;
-    sacc.push_back(ac);
-    pf = PendF();
-  };
-  for (int I = 0; I < nb; ++I) {
-    const Panel& P = p.panels[I];
-    for (int c = st0[I]; c < st0[I + 1]; ++c) emit_fupd(c);
-    // sum the extra accumulators of I's tiles into b_I
-    for (int c = st0[I]; c < st0[I + 1]; ++c) {
-      const int used = std::min(nupd[c], kSolveSlots + 1) - 1;
-      if (used <= 0) continue;
-      Task t{};
-      t.kind = TK_RED;
-      t.panel = I;
-      t.m = stl[c].second;
-      t.k = used;
-      t.aux = c;
-      t.c_off = P.prow0 + stl[c].first;
-      std::vector<int32_t> pr{lastb[c]};
-      std::vector<Access> ac{{wkey(0, c), true}};
-      for (int q = 1; q <= used; ++q) {
-        pr.push_back(lastx[c][q]);
-        ac.push_back({wkey(q, c), false});
-      }
-      lastb[c] = sg.add(t, pr, 10.0);
-      sacc.push_back(ac);
-    }
-    std::vector<int32_t> inpr;
-    for (int c = st0[I]; c < st0[I + 1]; ++c) inpr.push_back(lastb[c]);
-    for (int c = st0[I]; c < st0[I + 1]; ++c) {
-      const int r0 = stl[c].first, sz = stl[c].second;
-      Task t{};
-      t.kind = TK_FTILE;
-      t.panel = I;
-      t.m = sz;
-      t.k = r0 + sz;
-      t.lda = P.n;
-      t.aux = c;
-      t.a_off = P.ioff + r0;
-      t.b_off = P.prow0;
-      t.c_off = P.prow0 + r0;
-      t.dofs = P.prow0 + r0;
-      t.pad0 = stf[c].second - (r0 + sz);  // with pivoting the sum runs to the factor tile's end
-      std::vector<Access> ac{{kZKey | c, true}};
-      for (int q = st0[I]; q < st0[I + 1]; ++q) ac.push_back({wkey(0, q), false});
-      int id = sg.add(t, inpr, w_solve(sz, r0 + sz));
-      ftile[I].push_back(id);
-      lastz[c] = id;
-      sacc.push_back(ac);
-    }
-    for (int b = 1; b < P.npb; ++b) {
-      const PBlock& B = p.pblocks[P.pb0 + b];
-      const Panel& PJ = p.panels[B.J];
-      for (int r = st0[B.J]; r < st0[B.J + 1]; ++r) {
-        const int r0 = stl[r].first, sz = stl[r].second;
-        PendF& pf = pendf[r];
-        if (pf.src.empty()) {
-          Task u{};
-          u.kind = TK_FUPD;
-          u.panel = I;
-          u.m = sz;
-          u.k = P.n;
-          u.lda = P.H;
-          u.aux = r;
-          u.a_off = P.off + B.prow + r0;                  // rows of (L D)_rI in LD
-          u.b_off = P.prow0;                              // rows of z_I in Z
-          u.c_off = PJ.prow0 + r0;
-          pf.t = u;
-          pf.ac.push_back({0, true});  // the target, set when the slot is known
-        }
-        pf.pr.insert(pf.pr.end(), ftile[I].begin(), ftile[I].end());
-        for (int c = st0[I]; c < st0[I + 1]; ++c) pf.ac.push_back({kZKey | c, false});
-        pf.src.push_back({P.off + B.prow + r0, P.prow0, P.n, P.H});
-        pf.w += tile_work(sz, 64, P.n) / 5.5e5 + (pf.src.size() > 1 ? 3.0 : 0.0);
-        if ((int)pf.src.size() >= kMergeSolve) emit_fupd(r);
-      }
-    }
-  }
   std::vector<std::vector<std::pair<int, int>>> holders(nb);  // J -> (panel I, row offset of J in I)
   for (int I = 0; I < nb; ++I)
     for (int b = 1; b < p.panels[I].npb; ++b) {
       const PBlock& B = p.pblocks[p.panels[I].pb0 + b];
       holders[B.J].push_back({I, B.prow});
     }
-  for (int J = nb - 1; J >= 0; --J) {
-    const Panel& PJ = p.panels[J];
-    std::vector<int32_t> zpr;
-    for (int c = st0[J]; c < st0[J + 1]; ++c) zpr.push_back(lastz[c]);
-    for (int c = st0[J]; c < st0[J + 1]; ++c) {
-      const int r0 = stl[c].first, sz = stl[c].second;
-      Task t{};
-      t.kind = TK_BTILE;
-      t.panel = J;
-      t.m = sz;
-      t.k = PJ.n - r0;
-      t.lda = PJ.n;
-      t.aux = c;
-      t.a_off = PJ.ioff + r0 + (int64_t)r0 * PJ.n;
-      t.b_off = PJ.prow0 + r0;
-      t.c_off = PJ.prow0 + r0;
-      t.pad0 = r0 - stf[c].first;  // with pivoting the sum starts at the factor tile's first row
-      std::vector<Access> ac{{wkey(0, c), true}};
-      for (int q = st0[J]; q < st0[J + 1]; ++q) ac.push_back({kZKey | q, false});
-      int id = sg.add(t, zpr, w_solve(sz, PJ.n - r0));
-      btile[J].push_back(id);
-      lastb[c] = id;
-      sacc.push_back(ac);
+  const int64_t kWKey = 1LL << 60, kZKey = 1LL << 58;
+  // The right-hand sides may be split into G groups of columns: the solve
+  // DAG is then G independent copies, copy g working on columns
+  // [g ceil(nrhs/G), (g+1) ceil(nrhs/G)) (its group is kept in bits 8.. of
+  // the task kind).  Twice the tasks of half the length: twice the
+  // parallelism and half as long dependency chains.
+  struct GState {
+    std::vector<int> lastb, lastz, nupd;
+    std::vector<std::vector<int>> ftile, btile;
+    std::vector<std::array<int, kSolveSlots + 1>> lastx;
+    struct PendF {
+      Task t;
+      std::vector<int32_t> pr;
+      std::vector<Access> ac;
+      std::vector<XSrc> src;
+      double w = 22.0;
+    };
+    std::vector<PendF> pendf;
+  };
+  auto gen_solve = [&](int G, TaskDag& fwd_out, std::vector<std::vector<Access>>& fwd_acc, TaskDag* bwd_out,
+                       std::vector<std::vector<Access>>* bwd_acc) {
+    GenDag sg, sgb;
+    std::vector<std::vector<Access>> sacc, saccb;
+    const bool split = bwd_out != nullptr;  // backward part as a launch of its own
+    GenDag& bg = split ? sgb : sg;
+    std::vector<std::vector<Access>>& bacc = split ? saccb : sacc;
+    const double wn = std::max(16, 64 / G);  // columns per task, for the weights
+    auto wsolve = [&](double m, double k) { return 22.0 + tile_work(m, wn, k) / 5.5e5; };
+    std::vector<GState> gs(G);
+    for (auto& q : gs) {
+      q.lastb.assign(stl.size(), -1);
+      q.lastz.assign(stl.size(), -1);
+      q.nupd.assign(stl.size(), 0);
+      q.ftile.assign(nb, {});
+      q.btile.assign(nb, {});
+      q.lastx.resize(stl.size());
+      for (auto& a : q.lastx) a.fill(-1);
+      q.pendf.assign(stl.size(), GState::PendF());
     }
-    for (auto& h : holders[J]) {
-      const int I = h.first;
-      const Panel& P = p.panels[I];
-      for (int c = st0[I]; c < st0[I + 1]; ++c) {
-        const int r0 = stl[c].first, sz = stl[c].second;
-        Task u{};
-        u.kind = TK_BUPD;
-        u.panel = I;
-        u.m = sz;
-        u.k = PJ.n;
-        u.lda = P.H;
-        u.aux = c;
-        u.a_off = P.off + h.second + (int64_t)r0 * P.H;
-        u.b_off = PJ.prow0;              // rows of x_J in W
-        u.c_off = P.prow0 + r0;          // rows of t_c in Z
-        std::vector<int32_t> pr2(btile[J]);
-        pr2.push_back(lastz[c]);
-        std::vector<Access> ac2{{kZKey | c, true}};
-        for (int cc = st0[J]; cc < st0[J + 1]; ++cc) ac2.push_back({wkey(0, cc), false});
-        int uid = sg.add(u, pr2, w_solve(sz, PJ.n));
-        lastz[c] = uid;
-        sacc.push_back(ac2);
+    auto forward = [&](int g) {
+      GState& S = gs[g];
+      const int64_t gk = (int64_t)g << 50;
+      auto wkey = [&](int slot, int r) { return kWKey | gk | ((int64_t)slot << 40) | r; };
+      // forward updates into tile r go round-robin to b and its extra
+      // accumulators (count of updates so far, last task per extra slot)
+      auto emit_fupd = [&](int r) {
+        GState::PendF& pf = S.pendf[r];
+        if (pf.src.empty()) return;
+        const int slot = S.nupd[r]++ % (kSolveSlots + 1);
+        Task u = pf.t;
+        u.c_off += (int64_t)slot * p.N;                    // rows of b_r (or a copy) in W
+        u.n = (slot > 0 && S.lastx[r][slot] < 0) ? 1 : 0;  // first into a copy: overwrite
+        if (pf.src.size() > 1) {
+          u.pad0 = (int32_t)pf.src.size();
+          u.pad1 = (int32_t)p.xsrc.size();
+          u.k = 0;
+          for (auto& x : pf.src) {
+            p.xsrc.push_back(x);
+            u.k += x.k;
+          }
+        }
+        std::vector<int32_t> pr = pf.pr;
+        pr.push_back(slot == 0 ? S.lastb[r] : S.lastx[r][slot]);
+        std::vector<Access> ac = pf.ac;
+        ac[0] = {wkey(slot, r), true};
+        int uid = sg.add(u, pr, pf.w);
+        if (slot == 0) S.lastb[r] = uid;
+        else S.lastx[r][slot] = uid;
+        sacc.push_back(ac);
+        pf = GState::PendF();
+      };
+      for (int I = 0; I < nb; ++I) {
+        const Panel& P = p.panels[I];
+        for (int c = st0[I]; c < st0[I + 1]; ++c) emit_fupd(c);
+        // sum the extra accumulators of I's tiles into b_I
+        for (int c = st0[I]; c < st0[I + 1]; ++c) {
+          const int used = std::min(S.nupd[c], kSolveSlots + 1) - 1;
+          if (used <= 0) continue;
+          Task t{};
+          t.kind = TK_RED | (g << 8);
+          t.panel = I;
+          t.m = stl[c].second;
+          t.k = used;
+          t.aux = c;
+          t.c_off = P.prow0 + stl[c].first;
+          std::vector<int32_t> pr{S.lastb[c]};
+          std::vector<Access> ac{{wkey(0, c), true}};
+          for (int q = 1; q <= used; ++q) {
+            pr.push_back(S.lastx[c][q]);
+            ac.push_back({wkey(q, c), false});
+          }
+          S.lastb[c] = sg.add(t, pr, 10.0);
+          sacc.push_back(ac);
+        }
+        if (I >= nfac) continue;  // not eliminated: its rows now hold the reduced right-hand side
+        std::vector<int32_t> inpr;
+        for (int c = st0[I]; c < st0[I + 1]; ++c) inpr.push_back(S.lastb[c]);
+        for (int c = st0[I]; c < st0[I + 1]; ++c) {
+          const int r0 = stl[c].first, sz = stl[c].second;
+          Task t{};
+          t.kind = TK_FTILE | (g << 8);
+          t.panel = I;
+          t.m = sz;
+          t.k = r0 + sz;
+          t.lda = P.n;
+          t.aux = c;
+          t.a_off = P.ioff + r0;
+          t.b_off = P.prow0;
+          t.c_off = P.prow0 + r0;
+          t.dofs = P.prow0 + r0;
+          t.pad0 = stf[c].second - (r0 + sz);  // with pivoting the sum runs to the factor tile's end
+          std::vector<Access> ac{{kZKey | gk | c, true}};
+          for (int q = st0[I]; q < st0[I + 1]; ++q) ac.push_back({wkey(0, q), false});
+          int id = sg.add(t, inpr, wsolve(sz, r0 + sz));
+          S.ftile[I].push_back(id);
+          S.lastz[c] = id;
+          sacc.push_back(ac);
+        }
+        for (int b = 1; b < P.npb; ++b) {
+          const PBlock& B = p.pblocks[P.pb0 + b];
+          const Panel& PJ = p.panels[B.J];
+          for (int r = st0[B.J]; r < st0[B.J + 1]; ++r) {
+            const int r0 = stl[r].first, sz = stl[r].second;
+            GState::PendF& pf = S.pendf[r];
+            if (pf.src.empty()) {
+              Task u{};
+              u.kind = TK_FUPD | (g << 8);
+              u.panel = I;
+              u.m = sz;
+              u.k = P.n;
+              u.lda = P.H;
+              u.aux = r;
+              u.a_off = P.off + B.prow + r0;                  // rows of (L D)_rI in LD
+              u.b_off = P.prow0;                              // rows of z_I in Z
+              u.c_off = PJ.prow0 + r0;
+              pf.t = u;
+              pf.ac.push_back({0, true});  // the target, set when the slot is known
+            }
+            pf.pr.insert(pf.pr.end(), S.ftile[I].begin(), S.ftile[I].end());
+            for (int c = st0[I]; c < st0[I + 1]; ++c) pf.ac.push_back({kZKey | gk | c, false});
+            pf.src.push_back({P.off + B.prow + r0, P.prow0, P.n, P.H});
+            pf.w += tile_work(sz, wn, P.n) / 5.5e5 + (pf.src.size() > 1 ? 3.0 : 0.0);
+            if ((int)pf.src.size() >= kMergeSolve) emit_fupd(r);
+          }
+        }
+      }
+    };
+    auto backward = [&](int g) {
+      GState& S = gs[g];
+      const int64_t gk = (int64_t)g << 50;
+      auto wkey = [&](int slot, int r) { return kWKey | gk | ((int64_t)slot << 40) | r; };
+      for (int J = nb - 1; J >= 0; --J) {
+        const Panel& PJ = p.panels[J];
+        std::vector<int32_t> zpr;
+        for (int c = st0[J]; c < st0[J + 1]; ++c) zpr.push_back(S.lastz[c]);
+        for (int c = st0[J]; c < st0[J + 1] && J < nfac; ++c) {
+          const int r0 = stl[c].first, sz = stl[c].second;
+          Task t{};
+          t.kind = TK_BTILE | (g << 8);
+          t.panel = J;
+          t.m = sz;
+          t.k = PJ.n - r0;
+          t.lda = PJ.n;
+          t.aux = c;
+          t.a_off = PJ.ioff + r0 + (int64_t)r0 * PJ.n;
+          t.b_off = PJ.prow0 + r0;
+          t.c_off = PJ.prow0 + r0;
+          t.pad0 = r0 - stf[c].first;  // with pivoting the sum starts at the factor tile's first row
+          std::vector<Access> ac{{wkey(0, c), true}};
+          for (int q = st0[J]; q < st0[J + 1]; ++q) ac.push_back({kZKey | gk | q, false});
+          int id = bg.add(t, zpr, wsolve(sz, PJ.n - r0));
+          S.btile[J].push_back(id);
+          S.lastb[c] = id;
+          bacc.push_back(ac);
+        }
+        for (auto& h : holders[J]) {
+          const int I = h.first;
+          if (I >= nfac) continue;
+          const Panel& P = p.panels[I];
+          for (int c = st0[I]; c < st0[I + 1]; ++c) {
+            const int r0 = stl[c].first, sz = stl[c].second;
+            Task u{};
+            u.kind = TK_BUPD | (g << 8);
+            u.panel = I;
+            u.m = sz;
+            u.k = PJ.n;
+            u.lda = P.H;
+            u.aux = c;
+            u.a_off = P.off + h.second + (int64_t)r0 * P.H;
+            u.b_off = PJ.prow0;              // rows of x_J in W
+            u.c_off = P.prow0 + r0;          // rows of t_c in Z
+            std::vector<int32_t> pr2(S.btile[J]);
+            pr2.push_back(S.lastz[c]);
+            std::vector<Access> ac2{{kZKey | gk | c, true}};
+            for (int cc = st0[J]; cc < st0[J + 1]; ++cc) ac2.push_back({wkey(0, cc), false});
+            int uid = bg.add(u, pr2, wsolve(sz, PJ.n));
+            S.lastz[c] = uid;
+            bacc.push_back(ac2);
+          }
+        }
+      }
+    };
+    for (int g = 0; g < G; ++g) forward(g);
+    if (split) {
+      // everything of the forward part is done before the backward launch,
+      // and x of the blocks left is given
+      finalize(sg, p.nworkers, sched, fwd_out);
+      if (sg.t.size() <= 40000) fwd_acc = std::move(sacc);
+      for (auto& q : gs) {
+        std::fill(q.lastz.begin(), q.lastz.end(), -1);
+        std::fill(q.lastb.begin(), q.lastb.end(), -1);
+      }
+    }
+    for (int g = 0; g < G; ++g) backward(g);
+    if (split) {
+      finalize(sgb, p.nworkers, sched, *bwd_out);
+      if (sgb.t.size() <= 40000) *bwd_acc = std::move(saccb);
+    } else {
+      finalize(sg, p.nworkers, sched, fwd_out);
+      if (sg.t.size() <= 40000) fwd_acc = std::move(sacc);
+    }
+  };
+  const bool partial = nfac < nb;
+  if (partial) {
+    gen_solve(1, p.sdag, p.sacc, &p.sdag2, &p.sacc2);
+  } else {
+    gen_solve(1, p.sdag, p.sacc, nullptr, nullptr);
+    if (p.rhs_groups > 1) gen_solve(p.rhs_groups, p.sdagg, p.saccg, nullptr, nullptr);
+  }
+  // ---- partial elimination: rows of the eliminated blocks, the reduced
+  // matrix's K offsets and where its blocks are in panel storage
+  if (partial) {
+    p.N_elim = 0;
+    for (int I = 0; I < nfac; ++I) p.N_elim += p.panels[I].n;
+    const int nr = p.nred;
+    p.koff_red.assign(nr + p.npair_red + 1, 0);
+    for (int i = 0; i < nr; ++i) p.koff_red[i + 1] = p.koff_red[i] + (int64_t)p.n[i] * p.n[i];
+    for (int k = 0; k < p.npair_red; ++k)
+      p.koff_red[nr + k + 1] = p.koff_red[nr + k] + (int64_t)p.n[p.pairs[k][0]] * p.n[p.pairs[k][1]];
+    p.kgather.clear();
+    for (int i = 0; i < nr; ++i) {
+      const Panel& P = p.panels[p.pos[i]];
+      p.kgather.push_back({P.off, p.koff_red[i], P.n, P.n, P.H, 0});
+    }
+    for (int k = 0; k < p.npair_red; ++k) {
+      const int a = p.pairs[k][0], b = p.pairs[k][1];  // K_ab, n_a x n_b
+      const int pa = p.pos[a], pb = p.pos[b];
+      if (pa > pb) {
+        const Panel& P = p.panels[pb];
+        p.kgather.push_back({P.off + prow_in[pb][pa], p.koff_red[nr + k], p.n[a], p.n[b], P.H, 0});
+      } else {
+        const Panel& P = p.panels[pa];
+        p.kgather.push_back({P.off + prow_in[pa][pb], p.koff_red[nr + k], p.n[b], p.n[a], P.H, 1});
       }
     }
   }
-  finalize(sg, p.nworkers, sched, p.sdag);
-  if (sg.t.size() <= 40000) p.sacc = std::move(sacc);
   *err = 0;
   return "";
 }

@@ -62,12 +62,30 @@ struct PlanImpl {
   std::vector<std::vector<Access>> facc, sacc;  // per generation index (small plans only)
   int nworkers = 256;
   int sched = 0;
+  // partial elimination (primal reduction): only the first nelim blocks of
+  // the order are eliminated; the others (user ids 0..nred-1) keep their
+  // Schur complement, the reduced matrix, whose K layout holds those
+  // blocks and the first npair_red pairs.  sdag is then the forward part of
+  // the solve over the eliminated blocks (it leaves the reduced right-hand
+  // side in the rows of the others) and sdag2 the backward part (from the
+  // others' given solution).
+  int nelim = 0, nred = 0, npair_red = 0;
+  int64_t N_elim = 0;                         // internal rows of the eliminated blocks
+  std::vector<int64_t> koff_red;              // K offsets of the reduced matrix
+  std::vector<KPlace> kgather;                // panel storage -> reduced K (src = panel, dst = K)
+  TaskDag sdag2;
+  std::vector<std::vector<Access>> sacc2;
+  // tuning knobs: solve tile rows, sources per merged update, and the
+  // right-hand-side groups of the grouped solve DAG sdagg (rhs_groups > 1)
+  int solve_tile = 64, merge = 8, rhs_groups = 1;
+  TaskDag sdagg;
+  std::vector<std::vector<Access>> saccg;
 };
 
 // Builds everything; returns an empty string or an error message.
 std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair, const int32_t* pairs,
-                       const int32_t* order, const int32_t* grid, int tile, int nworkers, int sched,
-                       int* errcode);
+                       const int32_t* order, const int32_t* grid, int tile, int nworkers, int sched, int nelim,
+                       int solve_tile, int merge, int rhs_groups, int* errcode);
 
 // Union of several instances' DAGs (instance i's tasks get inst = i),
 // re-scheduled together on P workers.

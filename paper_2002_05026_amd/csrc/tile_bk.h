@@ -63,7 +63,9 @@ template <typename T> __device__ __forceinline__ T bk_wave_max(T v) {
 }
 
 // T: arithmetic precision; TS: storage precision.  row0: internal row of
-// the tile's first unknown (for the status of a zero pivot column).
+// the tile's first unknown.  A zero (or not finite) pivot records its
+// position, row0 + k, in status[0] (the smallest position wins, i.e. the
+// first in elimination order); ipiv maps it to the unknown.
 template <typename T, typename TS>
 __device__ __noinline__ void tile_bk(typename Cplx<TS>::type* a_, int64_t lda, int m, typename Cplx<TS>::type* dout_,
                         typename Cplx<TS>::type* doff_, int32_t* ipiv, typename Cplx<TS>::type* linv_,
@@ -189,7 +191,7 @@ __device__ __noinline__ void tile_bk(typename Cplx<TS>::type* a_, int64_t lda, i
       if (!ok) skip = 1;
       if (skip) {
         if (tid == 0) {
-          atomicMin(&status[0], row0 + perm[k]);
+          atomicMin(&status[0], row0 + k);  // the position; the host maps it through ipiv
           atomicAdd(&status[1], 1);
         }
       } else {
@@ -220,7 +222,7 @@ __device__ __noinline__ void tile_bk(typename Cplx<TS>::type* a_, int64_t lda, i
       const bool ok = (det.x != (T)0 || det.y != (T)0) && isfinite(det.x) && isfinite(det.y);
       if (!ok) {
         if (tid == 0) {
-          atomicMin(&status[0], row0 + perm[k]);
+          atomicMin(&status[0], row0 + k);  // the position; the host maps it through ipiv
           atomicAdd(&status[1], 1);
         }
       } else {

@@ -7,6 +7,12 @@
          n~U{100..500}, f in [0.5, 2]), 16 RHS each, complex64 + FP64
          refinement, one persistent launch per phase, captured in a hipGraph
          and replayed; tiles from the tuner.
+* pivot: the precision workload (4x4x4) factored with Bunch-Kaufman pivoting
+         inside each diagonal tile, both precisions, against the unpivoted
+         factor on the same K.
+* primal: primal reduction (interior blocks of a 4x4x4 domain grid
+         eliminated onto the interfaces), the reduced system's mixed
+         solve, and the primal recovery with 8 port projections.
 * diff:  6x6x6 grid, 540 interfaces, n~U{300..700} (about 270k unknowns),
          128 RHS, complex64 + FP64 refinement, then the adjoint (lambda and
          dK on K's pattern) with the same factors.  Its gradient is checked
@@ -40,10 +46,14 @@ def fp64(args):
     res = {"metric": "block-LDLT TFLOP/s + time-to-solve, FP64 plain method", "unit": "TFLOP/s",
            "data": "synthetic", "dtype": "c128", "n_gpus": 1,
            "config": {"workload": "fp64: 8x8x1 domain grid, 112 interfaces, n~U{200..400}, complex128"}}
+    from paper_2002_05026_amd import tune
     runs = {}
     for nrhs in (1, 16):
         inst = gen.config_fp64(nrhs=nrhs)
-        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid)
+        tuned = {"config": dict(tune.DEFAULT)} if getattr(args, "no_tune", False) else \
+            tune.tune(inst, d3m.C128, nrhs=nrhs, reps=2, save=False)
+        _log(f"fp64 nrhs={nrhs} tuned {tuned}")
+        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, **tuned["config"])
         flops = plan.info["flops_factor"]
         K = torch.from_numpy(inst.K).cuda()
         B = torch.from_numpy(inst.B).cuda()
@@ -69,7 +79,7 @@ def fp64(args):
         runs[nrhs] = {"N": inst.N, "time_to_solve_ms": ms, "factor_dag_ms": dag, "factor_tflops": flops / dag / 1e9,
                       "frac_fp64_peak": flops / dag / 1e9 / PEAK_FP64_MFMA, "solve_dag_ms": sdag,
                       "solve_GBps_factor_bytes": solve_bytes / sdag / 1e6, "eta": st["eta"],
-                      "factor_gflop": flops / 1e9}
+                      "factor_gflop": flops / 1e9, "tuned": tuned["config"]}
         _log(f"fp64 nrhs={nrhs}: {runs[nrhs]}")
     res["runs"] = runs
     res["value"] = runs[1]["factor_tflops"]
@@ -86,12 +96,12 @@ def batch(args):
     _log(f"batch: {len(insts)} instances, N = {[i.N for i in insts][:8]}...")
     # tile edge from the tuner (timed on one instance of the largest grid)
     probe = max(insts, key=lambda i: i.N)
-    tuned = tune.tune(probe, d3m.C64_IR, reps=2)
-    tile = tuned["tile"]
+    tuned = tune.tune(probe, d3m.C64_IR, nrhs=16, reps=2)
+    cfg = tuned["config"]
     _log(f"tuned tile {tuned}")
     fs, Ks, Bs, Xs, flops = [], [], [], [], 0.0
     for inst in insts:
-        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=tile)
+        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, **cfg)
         flops += plan.info["flops_factor"]
         fs.append(d3m.Factor(plan, d3m.C64_IR, nrhs_max=16))
         Ks.append(torch.from_numpy(inst.K).cuda())
@@ -134,7 +144,7 @@ def batch(args):
     return {"metric": "batched frequency sweep: aggregate factor TFLOP/s and time for all instances",
             "value": flops / ms / 1e9, "unit": "TFLOP/s", "ms_per_sweep": ms, "sequential_ms": seq,
             "n_instances": len(insts), "status_ok": ok, "max_eta": max(etas), "ir_iters": sorted(set(iters)),
-            "tile": tile, "tuner_ms": tuned["ms"], "factor_gflop_total": flops / 1e9, "dtype": "c64+c128",
+            "tuned": cfg, "tuner_ms": tuned["timings"], "factor_gflop_total": flops / 1e9, "dtype": "c64+c128",
             "data": "synthetic", "n_gpus": 1,
             "config": {"workload": "batch: 32-instance sweep, grids {2x2x2,3x3x2,4x4x2}, n~U{100..500}, "
                                    "f_k = 0.5 + 1.5k/31, 16 RHS each, hipGraph replay"}}
@@ -186,3 +196,98 @@ def diff(args):
             "factor_gflop": flops / 1e9, "dtype": "c64+c128", "data": "synthetic", "n_gpus": 1,
             "config": {"workload": "diff: 6x6x6 domain grid, 540 interfaces, n~U{300..700}, 128 RHS, "
                                    "complex64 factor + FP64 refinement + adjoint"}}
+
+
+def pivot(args):
+    """The precision workload's K factored with and without in-tile pivoting."""
+    import torch
+
+    import paper_2002_05026_amd as d3m
+    from paper_2002_05026_amd import instances as gen
+    inst = gen.config_precision(nrhs=64)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid)
+    flops = plan.info["flops_factor"]
+    K = torch.from_numpy(inst.K).cuda()
+    B = torch.from_numpy(inst.B).cuda()
+    X = torch.empty_like(B)
+    out = {}
+    for prec in (d3m.C64_IR, d3m.C128):
+        for piv in (False, True):
+            f = d3m.Factor(plan, prec, nrhs_max=64, timing=True, pivot=piv)
+            f.factorize(K)
+            f.solve(B, X)
+            torch.cuda.synchronize()
+            f.status()
+            e0, e1 = _events()
+            e0.record()
+            for _ in range(args.steps):
+                f.factorize(K)
+                f.solve(B, X)
+            e1.record()
+            torch.cuda.synchronize()
+            st = f.status()
+            key = ("c64+IR" if prec == d3m.C64_IR else "c128") + (" pivoted" if piv else "")
+            dag = st["t_factor_dag_ms"] / max(1, st["n_factor_dag"])
+            out[key] = {"time_to_solve_ms": e0.elapsed_time(e1) / args.steps, "factor_dag_ms": dag,
+                        "factor_tflops": flops / dag / 1e9, "eta": st["eta"], "ir_iters": st["ir_iters"],
+                        "status": st["status"]}
+            _log(f"pivot {key}: {out[key]}")
+            del f
+            torch.cuda.empty_cache()
+    return {"metric": "in-tile Bunch-Kaufman pivoting: factor and time-to-solve against the unpivoted factor",
+            "unit": "ms", "value": out["c64+IR pivoted"]["time_to_solve_ms"], "runs": out, "n_gpus": 1,
+            "dtype": "c64+c128", "data": "synthetic",
+            "config": {"workload": "pivot: the precision workload (4x4x4, N=%d, 64 RHS)" % inst.N}}
+
+
+def primal(args):
+    """Primal reduction -> reduced mixed solve -> primal recovery with ports."""
+    import torch
+
+    import paper_2002_05026_amd as d3m
+    from paper_2002_05026_amd import instances as gen
+    inst = gen.config_primal(nrhs=16)
+    red = d3m.Plan(inst.sizes[:inst.nb], inst.pairs[:inst.npair_red], grid=inst.grid)
+    order = [inst.nb + d for d in range(inst.ndom)] + red.order().tolist()
+    plan = d3m.Plan(inst.sizes, inst.pairs, order=order, nelim=inst.ndom)
+    _log(f"primal: N={inst.N} ({inst.ndom} interiors, reduced N={red.N}), "
+         f"{plan.info['flops_factor'] / 1e9:.0f} GFLOP reduction, {red.info['flops_factor'] / 1e9:.0f} GFLOP dual")
+    A = torch.from_numpy(inst.K).cuda()
+    F = torch.from_numpy(inst.F).cuda()
+    M = torch.from_numpy(inst.M).cuda()
+    fp = d3m.Factor(plan, d3m.C128, nrhs_max=16, timing=True)
+    fd = d3m.Factor(red, d3m.C64_IR, nrhs_max=16, timing=True)
+
+    def step():
+        Kred, G = fp.reduce(A, F)
+        fd.factorize(Kred)
+        Xred = fd.solve(G)
+        return fp.recover(Xred, M)
+
+    step()
+    torch.cuda.synchronize()
+    fp.status()
+    fd.status()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    tr = td = tc = 0.0
+    for _ in range(args.steps):
+        ev[0].record()
+        Kred, G = fp.reduce(A, F)
+        ev[1].record()
+        fd.factorize(Kred)
+        Xred = fd.solve(G)
+        ev[2].record()
+        U, S = fp.recover(Xred, M)
+        ev[3].record()
+        torch.cuda.synchronize()
+        tr += ev[0].elapsed_time(ev[1])
+        td += ev[1].elapsed_time(ev[2])
+        tc += ev[2].elapsed_time(ev[3])
+    sp, sd = fp.status(), fd.status()
+    n = args.steps
+    return {"metric": "primal reduction + dual solve + primal recovery time", "unit": "ms",
+            "value": (tr + td + tc) / n, "reduce_ms": tr / n, "dual_ms": td / n, "recover_ms": tc / n,
+            "reduce_tflops": plan.info["flops_factor"] / (tr / n) / 1e9,
+            "dual_eta": sd["eta"], "status": [sp["status"], sd["status"]], "N": inst.N, "N_reduced": red.N,
+            "n_gpus": 1, "dtype": "c128 reduction + c64/c128 dual", "data": "synthetic",
+            "config": {"workload": "primal: 4x4x4 domains, interfaces and interiors n~U{300..600}, 16 RHS, 8 ports"}}

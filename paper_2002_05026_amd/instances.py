@@ -258,3 +258,139 @@ def config_batch(count: int = 32, nrhs: int = 16, size_range=(100, 500), indices
 def config_diff(nrhs: int = 128, grid=(6, 6, 6), size_range=(300, 700)) -> Instance:
     """6x6x6 grid, 540 interfaces, n ~ U{300..700} (about 270k unknowns)."""
     return make_instance(grid, size_range, COEF_PLAIN, nrhs, 4, with_c=True)
+
+
+# ---------------------------------------------------------------- primal (domain) matrices
+def grid_domains(grid: Sequence[int]) -> np.ndarray:
+    """Domains of the grid, lexicographic (x slowest)."""
+    a, b, c = (int(g) for g in grid)
+    return np.asarray([(x, y, z) for x in range(a) for y in range(b) for z in range(c)], dtype=np.int32)
+
+
+def domain_interfaces(grid: Sequence[int], ifaces: Optional[np.ndarray] = None) -> list:
+    """For each domain, the interfaces on its faces (increasing ids)."""
+    if ifaces is None:
+        ifaces = grid_interfaces(grid)
+    doms = grid_domains(grid)
+    index = {tuple(d): k for k, d in enumerate(doms.tolist())}
+    out = [[] for _ in range(len(doms))]
+    for i, (ax, x, y, z) in enumerate(np.asarray(ifaces).tolist()):
+        d0 = [x, y, z]
+        d1 = [x, y, z]
+        d1[ax] += 1
+        out[index[tuple(d0)]].append(i)
+        out[index[tuple(d1)]].append(i)
+    return [sorted(v) for v in out]
+
+
+@dataclasses.dataclass
+class PrimalInstance:
+    """A synthetic primal (FEM-like) matrix in block form: blocks 0..nb-1
+    are the interfaces, block nb + d the interior unknowns of domain d.  K
+    uses the library's K layout over all blocks (pairs: the interface pairs
+    first, as grid_pairs gives them, then (nb + d, I) for each domain d and
+    interface I on its faces).  F: right-hand sides; M: port modes (one
+    column per port, unit-norm, on the interior unknowns of one domain)."""
+    grid: tuple
+    nb: int                 # interfaces (the reduced blocks)
+    ndom: int
+    sizes: np.ndarray       # (nb + ndom,) int32
+    pairs: np.ndarray       # (npair, 2) int32, first npair_red between interfaces
+    npair_red: int
+    offsets: np.ndarray
+    K: np.ndarray
+    F: np.ndarray           # (nrhs, N)
+    M: np.ndarray           # (nports, N)
+    port_domain: list
+    dom_ifaces: list
+
+    @property
+    def N(self) -> int:
+        return int(self.sizes.astype(np.int64).sum())
+
+    @property
+    def row_offsets(self) -> np.ndarray:
+        o = np.zeros(self.sizes.shape[0] + 1, dtype=np.int64)
+        o[1:] = np.cumsum(self.sizes.astype(np.int64))
+        return o
+
+
+def make_primal_instance(grid: Sequence[int], iface_range, interior_range, coef: complex, nrhs: int, seed,
+                         nports: int = 4) -> PrimalInstance:
+    """Synthetic primal matrix.  Interface diagonal blocks and the couplings
+    between interfaces of one domain follow the reduced-matrix recipe (they
+    stand for the assembled interface parts of the two domain matrices);
+    each domain's interior block is symmetric complex normal plus the
+    diagonal shift s_k coef sqrt(n_d) (the regularized domain matrix), and
+    its coupling to each face interface is complex normal / sqrt(max(n_d,
+    n_I)).  Draw order: interface sizes, interior sizes, interface blocks,
+    interface pairs, interior blocks, interior-interface blocks, F, M."""
+    grid = tuple(int(g) for g in grid)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ifaces = grid_interfaces(grid)
+    nb = ifaces.shape[0]
+    doms = grid_domains(grid)
+    ndom = doms.shape[0]
+    def draw_sizes(rng_, r, count):
+        if isinstance(r, (int, np.integer)):
+            return np.full(count, int(r), dtype=np.int32)
+        return rng_.integers(int(r[0]), int(r[1]) + 1, size=count).astype(np.int32)
+    s_if = draw_sizes(rng, iface_range, nb)
+    s_in = draw_sizes(rng, interior_range, ndom)
+    sizes = np.concatenate([s_if, s_in]).astype(np.int32)
+    dif = domain_interfaces(grid, ifaces)
+    red_pairs = grid_pairs(grid, ifaces)
+    dom_pairs = [(nb + d, I) for d in range(ndom) for I in dif[d]]
+    pairs = np.concatenate([red_pairs, np.asarray(dom_pairs, dtype=np.int32).reshape(-1, 2)]).astype(np.int32)
+    off = k_offsets(sizes, pairs)
+    K = np.empty(int(off[-1]), dtype=np.complex128)
+
+    def sym_block(n):
+        iu, ju = np.triu_indices(n)
+        vals = _cn(rng, iu.shape[0])
+        blk = np.empty((n, n), dtype=np.complex128)
+        blk[iu, ju] = vals
+        blk[ju, iu] = vals
+        signs = rng.integers(0, 2, size=n) * 2 - 1
+        blk[np.arange(n), np.arange(n)] += signs * coef * math.sqrt(n)
+        return blk
+
+    for i in range(nb):
+        K[off[i]:off[i + 1]] = sym_block(int(sizes[i])).reshape(-1, order="F")
+    npr = red_pairs.shape[0]
+    for k in range(npr):
+        i, j = (int(v) for v in pairs[k])
+        ni, nj = int(sizes[i]), int(sizes[j])
+        K[off[nb + ndom + k]:off[nb + ndom + k + 1]] = (
+            _cn(rng, (ni, nj)) * (1.0 / math.sqrt(max(ni, nj)))).reshape(-1, order="F")
+    for d in range(ndom):
+        i = nb + d
+        K[off[i]:off[i + 1]] = sym_block(int(sizes[i])).reshape(-1, order="F")
+    for k in range(npr, pairs.shape[0]):
+        i, j = (int(v) for v in pairs[k])
+        ni, nj = int(sizes[i]), int(sizes[j])
+        K[off[nb + ndom + k]:off[nb + ndom + k + 1]] = (
+            _cn(rng, (ni, nj)) * (1.0 / math.sqrt(max(ni, nj)))).reshape(-1, order="F")
+    N = int(sizes.astype(np.int64).sum())
+    F = _cn(rng, (nrhs, N))
+    row0 = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
+    # ports on the interiors of domains on the grid's x = 0 face, in turn
+    face = [d for d in range(ndom) if doms[d][0] == 0]
+    M = np.zeros((nports, N), dtype=np.complex128)
+    pdom = []
+    for q in range(nports):
+        d = face[q % len(face)]
+        n = int(sizes[nb + d])
+        v = _cn(rng, n)
+        M[q, row0[nb + d]:row0[nb + d + 1]] = v / np.linalg.norm(v)
+        pdom.append(d)
+    return PrimalInstance(grid, nb, ndom, sizes, pairs, int(npr), off, K, F, M, pdom, dif)
+
+
+def config_primal(nrhs: int = 16, grid=(4, 4, 4), iface_range=(300, 600), interior_range=(300, 600),
+                  nports: int = 8) -> PrimalInstance:
+    """The primal reduction and recovery around the precision workload's
+    grid: 4x4x4 domains, interfaces of n ~ U{300..600} and interiors of
+    n ~ U{300..600} unknowns, coefficient 3 + 0.5j, 16 right-hand sides, 8
+    ports on the x = 0 face."""
+    return make_primal_instance(grid, iface_range, interior_range, COEF_PLAIN, nrhs, 5, nports)

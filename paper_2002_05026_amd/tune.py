@@ -1,22 +1,30 @@
-"""Tile-size tuner.
+"""Autotuner of the plan's tile knobs.
 
-The planner splits every interface into tiles of at most `tile` rows; the
-tile edge sets the grain of the factor DAG (bigger tiles: fewer tasks and
-more work per MFMA tile product; smaller tiles: shorter critical path on
-small fronts).  The paper weighs its dual tasks with benchmarked GEMM,
-sytrf and triSolve timings (Sec. II); here the whole factor is timed on the
-device for each candidate edge and the fastest is kept, per precision and
-size bucket, in a JSON cache keyed by the GPU architecture.
+The paper weighs its dual tasks with benchmarked GEMM, sytrf and triSolve
+timings (Sec. II) to schedule them; here the knobs that set the grain of the
+GPU task DAGs are chosen by timing the library itself on the device:
 
-Cache file: $D3M_TUNE_CACHE, else ~/.cache/d3m_tune.json.
+* tile        edge of the factor tiles (FACT/TRSM/update grain)      -> factor DAG time
+* merge       source panels per merged Schur update task            -> factor DAG time
+* solve_tile  rows of a solve task                                  -> solve DAG time
+* rhs_groups  column groups of the right-hand sides (grouped DAG)   -> solve DAG time
+
+Coordinate descent in that order: each knob's candidates are timed with the
+best values found so far for the others (factor knobs by the time of
+d3m_factorize, solve knobs by the time of d3m_solve for the caller's number
+of right-hand sides, HIP events on the stream), and the fastest is kept.  Results are cached as JSON keyed
+by GPU architecture, precision, interface-size bucket and right-hand-side
+bucket.  Cache file: $D3M_TUNE_CACHE, else ~/.cache/d3m_tune.json.
 """
 from __future__ import annotations
 
 import json
 import os
-from typing import Optional, Sequence
+from typing import Optional
 
-CANDIDATES = (64, 96, 128)
+KNOBS = (("tile", (64, 96, 128)), ("merge", (4, 8, 12)), ("solve_tile", (32, 64, 128)), ("rhs_groups", (1, 2, 4)))
+DEFAULT = {"tile": 128, "merge": 8, "solve_tile": 64, "rhs_groups": 1}
+FACTOR_KNOBS = ("tile", "merge")
 
 
 def _cache_path() -> str:
@@ -32,6 +40,14 @@ def size_bucket(mean_n: float) -> str:
     return "n<=256" if mean_n <= 256 else ("n<=512" if mean_n <= 512 else "n>512")
 
 
+def rhs_bucket(nrhs: int) -> str:
+    return "1" if nrhs <= 1 else ("<=16" if nrhs <= 16 else ("<=64" if nrhs <= 64 else ">64"))
+
+
+def key(precision: int, mean_n: float, nrhs: int) -> str:
+    return f"{_arch()}/{precision}/{size_bucket(mean_n)}/rhs{rhs_bucket(nrhs)}"
+
+
 def load() -> dict:
     try:
         with open(_cache_path()) as fh:
@@ -40,46 +56,68 @@ def load() -> dict:
         return {}
 
 
-def lookup(precision: int, mean_n: float, default: int = 128) -> int:
+def lookup(precision: int, mean_n: float, nrhs: int) -> dict:
+    """The cached configuration for this bucket, else the defaults."""
     try:
-        key = f"{_arch()}/{precision}/{size_bucket(mean_n)}"
+        k = key(precision, mean_n, nrhs)
     except Exception:
-        return default
-    return int(load().get(key, {}).get("tile", default))
+        return dict(DEFAULT)
+    return dict(load().get(k, {}).get("config", DEFAULT))
 
 
-def tune(instance, precision: int, candidates: Sequence[int] = CANDIDATES, reps: int = 3,
-         save: bool = True) -> dict:
-    """Time the factorization of `instance` for each tile edge; return and
-    cache {'tile': best, 'ms': {tile: ms}}."""
+def _time(instance, precision: int, nrhs: int, cfg: dict, reps: int) -> tuple:
+    """(factorize ms, solve ms) of one configuration, means over reps (HIP
+    events on the stream around the calls; what the knobs do not touch --
+    scatter, norms, residuals -- is the same for every candidate)."""
+    import numpy as np
     import torch
 
     import paper_2002_05026_amd as d3m
+    plan = d3m.Plan(instance.sizes, instance.pairs, grid=instance.grid, **cfg)
     K = torch.from_numpy(instance.K).cuda()
-    times = {}
-    for tile in candidates:
-        plan = d3m.Plan(instance.sizes, instance.pairs, grid=instance.grid, tile=tile)
-        f = d3m.Factor(plan, precision, nrhs_max=1)
+    B = torch.from_numpy(np.ascontiguousarray(instance.B[:nrhs])).cuda()
+    X = torch.empty_like(B)
+    f = d3m.Factor(plan, precision, nrhs_max=nrhs)
+    f.factorize(K)
+    f.solve(B, X)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tf = ts = 0.0
+    for _ in range(reps):
+        ev[0].record()
         f.factorize(K)
+        ev[1].record()
+        f.solve(B, X)
+        ev[2].record()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            f.factorize(K)
-        e1.record()
-        torch.cuda.synchronize()
-        times[int(tile)] = e0.elapsed_time(e1) / reps
-        st = f.status()
-        if st["status"] not in (0,):
-            raise RuntimeError(f"tuning factorization failed: {st}")
-        del f
-    best = min(times, key=times.get)
-    res = {"tile": best, "ms": times}
+        tf += ev[0].elapsed_time(ev[1])
+        ts += ev[1].elapsed_time(ev[2])
+    st = f.status()
+    if st["status"] != 0:
+        raise RuntimeError(f"tuning run failed: {st}")
+    return tf / reps, ts / reps
+
+
+def tune(instance, precision: int, nrhs: Optional[int] = None, reps: int = 2, save: bool = True,
+         knobs=KNOBS) -> dict:
+    """Coordinate descent over the knobs on `instance`; returns (and caches)
+    {'config': best, 'timings': {knob: {value: ms}}, 'key': cache key}."""
+    if nrhs is None:
+        nrhs = int(instance.B.shape[0])
+    cfg = dict(DEFAULT)
+    timings = {}
+    for name, cands in knobs:
+        times = {}
+        for v in cands:
+            trial = dict(cfg, **{name: v})
+            fac, sol = _time(instance, precision, nrhs, trial, reps)
+            times[int(v)] = fac if name in FACTOR_KNOBS else sol
+        cfg[name] = min(times, key=times.get)
+        timings[name] = times
+    mean_n = float(instance.sizes.mean())
+    res = {"config": cfg, "timings": timings, "key": key(precision, mean_n, nrhs)}
     if save:
-        mean_n = float(instance.sizes.mean())
-        key = f"{_arch()}/{precision}/{size_bucket(mean_n)}"
         data = load()
-        data[key] = res
+        data[res["key"]] = res
         path = _cache_path()
         os.makedirs(os.path.dirname(path), exist_ok=True)
         tmp = path + ".tmp"

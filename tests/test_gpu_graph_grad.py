@@ -178,11 +178,23 @@ def test_batch_instance_equals_single_run_bitwise():
         assert np.array_equal(Xs1.cpu().numpy(), X.cpu().numpy())
 
 
-def test_tuner_picks_a_candidate(tmp_path, monkeypatch):
+def test_tuner_times_every_candidate_and_applies_the_best(tmp_path, monkeypatch):
+    # coordinate descent over the four knobs, three timed candidates each;
+    # the cached choice is the fastest of each knob's timings
     d3m = _d3m()
     from paper_2002_05026_amd import tune
     monkeypatch.setenv("D3M_TUNE_CACHE", str(tmp_path / "tune.json"))
-    inst = gen.make_instance((2, 2, 2), (100, 300), gen.COEF_PLAIN, 1, 4)
-    res = tune.tune(inst, d3m.C64_IR, candidates=(64, 128), reps=2)
-    assert res["tile"] in (64, 128) and all(v > 0 for v in res["ms"].values())
-    assert tune.lookup(d3m.C64_IR, float(inst.sizes.mean())) == res["tile"]
+    inst = gen.make_instance((2, 2, 2), (100, 300), gen.COEF_PLAIN, 32, 4)
+    res = tune.tune(inst, d3m.C64_IR, nrhs=32, reps=1)
+    print(f"[case] tuner {res}", flush=True)
+    for name, cands in tune.KNOBS:
+        t = res["timings"][name]
+        assert sorted(t) == sorted(cands) and all(v > 0 for v in t.values())
+        assert res["config"][name] == min(t, key=t.get)
+    assert tune.lookup(d3m.C64_IR, float(inst.sizes.mean()), 32) == res["config"]
+    # the tuned plan solves
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, **res["config"])
+    f = d3m.Factor(plan, d3m.C64_IR, nrhs_max=32)
+    f.factorize(torch.from_numpy(inst.K).cuda())
+    f.solve(torch.from_numpy(inst.B).cuda())
+    assert f.status()["status"] == 0

@@ -266,3 +266,88 @@ def test_forced_fp64_fallback_of_diagonal_tiles():
     sq = q.status()
     assert sq["status"] == 0 and 0 < sq["fallbacks"] <= plan.info["ntiles"], sq
     assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, Xq, inst.B).max() <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rhs_groups_are_bitwise_the_ungrouped_solve(precision):
+    # a grouped solve DAG computes every column with the same products in the
+    # same order as the ungrouped one: bitwise equal results
+    d3m = _d3m()
+    inst = gen.make_instance((3, 2, 2), (40, 200), gen.COEF_PRECISION, 64, 707)
+    K = torch.from_numpy(inst.K).cuda()
+    xs = []
+    for groups, nrhs in ((1, 64), (2, 64), (4, 64), (2, 37)):
+        print(f"[case] rhs groups {groups} nrhs {nrhs} prec {precision}", flush=True)
+        plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, rhs_groups=groups)
+        f = d3m.Factor(plan, precision, nrhs_max=64)
+        f.factorize(K)
+        X = f.solve(torch.from_numpy(np.ascontiguousarray(inst.B[:nrhs])).cuda()).cpu().numpy()
+        assert f.status()["status"] == 0
+        xs.append(X)
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    assert np.array_equal(xs[0][:37], xs[3])
+    eta = oracle.backward_error(inst.sizes, inst.pairs, inst.K, xs[1], inst.B)
+    assert eta.max() <= (1e-12 if precision == 0 else 1e-10)
+
+
+@pytest.mark.parametrize("solve_tile,merge", [(32, 1), (128, 4), (64, 16)])
+def test_tuning_knobs_against_oracle(solve_tile, merge):
+    d3m = _d3m()
+    inst = gen.make_instance((3, 3, 2), (60, 200), gen.COEF_PLAIN, 4, 808)
+    print(f"[case] knobs solve_tile {solve_tile} merge {merge}", flush=True)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, solve_tile=solve_tile, merge=merge, rhs_groups=2)
+    f = d3m.Factor(plan, 0, nrhs_max=4)
+    f.factorize(torch.from_numpy(inst.K).cuda())
+    X = f.solve(torch.from_numpy(inst.B).cuda()).cpu().numpy()
+    assert f.status()["status"] == 0
+    p, Xo = _oracle_solution(inst, oracle.nd_order(inst.grid), inst.B)
+    assert _fwd_err(X, Xo) <= 1e-10
+
+
+def test_fp64_fallback_refactors_the_stored_tile_in_fp64():
+    # The first eliminated interface's diagonal block is L0 D0 L0^T (L0 = I +
+    # 0.3 x strictly lower complex normal) with one pivot 1e-7 times the
+    # others.  Eliminated in FP32, that pivot comes out of cancellation with
+    # an error of the order of u32 times the block's scale.  The growth check
+    # trips (min|d| < 1e-4 max|A|) and the tile is factored again in FP64 from
+    # the same stored (complex64) entries: its D must then be the FP64
+    # elimination of the complex64-rounded block -- the oracle's factor of K
+    # rounded to complex64 -- to complex64 precision, while the FP32
+    # elimination is far from it.  (The rounding of the input itself moves
+    # the small pivot by O(1) relative to D0; no re-factor recovers that, and
+    # the block row below the pivot still grows by ~1e7, so refinement needs
+    # many steps; the solve must reach the tolerance.)
+    d3m = _d3m()
+    inst = gen.make_instance((2, 2, 1), 40, gen.COEF_PLAIN, 2, 1212)
+    order = oracle.nd_order(inst.grid)
+    I = int(order[0])
+    n = int(inst.sizes[I])
+    rng = np.random.default_rng(3)
+    L0 = np.eye(n) + 0.3 * np.tril((rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2), -1)
+    d0 = (3.0 + 0.5j) * np.sqrt(n) * rng.choice([-1.0, 1.0], n)
+    d0[n // 2] *= 1e-7
+    A = (L0 * d0) @ L0.T
+    inst.K[inst.offsets[I]:inst.offsets[I + 1]] = A.reshape(-1, order="F")
+    ref = oracle.OraclePlan(inst.sizes, inst.pairs, order)
+    assert ref.factor(inst.K.astype(np.complex64).astype(np.complex128)) < 0
+    dref = np.diag(ref.block(I, I))
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=64)
+    assert int(plan.order()[0]) == I
+    K = torch.from_numpy(inst.K).cuda()
+    B = torch.from_numpy(inst.B).cuda()
+    st, err = {}, {}
+    for fb in (True, False):
+        print(f"[case] cancelled pivot fallback={fb}", flush=True)
+        f = d3m.Factor(plan, d3m.C64_IR, nrhs_max=2, fallback=fb, max_iter=30)
+        f.factorize(K)
+        X = f.solve(B).cpu().numpy()
+        st[fb] = f.status()
+        d = np.diag(f.block(I, I))
+        err[fb] = (np.abs(d - dref) / np.abs(dref)).max()
+        print(f"[case] fallback={fb} max relative D error {err[fb]:.3e} status {st[fb]}", flush=True)
+        if fb:
+            assert st[fb]["fallbacks"] >= 1 and st[fb]["status"] == 0, st[fb]
+            assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, inst.B).max() <= 1e-10
+    assert st[False]["fallbacks"] == 0
+    assert err[True] <= 1e-4, err       # FP64 elimination, stored in complex64
+    assert err[False] >= 1e-2, err      # FP32 elimination: the cancellation shows

@@ -96,10 +96,18 @@ def test_pivoting_solves_where_the_plain_factor_fails():
     f0.solve(torch.from_numpy(inst.B).cuda())
     assert f0.status()["status"] == 1  # D3M_ZERO_PIVOT without pivoting
     for prec in (d3m.C128, d3m.C64_IR):
-        plan, f, X, st = _run(d3m, inst, prec, 32, tol=1e-10, max_iter=20)
+        # one tile per interface: the whole diagonal block is the pivot search
+        plan, f, X, st = _run(d3m, inst, prec, 64, tol=1e-10, max_iter=20)
         assert st["status"] == 0, st
         bound = 1e-12 if prec == d3m.C128 else 1e-10
         assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, inst.B).max() <= bound
+    # pivoting is restricted to tiles: with tiles of 32 the first tile of each
+    # interface, [0 H1; H1^T 0] with H1 of 20 x 12, has rank 24 < 32, and the
+    # device reports the zero pivot where the oracle with the same tiles does
+    plan, f, X, st = _run(d3m, inst, d3m.C128, 32)
+    p = oracle.OraclePlan(inst.sizes, inst.pairs, oracle.nd_order(inst.grid))
+    r = p.factor_bk(inst.K, tile=32)
+    assert r >= 0 and st["status"] == 1 and st["pivot_row"] == r, (r, st)
 
 
 def test_pivoting_on_a_dominant_input_keeps_the_diagonal():

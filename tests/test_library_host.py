@@ -111,3 +111,58 @@ def test_batch_merge_keeps_every_task():
     insts = gen.config_batch(count=3, nrhs=1, size_range=(20, 40))
     plans = [d3m.Plan(i.sizes, i.pairs, grid=i.grid, tile=32) for i in insts]
     assert all(pl.info["ntask_factor"] > 0 for pl in plans)
+
+
+def _primal_plan(inst, tile=32, **kw):
+    """A partial-elimination plan of a primal instance: the domains' interior
+    blocks first, then the interfaces in the library's nested-dissection
+    order of the reduced matrix."""
+    red = d3m.Plan(inst.sizes[:inst.nb], inst.pairs[:inst.npair_red], grid=inst.grid)
+    order = [inst.nb + d for d in range(inst.ndom)] + red.order().tolist()
+    return d3m.Plan(inst.sizes, inst.pairs, order=order, tile=tile, nelim=inst.ndom, **kw), red
+
+
+@pytest.mark.parametrize("grid", [(2, 2, 1), (2, 2, 2), (3, 2, 2)])
+def test_partial_elimination_plans(grid):
+    inst = gen.make_primal_instance(grid, (20, 70), (30, 90), gen.COEF_PLAIN, 1, 7)
+    plan, red = _primal_plan(inst)
+    # the factor, forward and backward solve DAGs are race-free
+    assert plan.check() == 0
+    # factor work: only the interior blocks are eliminated
+    n_in = inst.sizes[inst.nb:].astype(float)
+    assert plan.info["flops_diag"] == pytest.approx((4.0 / 3.0 * n_in ** 3).sum(), rel=1e-12)
+    fl_trsm = sum(4.0 * inst.sizes[I] * n_in[d] ** 2 for d in range(inst.ndom) for I in inst.dom_ifaces[d])
+    assert plan.info["flops_trsm"] == pytest.approx(fl_trsm, rel=1e-12)
+
+
+def test_partial_elimination_argument_errors():
+    inst = gen.make_primal_instance((2, 2, 1), 8, 9, gen.COEF_PLAIN, 1, 8)
+    red = d3m.Plan(inst.sizes[:inst.nb], inst.pairs[:inst.npair_red], grid=inst.grid)
+    order = [inst.nb + d for d in range(inst.ndom)] + red.order().tolist()
+    # the blocks left must be user ids 0..nred-1
+    bad = list(reversed(order))
+    with pytest.raises(d3m.D3MError) as e:
+        d3m.Plan(inst.sizes, inst.pairs, order=bad, nelim=inst.ndom)
+    assert e.value.code == -2
+    # the pairs between the blocks left must come first
+    pairs = np.concatenate([inst.pairs[inst.npair_red:], inst.pairs[:inst.npair_red]])
+    with pytest.raises(d3m.D3MError):
+        d3m.Plan(inst.sizes, pairs, order=order, nelim=inst.ndom)
+    # a missing interface pair would be filled by the elimination
+    pairs = np.concatenate([inst.pairs[1:inst.npair_red], inst.pairs[inst.npair_red:]])
+    with pytest.raises(d3m.D3MError):
+        d3m.Plan(inst.sizes, pairs, order=order, nelim=inst.ndom)
+    with pytest.raises(d3m.D3MError):
+        d3m.Plan(inst.sizes, inst.pairs, order=order, nelim=inst.nb + inst.ndom)
+
+
+@pytest.mark.parametrize("solve_tile,merge,groups", [(32, 1, 2), (128, 4, 4), (64, 16, 2), (16, 8, 8)])
+def test_tuning_knobs_keep_the_dags_race_free(solve_tile, merge, groups):
+    inst = gen.make_instance((3, 2, 2), (20, 90), gen.COEF_PLAIN, 1, 55)
+    plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=32, solve_tile=solve_tile, merge=merge,
+                    rhs_groups=groups)
+    assert plan.check() == 0
+    with pytest.raises(d3m.D3MError):
+        d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, solve_tile=24)
+    with pytest.raises(d3m.D3MError):
+        d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, merge=17)
