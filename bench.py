@@ -126,6 +126,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true", help="default plan knobs instead of the autotuner's")
+    ap.add_argument("--fp64-nrhs", default="1,16", help="right-hand-side counts of the fp64 workload")
     ap.add_argument("--knobs", default=None,
                     help='fixed plan knobs instead of the autotuner, JSON for both precisions or '
                          '{"c64": {...}, "c128": {...}} (e.g. to profile a tuned configuration)')

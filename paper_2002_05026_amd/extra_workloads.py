@@ -48,7 +48,7 @@ def fp64(args):
            "config": {"workload": "fp64: 8x8x1 domain grid, 112 interfaces, n~U{200..400}, complex128"}}
     from paper_2002_05026_amd import tune
     runs = {}
-    for nrhs in (1, 16):
+    for nrhs in (int(v) for v in str(getattr(args, "fp64_nrhs", "1,16")).split(",")):
         inst = gen.config_fp64(nrhs=nrhs)
         tuned = {"config": dict(tune.DEFAULT)} if getattr(args, "no_tune", False) else \
             tune.tune(inst, d3m.C128, nrhs=nrhs, reps=2, save=False)
@@ -82,7 +82,7 @@ def fp64(args):
                       "factor_gflop": flops / 1e9, "tuned": tuned["config"]}
         _log(f"fp64 nrhs={nrhs}: {runs[nrhs]}")
     res["runs"] = runs
-    res["value"] = runs[1]["factor_tflops"]
+    res["value"] = runs[min(runs)]["factor_tflops"]
     return res
 
 

@@ -304,50 +304,60 @@ def test_tuning_knobs_against_oracle(solve_tile, merge):
     assert _fwd_err(X, Xo) <= 1e-10
 
 
-def test_fp64_fallback_refactors_the_stored_tile_in_fp64():
-    # The first eliminated interface's diagonal block is L0 D0 L0^T (L0 = I +
-    # 0.3 x strictly lower complex normal) with one pivot 1e-7 times the
-    # others.  Eliminated in FP32, that pivot comes out of cancellation with
-    # an error of the order of u32 times the block's scale.  The growth check
-    # trips (min|d| < 1e-4 max|A|) and the tile is factored again in FP64 from
-    # the same stored (complex64) entries: its D must then be the FP64
-    # elimination of the complex64-rounded block -- the oracle's factor of K
-    # rounded to complex64 -- to complex64 precision, while the FP32
-    # elimination is far from it.  (The rounding of the input itself moves
-    # the small pivot by O(1) relative to D0; no re-factor recovers that, and
-    # the block row below the pivot still grows by ~1e7, so refinement needs
-    # many steps; the solve must reach the tolerance.)
+def test_fp64_fallback_recovers_a_pivot_fp32_cannot_carry():
+    # The first eliminated interface's diagonal block has small integer
+    # entries (exact in complex64) and, at rows k, k+1, the pair
+    # [[12288, 12289], [12289, 12290]] coupled to row k+2 by 64: the block is
+    # well conditioned (cond ~3e3), but its pivot at k+1 is 12290 -
+    # 12289^2/12288 = -1/12288, a cancellation to 8 digits.  FP32 elimination
+    # cannot carry it: the multiplier 12289/12288 rounds at 6e-8, times 12289
+    # that is an absolute error of 7e-4, several times the pivot itself.  The
+    # growth check trips (min|d| < 1e-4 max|A|) and the tile is factored
+    # again in FP64 from the stored entries, which are exact: D must then be
+    # the oracle's FP64 elimination of K (rounded to complex64) to complex64
+    # precision, and the solve must reach the tolerance.
+    # The right pivot does not make the first solution better: below it L
+    # grows by 1/|d| (L(k+2, k+1) = 64 * 12288), and the FP32 Schur updates
+    # carry that growth either way; in-tile pivoting, which takes rows
+    # k+1, k+2 as a 2x2 pivot, is what removes it (x0 at least 10x better).
     d3m = _d3m()
     inst = gen.make_instance((2, 2, 1), 40, gen.COEF_PLAIN, 2, 1212)
     order = oracle.nd_order(inst.grid)
     I = int(order[0])
     n = int(inst.sizes[I])
-    rng = np.random.default_rng(3)
-    L0 = np.eye(n) + 0.3 * np.tril((rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2), -1)
-    d0 = (3.0 + 0.5j) * np.sqrt(n) * rng.choice([-1.0, 1.0], n)
-    d0[n // 2] *= 1e-7
-    A = (L0 * d0) @ L0.T
+    rng = np.random.default_rng(5)
+    R = rng.integers(-8, 9, size=(n, n)) + 1j * rng.integers(-8, 9, size=(n, n))
+    A = np.tril(R, -1)
+    A = A + A.T + np.diag(rng.integers(200, 260, size=n) * rng.choice([-1, 1], n)).astype(complex)
+    k = n // 2
+    A[k, :] = A[:, k] = A[k + 1, :] = A[:, k + 1] = 0
+    A[k, k], A[k, k + 1], A[k + 1, k], A[k + 1, k + 1] = 12288, 12289, 12289, 12290
+    A[k + 1, k + 2] = A[k + 2, k + 1] = 64
+    assert np.linalg.cond(A) < 1e4
     inst.K[inst.offsets[I]:inst.offsets[I + 1]] = A.reshape(-1, order="F")
     ref = oracle.OraclePlan(inst.sizes, inst.pairs, order)
     assert ref.factor(inst.K.astype(np.complex64).astype(np.complex128)) < 0
     dref = np.diag(ref.block(I, I))
+    assert abs(dref[k + 1] * 12288 + 1) <= 1e-6   # the cancellation costs FP64 ~8 digits too
     plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, tile=64)
     assert int(plan.order()[0]) == I
     K = torch.from_numpy(inst.K).cuda()
     B = torch.from_numpy(inst.B).cuda()
     st, err = {}, {}
-    for fb in (True, False):
-        print(f"[case] cancelled pivot fallback={fb}", flush=True)
-        f = d3m.Factor(plan, d3m.C64_IR, nrhs_max=2, fallback=fb, max_iter=30)
+    for mode in ("fallback", "plain", "pivot"):
+        print(f"[case] integer block {mode}", flush=True)
+        f = d3m.Factor(plan, d3m.C64_IR, nrhs_max=2, fallback=mode == "fallback", pivot=mode == "pivot",
+                       max_iter=30)
         f.factorize(K)
         X = f.solve(B).cpu().numpy()
-        st[fb] = f.status()
-        d = np.diag(f.block(I, I))
-        err[fb] = (np.abs(d - dref) / np.abs(dref)).max()
-        print(f"[case] fallback={fb} max relative D error {err[fb]:.3e} status {st[fb]}", flush=True)
-        if fb:
-            assert st[fb]["fallbacks"] >= 1 and st[fb]["status"] == 0, st[fb]
-            assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, inst.B).max() <= 1e-10
-    assert st[False]["fallbacks"] == 0
-    assert err[True] <= 1e-4, err       # FP64 elimination, stored in complex64
-    assert err[False] >= 1e-2, err      # FP32 elimination: the cancellation shows
+        st[mode] = f.status()
+        if mode != "pivot":
+            d = np.diag(f.block(I, I))
+            err[mode] = (np.abs(d - dref) / np.abs(dref)).max()
+        print(f"[case] {mode}: D error {err.get(mode)} status {st[mode]}", flush=True)
+        assert st[mode]["status"] == 0, st[mode]
+        assert oracle.backward_error(inst.sizes, inst.pairs, inst.K, X, inst.B).max() <= 1e-10
+    assert st["fallback"]["fallbacks"] >= 1 and st["plain"]["fallbacks"] == 0
+    assert err["fallback"] <= 1e-6, err   # FP64 elimination of exact entries, stored in complex64
+    assert err["plain"] >= 0.5, err       # FP32 elimination: the pivot is wrong in its leading digit
+    assert 10 * st["pivot"]["eta_hist"][0] <= min(st["fallback"]["eta_hist"][0], st["plain"]["eta_hist"][0]), st
