@@ -223,10 +223,9 @@ def main():
     if st_mixed["status"] != 0:
         raise SystemExit(f"mixed path status {st_mixed}")
     dag_ms = st_mixed["t_factor_dag_ms"] / max(1, st_mixed["n_factor_dag"])
-    # every solve launch is timed, also the refinement steps that return at
-    # once after convergence (a few microseconds each): per solve pass that
-    # ran, the total over the (ir_iters + 1) passes of each step
-    solve_ms = st_mixed["t_solve_dag_ms"] / (args.steps * (st_mixed["ir_iters"] + 1))
+    # the first solve launch of each step is timed (the refinement's
+    # launches run under the device stop flag and are not)
+    solve_ms = st_mixed["t_solve_dag_ms"] / max(1, st_mixed["n_solve_dag"])
     solve_bytes = 2.0 * plan.info["nnz_L"] * 8
     del f32
     torch.cuda.empty_cache()

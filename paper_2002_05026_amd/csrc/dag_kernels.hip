@@ -18,6 +18,7 @@
 #include "d3m_internal.h"
 #include "gemm_engine.h"
 #include "launch.h"
+#include "solve_mv.h"
 #include "tile_bk.h"
 #include "tile_ldlt.h"
 
@@ -33,7 +34,7 @@ template <typename T> struct Ctx {
   C* Gi;  // with pivoting: D^-1 L^-1 P of each diagonal block (Li then holds L^-1 P)
   C* W;
   C* Z;
-    const InstView* iv;
+  const InstView* iv;
   lds_char* lds;
   int nrhs;   // right-hand sides of the launch: the row stride of W and Z
   int j0;     // solve tasks: first column of the task's right-hand-side group
@@ -85,7 +86,7 @@ template <typename T> __device__ __forceinline__ Ctx<T> uniform_ctx(const Ctx<T>
   c.Z = ufirst_ptr(a.Z);
   c.iv = ufirst_ptr(a.iv);
   c.lds = (lds_char*)(uintptr_t)(uint32_t)ufirst((int32_t)(uint32_t)(uintptr_t)a.lds);
-    c.nrhs = ufirst(a.nrhs);
+  c.nrhs = ufirst(a.nrhs);
   c.j0 = ufirst(a.j0);
   c.ncols = ufirst(a.ncols);
   return c;
@@ -275,7 +276,17 @@ template <typename T>
 __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  if (nc <= kMvMaxCols) {
+    Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
+    if (cx.iv->pivot) {
+      solve_mv<T, false>(t.m, nc, t.k + t.pad0, cx.Gi + t.a_off, t.lda, cx.W + t.b_off * nr + j0, nr, o, cx.lds);
+    } else {
+      o.rowdiv = cx.D + t.dofs;
+      solve_mv<T, false>(t.m, nc, t.k, cx.Li + t.a_off, t.lda, cx.W + t.b_off * nr + j0, nr, o, cx.lds);
+    }
+    return;
+  }
   Acc<T> acc;
   acc.zero();
   if (cx.iv->pivot) {
@@ -298,7 +309,12 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
 // operands); t.n = 1: the target is an extra accumulator written first
 template <typename T>
 __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
-    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  if (nc <= kMvMaxCols && t.pad0 <= 1) {
+    const Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, t.n ? (T)0 : (T)1);
+    solve_mv<T, false>(t.m, nc, t.k, cx.LD + t.a_off, t.lda, cx.Z + t.b_off * nr + j0, nr, o, cx.lds);
+    return;
+  }
   Acc<T> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
@@ -319,7 +335,7 @@ template <typename T>
 __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-    const int64_t nr = cx.nrhs, stride = cx.iv->N * nr, nc = cx.ncols;
+  const int64_t nr = cx.nrhs, stride = cx.iv->N * nr, nc = cx.ncols;
   D3M_GLB cpx<T>* w = gptr_mut<T>(cx.W + t.c_off * nr + cx.j0);
   const int64_t tot = (int64_t)t.m * nc;
   auto at = [&](int64_t e) { return (e / nc) * nr + e % nc; };  // element e: row e / nc, group column e % nc
@@ -332,7 +348,7 @@ __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
     cpx<T> v[E], u[kSolveSlots][E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-            const int64_t e = e0 + (int64_t)i * kThreads, ec = e < tot ? at(e) : 0;
+      const int64_t e = e0 + (int64_t)i * kThreads, ec = e < tot ? at(e) : 0;
       v[i] = w[ec];
 #pragma unroll
       for (int q = 0; q < kSolveSlots; ++q) u[q][i] = w[(q < t.k ? (q + 1) * stride : 0) + ec];
@@ -346,7 +362,7 @@ __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
           v[i].x += u[q][i].x;
           v[i].y += u[q][i].y;
         }
-            if (e < tot) w[at(e)] = v[i];
+      if (e < tot) w[at(e)] = v[i];
     }
   }
 }
@@ -356,7 +372,12 @@ template <typename T>
 __device__ __noinline__ void task_bupd(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  if (nc <= kMvMaxCols) {
+    const Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)-1, (T)1);
+    solve_mv<T, true>(t.m, nc, t.k, cx.L + t.a_off, t.lda, cx.W + t.b_off * nr + j0, nr, o, cx.lds);
+    return;
+  }
   Acc<T> acc;
   acc.zero();
   gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(acc, t.m, nc, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T),
@@ -371,10 +392,16 @@ template <typename T>
 __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   const Ctx<T> cx = uniform_ctx(cx_);
   const Task t = uniform_task(t_);
-    const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
+  const int back = cx.iv->pivot ? t.pad0 : 0;
+  if (nc <= kMvMaxCols) {
+    const Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
+    solve_mv<T, true>(t.m, nc, t.k + back, cx.Li + t.a_off - back, t.lda, cx.Z + (t.b_off - back) * nr + j0, nr, o,
+                      cx.lds);
+    return;
+  }
   Acc<T> acc;
   acc.zero();
-  const int back = cx.iv->pivot ? t.pad0 : 0;
   gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(
       acc, t.m, nc, t.k + back, opn<T>(cx.Li + t.a_off - back, t.lda, OP_T), nullptr,
       opn<T>(cx.Z + (t.b_off - back) * nr + j0, nr), cx.lds);
@@ -394,7 +421,7 @@ __device__ void run_task(const Task& t, const InstView* ivs, int nrhs, int group
   cx.W = reinterpret_cast<C*>(cx.iv->W);
   cx.Z = reinterpret_cast<C*>(cx.iv->Z);
   cx.lds = lds;
-    cx.nrhs = nrhs > 0 ? nrhs : cx.iv->nrhs;
+  cx.nrhs = nrhs > 0 ? nrhs : cx.iv->nrhs;
   // the right-hand-side group of a solve task (bits 8.. of the kind)
   const int grp = t.kind >> 8, per = (cx.nrhs + groups - 1) / groups;
   cx.j0 = grp * per;
@@ -528,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
     const int t = __builtin_amdgcn_readfirstlane(s_ticket);
     if (t < 0) break;
     const Task task = uniform_task(s_task[b]);
-        run_task<T, kPreSrc>(task, a.inst, a.nrhs, a.rhs_groups > 0 ? a.rhs_groups : 1, (lds_char*)lds);
+    run_task<T, kPreSrc>(task, a.inst, a.nrhs, a.rhs_groups > 0 ? a.rhs_groups : 1, (lds_char*)lds);
     // The source table is single-buffered: the only task that reads it (a
     // merged XUPD) ends with a barrier after its last read, and every LDS
     // access of any task after its last barrier lies below the table, so
@@ -550,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const Task* tasks, int begin
   int t = begin + blockIdx.x;
   if (t >= end) return;
   const Task task = tasks[t];
-    run_task<T>(task, iv, 0, 1, (lds_char*)lds);
+  run_task<T>(task, iv, 0, 1, (lds_char*)lds);
 }
 
 __global__ void k_reset(int32_t* counters, const int32_t* init, int n, int32_t* head, int32_t* abort_flag,
