@@ -116,6 +116,7 @@ __device__ __forceinline__ Out<T> outp(typename Cplx<T>::type* dst, int64_t rs, 
   o.dst2 = nullptr;
   o.rowdiv = nullptr;
   o.coldiv = nullptr;
+  o.wt = false;
   return o;
 }
 
@@ -279,6 +280,7 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
   const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   if (nc <= kMvMaxCols) {
     Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
+    o.wt = true;
     if (cx.iv->pivot) {
       solve_mv<T, false>(t.m, nc, t.k + t.pad0, cx.Gi + t.a_off, t.lda, cx.W + t.b_off * nr + j0, nr, o, cx.lds);
     } else {
@@ -293,7 +295,9 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
     gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, t.k + t.pad0,
                                                                opn<T>(cx.Gi + t.a_off, t.lda), nullptr,
                                                                opn<T>(cx.W + t.b_off * nr + j0, nr), cx.lds);
-    gemm_store<T>(acc, t.m, nc, outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0));
+    Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
+    o.wt = true;
+    gemm_store<T>(acc, t.m, nc, o);
     return;
   }
   gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, t.k, opn<T>(cx.Li + t.a_off, t.lda),
@@ -301,6 +305,7 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
                                                              cx.lds);
   Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
   o.rowdiv = cx.D + t.dofs;
+  o.wt = true;
   gemm_store<T>(acc, t.m, nc, o);
 }
 
@@ -311,7 +316,8 @@ template <typename T>
 __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   if (nc <= kMvMaxCols && t.pad0 <= 1) {
-    const Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, t.n ? (T)0 : (T)1);
+    Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, t.n ? (T)0 : (T)1);
+    o.wt = true;
     solve_mv<T, false>(t.m, nc, t.k, cx.LD + t.a_off, t.lda, cx.Z + t.b_off * nr + j0, nr, o, cx.lds);
     return;
   }
@@ -326,8 +332,10 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
                                                                cx.lds);
   }
   // two stores with a constant beta each, so neither has a per-element branch
-  if (t.n) gemm_store<T>(acc, t.m, nc, outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)0));
-  else gemm_store<T>(acc, t.m, nc, outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)1));
+  Out<T> o0 = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)0), o1 = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)1);
+  o0.wt = o1.wt = true;
+  if (t.n) gemm_store<T>(acc, t.m, nc, o0);
+  else gemm_store<T>(acc, t.m, nc, o1);
 }
 
 // b_r += the t.k extra accumulators of tile r (N rows apart) (TK_RED)
@@ -362,7 +370,7 @@ __device__ __noinline__ void task_red(const Ctx<T>& cx_, const Task& t_) {
           v[i].x += u[q][i].x;
           v[i].y += u[q][i].y;
         }
-      if (e < tot) w[at(e)] = v[i];
+      if (e < tot) st_out<T>(w + at(e), v[i], true);
     }
   }
 }
@@ -374,7 +382,8 @@ __device__ __noinline__ void task_bupd(const Ctx<T>& cx_, const Task& t_) {
   const Task t = uniform_task(t_);
   const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   if (nc <= kMvMaxCols) {
-    const Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)-1, (T)1);
+    Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)-1, (T)1);
+    o.wt = true;
     solve_mv<T, true>(t.m, nc, t.k, cx.L + t.a_off, t.lda, cx.W + t.b_off * nr + j0, nr, o, cx.lds);
     return;
   }
@@ -382,7 +391,9 @@ __device__ __noinline__ void task_bupd(const Ctx<T>& cx_, const Task& t_) {
   acc.zero();
   gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(acc, t.m, nc, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T),
                                                               nullptr, opn<T>(cx.W + t.b_off * nr + j0, nr), cx.lds);
-  gemm_store<T>(acc, t.m, nc, outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)-1, (T)1));
+  Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)-1, (T)1);
+  o.wt = true;
+  gemm_store<T>(acc, t.m, nc, o);
 }
 
 // backward, one tile: x_c = sum_{p >= r0_c} Linv_II(p, c) t_p; with
@@ -395,7 +406,8 @@ __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   const int back = cx.iv->pivot ? t.pad0 : 0;
   if (nc <= kMvMaxCols) {
-    const Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
+    Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
+    o.wt = true;
     solve_mv<T, true>(t.m, nc, t.k + back, cx.Li + t.a_off - back, t.lda, cx.Z + (t.b_off - back) * nr + j0, nr, o,
                       cx.lds);
     return;
@@ -405,7 +417,9 @@ __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(
       acc, t.m, nc, t.k + back, opn<T>(cx.Li + t.a_off - back, t.lda, OP_T), nullptr,
       opn<T>(cx.Z + (t.b_off - back) * nr + j0, nr), cx.lds);
-  gemm_store<T>(acc, t.m, nc, outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)1, (T)0));
+  Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
+  o.wt = true;
+  gemm_store<T>(acc, t.m, nc, o);
 }
 
 template <typename T, bool PRESRC = false>
@@ -499,7 +513,11 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
   // among the outstanding vector-memory operations)
   auto release = [&](const Task& task, int t) {
     if (threadIdx.x < 64) {
-      __scoped_atomic_thread_fence(__ATOMIC_RELEASE, __MEMORY_SCOPE_DEVICE);
+      // solve tasks store only with write-through stores (st_out), complete
+      // here (each wave waited for its stores before the barrier): no L2
+      // write-back; the factor's tile stores are ordinary and need it
+      if constexpr (PHASE == 1) __scoped_atomic_thread_fence(__ATOMIC_RELEASE, __MEMORY_SCOPE_WRKGRP);
+      else __scoped_atomic_thread_fence(__ATOMIC_RELEASE, __MEMORY_SCOPE_DEVICE);
       if (threadIdx.x == 0 && a.trace) a.trace[4 * t + 2] = (int64_t)wall_clock64();
       for (int s = threadIdx.x; s < task.nsucc; s += 64)
         __hip_atomic_fetch_add(&a.counters[a.succ[task.succ_begin + s]], -1, __ATOMIC_RELAXED,

@@ -117,7 +117,22 @@ template <typename T> struct Out {
   T alpha, beta;
   const typename Cplx<T>::type* rowdiv;     // divide row i by rowdiv[i], or null
   const typename Cplx<T>::type* coldiv;     // divide column j by coldiv[j], or null
+  bool wt = false;                          // store with device-scope atomic stores (write-through)
 };
+
+// One output element.  wt: as two relaxed device-scope atomic stores, which
+// write through to where every XCD sees them; a task whose stores are all of
+// that kind needs no L2 write-back before it releases its successors.
+template <typename T>
+__device__ __forceinline__ void st_out(D3M_GLB cpx<T>* p, const cpx<T>& v, bool wt) {
+  if (wt) {
+    D3M_GLB T* q = (D3M_GLB T*)p;
+    __hip_atomic_store(q, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = v;
+  }
+}
 
 // Accumulator of one wave: 8 column blocks of 16x16.  complex128 keeps the
 // real and imaginary parts.  complex64 uses three real products per complex
@@ -870,7 +885,7 @@ __device__ __forceinline__ void gemm_store_impl(const Acc<T, TR>& acc, int m, in
               }
               gptr_mut<T>(o.dst2)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
             }
-            dst[(int64_t)i * o.rs + (int64_t)j * o.cs] = res[b4][v];
+            st_out<T>(dst + (int64_t)i * o.rs + (int64_t)j * o.cs, res[b4][v], o.wt);
           }
         }
       }

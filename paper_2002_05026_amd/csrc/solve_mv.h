@@ -31,6 +31,7 @@
 namespace d3m {
 
 constexpr int kMvMaxCols = 8;  // right-hand-side columns of one task handled here
+static_assert(kTileMax * kMvMaxCols <= 2 * kThreads, "mv_n: at most two outputs per thread");
 
 template <typename T> __device__ __forceinline__ cpx<T> mv_zero() {
   cpx<T> z;
@@ -47,17 +48,28 @@ template <typename T> __device__ __forceinline__ void mv_fma(cpx<T>& acc, cpx<T>
   acc.y = fma(a.y, b.x, acc.y);
 }
 
-template <typename T> __device__ __forceinline__ void mv_put(const Out<T>& o, int i, int j, cpx<T> acc) {
+// The beta term and the row divisor of output (i, j), loaded ahead (their
+// latency then overlaps the products).
+template <typename T> struct MvPre {
+  cpx<T> src, div;
+};
+template <typename T> __device__ __forceinline__ MvPre<T> mv_pre(const Out<T>& o, int i, int j) {
+  MvPre<T> q;
+  q.src = o.src ? *gptr<T>(o.src + (int64_t)i * o.srs + (int64_t)j * o.scs) : mv_zero<T>();
+  q.div = o.rowdiv ? *gptr<T>(o.rowdiv + i) : mv_zero<T>();
+  return q;
+}
+template <typename T> __device__ __forceinline__ void mv_put(const Out<T>& o, int i, int j, cpx<T> acc,
+                                                           const MvPre<T>& q) {
   cpx<T> r;
   r.x = acc.x * o.alpha;
   r.y = acc.y * o.alpha;
   if (o.src) {
-    const cpx<T> s = *gptr<T>(o.src + (int64_t)i * o.srs + (int64_t)j * o.scs);
-    r.x += o.beta * s.x;
-    r.y += o.beta * s.y;
+    r.x += o.beta * q.src.x;
+    r.y += o.beta * q.src.y;
   }
-  if (o.rowdiv) r = cpx_div(r, *gptr<T>(o.rowdiv + i));
-  gptr_mut<T>(o.dst)[(int64_t)i * o.rs + (int64_t)j * o.cs] = r;
+  if (o.rowdiv) r = cpx_div(r, q.div);
+  st_out<T>(gptr_mut<T>(o.dst) + (int64_t)i * o.rs + (int64_t)j * o.cs, r, o.wt);
 }
 
 // OP_N.  NCP: nc rounded up to a power of two.
@@ -78,15 +90,49 @@ __device__ __noinline__ void mv_n(int m, int nc, int k, const typename Cplx<T>::
   cpx<T> acc[NCP];
 #pragma unroll
   for (int j = 0; j < NCP; ++j) acc[j] = mv_zero<T>();
+  // the output terms this thread will need (m * nc <= 1024: outputs tid and
+  // tid + 512)
+  MvPre<T> pre[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + h * kThreads < m * nc ? tid + h * kThreads : 0;
+    pre[h] = mv_pre(o, e / nc, e - (e / nc) * nc);
+  }
+  // UN loads per lane go out before their products: with 512 lanes that
+  // keeps UN x 8 KB (complex128) in flight per CU.  The first pass's loads
+  // of each chunk are issued before B is staged, which then overlaps them.
+  constexpr int UN = 16;
   for (int k0 = 0; k0 < k; k0 += KC) {
     const int kc = min(KC, k - k0);
+    const typename Cplx<T>::type* Ar = A + rc + (int64_t)k0 * lda;
+    cpx<T> a0[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int p = g + u * G;
+      a0[u] = *gptr<T>(Ar + (int64_t)(p < kc ? p : 0) * lda);
+    }
     for (int e = tid; e < kc * NCP; e += kThreads) {
       const int p = e / NCP, j = e % NCP;
       Bs[e] = j < nc ? *gptr<T>(B + (int64_t)(k0 + p) * ldb + j) : mv_zero<T>();
     }
     __syncthreads();
-    const typename Cplx<T>::type* Ar = A + rc + (int64_t)k0 * lda;
-    int p = g;
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int p = g + u * G;
+      if (p < kc)
+#pragma unroll
+        for (int j = 0; j < NCP; ++j) mv_fma(acc[j], a0[u], Bs[p * NCP + j]);
+    }
+    int p = g + UN * G;
+    for (; p + (UN - 1) * G < kc; p += UN * G) {
+      cpx<T> a[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) a[u] = *gptr<T>(Ar + (int64_t)(p + u * G) * lda);
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int j = 0; j < NCP; ++j) mv_fma(acc[j], a[u], Bs[(p + u * G) * NCP + j]);
+    }
     for (; p + 3 * G < kc; p += 4 * G) {
       cpx<T> a[4];
 #pragma unroll
@@ -122,15 +168,19 @@ __device__ __noinline__ void mv_n(int m, int nc, int k, const typename Cplx<T>::
     }
     __syncthreads();
   }
-  for (int e = tid; e < m * nc; e += kThreads) {
-    const int i = e / nc, j = e - (e / nc) * nc;
-    cpx<T> s = red[i * NCP + j];
-    for (int q = 1; q < S; ++q) {
-      const cpx<T> v = red[(q * RM + i) * NCP + j];
-      s.x += v.x;
-      s.y += v.y;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + h * kThreads;
+    if (e < m * nc) {
+      const int i = e / nc, j = e - (e / nc) * nc;
+      cpx<T> s = red[i * NCP + j];
+      for (int q = 1; q < S; ++q) {
+        const cpx<T> v = red[(q * RM + i) * NCP + j];
+        s.x += v.x;
+        s.y += v.y;
+      }
+      mv_put(o, i, j, s, pre[h]);
     }
-    mv_put(o, i, j, s);
   }
   __syncthreads();
 }
@@ -177,38 +227,50 @@ __device__ __noinline__ void mv_t(int m, int nc, int k, const typename Cplx<T>::
   const int nbat = (m + RG - 1) / RG;
   for (int bt = w; bt < nbat; bt += kThreads / 64) {
     const int i0 = bt * RG;
+    // the output term of the value this lane will hold after the reduction
+    const int idx0 = lane >> SH;
+    const int rr0 = (idx0 >> 1) / NCP, j0 = (idx0 >> 1) % NCP;
+    const bool mine = (lane & ((1 << SH) - 1)) == 0 && (idx0 & 1) == 0 && i0 + rr0 < m && j0 < nc;
+    const MvPre<T> pre = mv_pre(o, mine ? i0 + rr0 : 0, mine ? j0 : 0);
     T v[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) v[q] = (T)0;
-    for (int p = lane; p < k; p += 64) {
-      cpx<T> b[NCP];
+    // UP passes over p go out together (their loads before any product)
+    constexpr int UP = 2;
+    for (int p0 = lane; p0 < k; p0 += 64 * UP) {
+      cpx<T> b[UP][NCP], a[UP][RG];
 #pragma unroll
-      for (int j = 0; j < NCP; ++j) b[j] = j < nc ? *gptr<T>(B + (int64_t)p * ldb + j) : mv_zero<T>();
-      cpx<T> a[RG];
+      for (int u = 0; u < UP; ++u) {
+        const int p = p0 + 64 * u;
+        const bool pk = p < k;
 #pragma unroll
-      for (int rr = 0; rr < RG; ++rr)
-        a[rr] = i0 + rr < m ? *gptr<T>(A + p + (int64_t)(i0 + rr) * lda) : mv_zero<T>();
+        for (int j = 0; j < NCP; ++j)
+          b[u][j] = (pk && j < nc) ? *gptr<T>(B + (int64_t)p * ldb + j) : mv_zero<T>();
 #pragma unroll
-      for (int rr = 0; rr < RG; ++rr)
+        for (int rr = 0; rr < RG; ++rr)
+          a[u][rr] = (pk && i0 + rr < m) ? *gptr<T>(A + p + (int64_t)(i0 + rr) * lda) : mv_zero<T>();
+      }
 #pragma unroll
-        for (int j = 0; j < NCP; ++j) {
-          cpx<T> s;
-          s.x = v[(rr * NCP + j) * 2];
-          s.y = v[(rr * NCP + j) * 2 + 1];
-          mv_fma(s, a[rr], b[j]);
-          v[(rr * NCP + j) * 2] = s.x;
-          v[(rr * NCP + j) * 2 + 1] = s.y;
-        }
+      for (int u = 0; u < UP; ++u)
+#pragma unroll
+        for (int rr = 0; rr < RG; ++rr)
+#pragma unroll
+          for (int j = 0; j < NCP; ++j) {
+            cpx<T> s;
+            s.x = v[(rr * NCP + j) * 2];
+            s.y = v[(rr * NCP + j) * 2 + 1];
+            mv_fma(s, a[u][rr], b[u][j]);
+            v[(rr * NCP + j) * 2] = s.x;
+            v[(rr * NCP + j) * 2 + 1] = s.y;
+          }
     }
     mv_wave_reduce<T, V>(v, lane);
-    const int idx = lane >> SH;
-    const T im = __shfl_xor(v[0], 1 << SH, 64);  // the partner holds value idx ^ 1
-    const int rr = (idx >> 1) / NCP, j = (idx >> 1) % NCP;
-    if ((lane & ((1 << SH) - 1)) == 0 && (idx & 1) == 0 && i0 + rr < m && j < nc) {
+    const T im = __shfl_xor(v[0], 1 << SH, 64);  // the partner holds value idx0 ^ 1
+    if (mine) {
       cpx<T> s;
       s.x = v[0];
       s.y = im;
-      mv_put(o, i0 + rr, j, s);
+      mv_put(o, i0 + rr0, j0, s, pre);
     }
   }
 }
