@@ -8,6 +8,7 @@
 #include "d3m_internal.h"
 #include "gemm_engine.h"
 #include "launch.h"
+#include "ir_parts.h"
 
 namespace d3m {
 
@@ -185,17 +186,7 @@ template <typename T>
 __global__ void k_perm_in(const double2* B, int64_t ld, typename Cplx<T>::type* W, const int32_t* perm,
                           int64_t N, int nrhs, const int32_t* skip) {
   if (skip && *skip) return;
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = N * nrhs;
-  for (; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t q = e / nrhs;
-    int j = (int)(e - q * nrhs);
-    double2 v = B[(int64_t)j * ld + perm[q]];
-    typename Cplx<T>::type o;
-    o.x = (T)v.x;
-    o.y = (T)v.y;
-    W[e] = o;
-  }
+  perm_in_part<T>(B, ld, W, perm, N, nrhs, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_perm_in(const void* B, int64_t ld, void* W, int prec, const UserView& uv, int nrhs,
@@ -210,13 +201,7 @@ hipError_t launch_perm_in(const void* B, int64_t ld, void* W, int prec, const Us
 }
 
 __global__ void k_perm_out(const double2* W, double2* X, int64_t ld, const int32_t* perm, int64_t N, int nrhs) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = N * nrhs;
-  for (; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t q = e / nrhs;
-    int j = (int)(e - q * nrhs);
-    X[(int64_t)j * ld + perm[q]] = W[e];
-  }
+  perm_out_part(W, X, ld, perm, N, nrhs, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_perm_out(const void* W, void* X, int64_t ld, const UserView& uv, int nrhs, hipStream_t s) {
@@ -309,65 +294,12 @@ hipError_t launch_ports(const void* M, int64_t ldm, const void* U, int64_t ldu, 
 }
 
 // ---------------------------------------------------------------- residual
-__device__ __forceinline__ void atomic_max_pos(double* p, double v) {
-  // non-negative doubles order like their bit patterns
-  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
-}
-
-// Partial residual products: workgroup (x, y, z) takes row tile x,
-// right-hand sides [64y, 64y + 64) and chunk z of the tile's block row, and
-// writes P_z = sum over the chunk's blocks K_IJ X_J (internal rows, RHS
-// fastest; zeros for an empty chunk).  Four 16-column FP64 accumulator
-// blocks per wave (no register spills at any nrhs), so the registers allow
-// slabs of 16 columns.
-constexpr int kResCols = 64;
+// (the bodies are in ir_parts.h, shared with the batched launches)
 __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const double2* X, double2* P, UserView uv,
                                                   const RTaskDev* rt, int nrhs, const int32_t* skip) {
-  constexpr int NB = kResCols / 16, KB = 16;  // 16-column FP64 slabs: more latency cover per slab
-  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double, KB>()];
+  __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double, kResKB>()];
   if (skip && *skip) return;
-  const RTaskDev t = rt[blockIdx.x];
-  const int I = t.I;
-  const int nI = uv.n[I];
-  const int j0 = kResCols * blockIdx.y;
-  const int nr = nrhs - j0 < kResCols ? nrhs - j0 : kResCols;
-  const int e0 = uv.rsplit[I * (kResSplit + 1) + blockIdx.z], e1 = uv.rsplit[I * (kResSplit + 1) + blockIdx.z + 1];
-  Acc<double> acc;
-  acc.zero();
-  for (int e = e0; e < e1; ++e) {
-    const RBlkDev b = uv.rblk[e];
-    const int nJ = uv.n[b.J];
-    Opnd<double> A;
-    A.i0 = 0;
-    if (b.mode == 0) { A.p = K + b.koff; A.ld = nI; A.mode = OP_SYM; A.i0 = t.r0; }
-    else if (b.mode == 1) { A.p = K + b.koff + t.r0; A.ld = nI; A.mode = OP_N; }
-    else { A.p = K + b.koff + (int64_t)t.r0 * nJ; A.ld = nJ; A.mode = OP_T; }
-    Opnd<double> Bo;
-    Bo.p = X + uv.prow0[b.J] * nrhs + j0;
-    Bo.ld = nrhs;
-    Bo.mode = OP_N;
-    Bo.i0 = 0;
-    gemm_acc<double, NB, KB>(acc, t.sz, nr, nJ, A, nullptr, Bo, (lds_char*)lds);
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  double2* dst = P + (int64_t)blockIdx.z * uv.N * nrhs + (uv.prow0[I] + t.r0) * nrhs + j0;
-  if (16 * w < t.sz) {
-#pragma unroll
-    for (int bj = 0; bj < NB; ++bj) {
-      const int j = 16 * bj + lr;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * w + acc_row<double>(lk, v);
-        if (i < t.sz && j < nr) {
-          double2 r;
-          r.x = acc.re[bj][v];
-          r.y = acc.im[bj][v];
-          dst[(int64_t)i * nrhs + j] = r;
-        }
-      }
-    }
-  }
+  residual_tile(K, X, P, uv, rt[blockIdx.x], nrhs, blockIdx.y, blockIdx.z, (lds_char*)lds);
 }
 
 // R = B - sum_z P_z (internal rows, RHS fastest; B in user layout) and the
@@ -376,26 +308,7 @@ __global__ void k_residual_fin(const double2* B, int64_t ld, const double2* P, d
                                UserView uv, int nrhs, const int32_t* skip) {
   if (skip && *skip) return;
   __shared__ unsigned long long cm[128];
-  if (threadIdx.x < 128) cm[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t tot = uv.N * nrhs;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t q = e / nrhs;
-    const int j = (int)(e - q * nrhs);
-    double2 r = B[uv.perm[q] + (int64_t)j * ld];
-#pragma unroll
-    for (int z = 0; z < kResSplit; ++z) {
-      const double2 p = P[z * tot + e];
-      r.x -= p.x;
-      r.y -= p.y;
-    }
-    R[e] = r;
-    double a = sqrt(r.x * r.x + r.y * r.y);
-    if (!(a == a)) a = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> inf
-    atomicMax(&cm[j], (unsigned long long)__double_as_longlong(a));
-  }
-  __syncthreads();
-  if (threadIdx.x < nrhs && cm[threadIdx.x]) atomic_max_pos(colmax + threadIdx.x, __longlong_as_double((long long)cm[threadIdx.x]));
+  residual_fin_part(B, ld, P, R, colmax, uv, nrhs, blockIdx.x, gridDim.x, cm);
 }
 
 hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void* X64, void* R64, void* P,
@@ -498,21 +411,7 @@ __global__ void k_colmax(const double2* V, int64_t rows, int nrhs, int64_t ld, i
                          const int32_t* skip) {
   if (skip && *skip) return;
   __shared__ unsigned long long cm[128];
-  if (threadIdx.x < 128) cm[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t tot = rows * nrhs;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t r;
-    int j;
-    double2 v;
-    if (rhs_fastest) { r = e / nrhs; j = (int)(e - r * nrhs); v = V[e]; }
-    else { j = (int)(e / rows); r = e - (int64_t)j * rows; v = V[(int64_t)j * ld + r]; }
-    double a = sqrt(v.x * v.x + v.y * v.y);
-    if (!(a == a)) a = __longlong_as_double(0x7ff0000000000000ll);
-    atomicMax(&cm[j], (unsigned long long)__double_as_longlong(a));
-  }
-  __syncthreads();
-  if (threadIdx.x < nrhs && cm[threadIdx.x]) atomic_max_pos(colmax + threadIdx.x, __longlong_as_double((long long)cm[threadIdx.x]));
+  colmax_part(V, rows, nrhs, ld, rhs_fastest, colmax, blockIdx.x, gridDim.x, cm);
 }
 
 hipError_t launch_colmax(const void* V, int64_t rows, int nrhs, int64_t ld, int rhs_fastest, double* colmax,
@@ -523,48 +422,14 @@ hipError_t launch_colmax(const void* V, int64_t rows, int nrhs, int64_t ld, int 
   return hipGetLastError();
 }
 
-// eta_j = rmax_j / (||K|| xmax_j + bmax_j); record max_j eta_j; decide.
 __global__ void k_ir_check(IrCtrl* c, double* rmax, double* xmax, const double* bmax, int nrhs, int final_step) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (c->stop) return;
-  double eta = 0;
-  bool nonfinite = false;
-  for (int j = 0; j < nrhs; ++j) {
-    double den = c->knorm * xmax[j] + bmax[j];
-    double e = den > 0 ? rmax[j] / den : rmax[j];
-    if (!(e <= 1e300)) nonfinite = true;
-    eta = fmax(eta, e);
-    rmax[j] = 0;
-    xmax[j] = 0;
-  }
-  const int it = c->it;
-  if (it < 32) c->eta_hist[it] = eta;
-  c->it = it + 1;
-  if (nonfinite) {
-    c->status = 2;  // D3M_NONFINITE
-    c->stop = 1;
-  } else if (eta <= c->tol || final_step == 2) {
-    c->stop = 1;
-  } else if (final_step || it >= c->max_iter) {
-    c->status = 3;  // D3M_IR_NOCONV
-    c->stop = 1;
-  } else if (it >= 2 && it < 32 && c->eta_hist[it - 2] >= 0 && eta > 0.5 * c->eta_hist[it - 2]) {
-    c->status = 3;  // stagnation
-    c->stop = 1;
-  } else {
-    c->iters = it + 1;
-  }
+  ir_check_one(c, rmax, xmax, bmax, nrhs, final_step);
 }
 
 __global__ void k_ir_reset(IrCtrl* c, double tol, int max_iter) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  c->stop = 0;
-  c->iters = 0;
-  c->status = 0;
-  c->it = 0;
-  c->tol = tol;
-  c->max_iter = max_iter;
-  for (int k = 0; k < 32; ++k) c->eta_hist[k] = -1.0;
+  ir_reset_one(c, tol, max_iter);
 }
 
 hipError_t launch_ir_reset(IrCtrl* ctrl, double tol, int max_iter, hipStream_t s) {
@@ -580,26 +445,12 @@ hipError_t launch_ir_check(IrCtrl* ctrl, double* rmax, double* xmax, const doubl
 
 __global__ void k_cvt_down(const double2* R, float2* W, int64_t n, const int32_t* skip) {
   if (skip && *skip) return;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    double2 v = R[e];
-    W[e] = make_float2((float)v.x, (float)v.y);
-  }
+  cvt_down_part(R, W, n, blockIdx.x, gridDim.x);
 }
-__global__ void k_cvt_up(const float2* W, double2* X, int64_t n) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    float2 v = W[e];
-    X[e] = make_double2(v.x, v.y);
-  }
-}
+__global__ void k_cvt_up(const float2* W, double2* X, int64_t n) { cvt_up_part(W, X, n, blockIdx.x, gridDim.x); }
 __global__ void k_axpy_up(const float2* W, double2* X, int64_t n, const int32_t* skip) {
   if (skip && *skip) return;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    float2 v = W[e];
-    double2 x = X[e];
-    x.x += v.x;
-    x.y += v.y;
-    X[e] = x;
-  }
+  axpy_up_part(W, X, n, blockIdx.x, gridDim.x);
 }
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 hipError_t launch_cvt_down(const void* R64, void* W32, int64_t n, const int32_t* skip, hipStream_t s) {

@@ -860,7 +860,7 @@ d3m_status d3m_tune_gemm(d3m_precision prec, void* dev_scratch, size_t bytes, in
 // ---------------------------------------------------------------- batching
 namespace {
 struct BatchLayout {
-  size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, counters, flags, iv, ctrls, total;
+  size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, counters, flags, iv, ctrls, bir, total;
 };
 BatchLayout batch_layout(const TaskDag& fd, const TaskDag& sd, int n) {
   BatchLayout l;
@@ -878,6 +878,7 @@ BatchLayout batch_layout(const TaskDag& fd, const TaskDag& sd, int n) {
   l.flags = take(4 * 4);
   l.iv = take(n * sizeof(InstView));
   l.ctrls = take(n * sizeof(IrCtrl*));
+  l.bir = take(n * sizeof(BatchIrDev));
   l.total = o;
   return l;
 }
@@ -890,6 +891,8 @@ struct d3m_batch_s {
   char* ws = nullptr;
   int prec = 0;
   int nworkers = 256;
+  int maxnrt = 1, maxnrhs = 1;
+  int64_t maxtot = 1;  // largest N * nrhs of an instance
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
 
@@ -955,12 +958,33 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
   b->ws = static_cast<char*>(dev_ws);
   std::vector<InstView> ivs(ninst);
   std::vector<IrCtrl*> ctrls(ninst);
+  std::vector<BatchIrDev> bir(ninst);
   for (int i = 0; i < ninst; ++i) {
     if (hipMemcpy(&ivs[i], f[i]->ws + f[i]->lay.iv, sizeof(InstView), hipMemcpyDeviceToHost) != hipSuccess) {
       delete b;
       return D3M_ERR_HIP;
     }
     ctrls[i] = f[i]->ctrl();
+    d3m_factor_s* fi = f[i];
+    BatchIrDev& t = bir[i];
+    std::memset(&t, 0, sizeof(t));
+    t.W = fi->ws + fi->lay.W;
+    t.X64 = fi->at<double2>(fi->lay.X64);
+    t.R64 = fi->at<double2>(fi->lay.R64);
+    t.P64 = fi->at<double2>(fi->lay.P64);
+    t.rmax = fi->rmax();
+    t.xmax = fi->xmax();
+    t.bmax = fi->bmax();
+    t.ctrl = fi->ctrl();
+    t.uv = fi->uv();
+    t.rt = fi->at<RTaskDev>(fi->lay.rt);
+    t.nrt = (int32_t)fi->tab.rt.size();
+    t.nrhs = fi->nrhs_max;
+    t.tol = fi->opt.tol;
+    t.max_iter = fi->opt.max_iter;
+    b->maxnrt = std::max(b->maxnrt, (int)t.nrt);
+    b->maxnrhs = std::max(b->maxnrhs, (int)t.nrhs);
+    b->maxtot = std::max<int64_t>(b->maxtot, fi->plan->p.N * t.nrhs);
   }
   auto up = [&](size_t off, const void* src, size_t n) {
     return n == 0 || hipMemcpy(b->ws + off, src, n, hipMemcpyHostToDevice) == hipSuccess;
@@ -972,7 +996,8 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
             up(b->lay.ssucc, b->sd.succ.data(), b->sd.succ.size() * 4) &&
             up(b->lay.scnt, b->sd.npred.data(), b->sd.npred.size() * 4) &&
             up(b->lay.iv, ivs.data(), ivs.size() * sizeof(InstView)) &&
-            up(b->lay.ctrls, ctrls.data(), ctrls.size() * sizeof(IrCtrl*));
+            up(b->lay.ctrls, ctrls.data(), ctrls.size() * sizeof(IrCtrl*)) &&
+            up(b->lay.bir, bir.data(), bir.size() * sizeof(BatchIrDev));
   if (!ok) { delete b; return D3M_ERR_HIP; }
   *out = b;
   return D3M_OK;
@@ -1000,50 +1025,31 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
   }
   d3m_status st = batch_dag(b, false, nullptr, s);
   if (st) return st;
-  for (int i = 0; i < n; ++i) {
-    d3m_factor_s* f = b->f[i];
-    HIPCHK(launch_copy_flag(b->at<int32_t>(b->lay.flags) + 1, f->at<int32_t>(f->lay.flags) + 1, s));
-    HIPCHK(launch_ir_reset(f->ctrl(), f->opt.tol, f->opt.max_iter, s));
-    HIPCHK(launch_zero_f64(f->rmax(), 3 * 128, s));
-    HIPCHK(launch_colmax(B[i], f->plan->p.N, nrhs[i], ld[i], 0, f->bmax(), nullptr, s));
-    HIPCHK(launch_perm_in(B[i], ld[i], f->ws + f->lay.W, b->prec, f->uv(), nrhs[i], nullptr, s));
-  }
+  for (int i = 0; i < n; ++i)
+    HIPCHK(launch_copy_flag(b->at<int32_t>(b->lay.flags) + 1, b->f[i]->at<int32_t>(b->f[i]->lay.flags) + 1, s));
+  // the refinement bookkeeping of all instances: one launch per kind and step
+  BatchIrDev* tab = b->at<BatchIrDev>(b->lay.bir);
+  HIPCHK(launch_batch_user(tab, n, K, B, X, ld, s));
+  HIPCHK(launch_batch_begin(tab, n, b->prec, b->maxtot, s));
   st = batch_dag(b, true, nullptr, s);
   if (st) return st;
   int32_t* allstop = b->at<int32_t>(b->lay.flags) + 2;
   const int max_iter = b->f[0]->opt.max_iter;
-  for (int i = 0; i < n; ++i) {
-    d3m_factor_s* f = b->f[i];
-    const int64_t nel = f->plan->p.N * nrhs[i];
-    if (b->prec == 1) HIPCHK(launch_cvt_up(f->ws + f->lay.W, f->ws + f->lay.X64, nel, s));
-  }
+  if (b->prec == 1) HIPCHK(launch_batch_cvt_up(tab, n, b->maxtot, s));
   for (int it = 0; it <= (b->prec == 1 ? max_iter : 0); ++it) {
-    for (int i = 0; i < n; ++i) {
-      d3m_factor_s* f = b->f[i];
-      const int64_t N = f->plan->p.N;
-      void* xv = b->prec == 1 ? f->ws + f->lay.X64 : f->ws + f->lay.W;
-      HIPCHK(launch_residual(K[i], B[i], ld[i], xv, f->ws + f->lay.R64, f->ws + f->lay.P64, f->rmax(), f->uv(),
-                             f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), nrhs[i], f->stop(), s));
-      HIPCHK(launch_colmax(xv, N, nrhs[i], 0, 1, f->xmax(), f->stop(), s));
-      HIPCHK(launch_ir_check(f->ctrl(), f->rmax(), f->xmax(), f->bmax(), nrhs[i],
-                             b->prec == 0 ? 2 : (it == max_iter ? 1 : 0), s));
-      if (b->prec == 1 && it < max_iter)
-        HIPCHK(launch_cvt_down(f->ws + f->lay.R64, f->ws + f->lay.W, N * nrhs[i], f->stop(), s));
-    }
+    HIPCHK(launch_batch_check(tab, n, b->prec, b->maxnrt, b->maxnrhs, b->maxtot,
+                              b->prec == 0 ? 2 : (it == max_iter ? 1 : 0), s));
+    if (b->prec == 1 && it < max_iter) HIPCHK(launch_batch_cvt_down(tab, n, b->maxtot, s));
     if (b->prec == 0 || it == max_iter) break;
     HIPCHK(launch_all_stop(b->at<IrCtrl*>(b->lay.ctrls), n, allstop, s));
     st = batch_dag(b, true, allstop, s);
     if (st) return st;
-    for (int i = 0; i < n; ++i) {
-      d3m_factor_s* f = b->f[i];
-      HIPCHK(launch_axpy_up(f->ws + f->lay.W, f->ws + f->lay.X64, f->plan->p.N * nrhs[i], f->stop(), s));
-    }
+    HIPCHK(launch_batch_axpy_up(tab, n, b->maxtot, s));
   }
+  HIPCHK(launch_batch_perm_out(tab, n, b->prec, b->maxtot, s));
   for (int i = 0; i < n; ++i) {
-    d3m_factor_s* f = b->f[i];
-    HIPCHK(launch_perm_out(b->prec == 1 ? f->ws + f->lay.X64 : f->ws + f->lay.W, X[i], ld[i], f->uv(), nrhs[i], s));
-    f->last = s;
-    f->factored = true;
+    b->f[i]->last = s;
+    b->f[i]->factored = true;
   }
   return D3M_OK;
 }

@@ -100,6 +100,46 @@ hipError_t launch_dk(const void* Lam, const void* X, int64_t ld, int nrhs, void*
                      const DkTaskDev* dt, int ndt, int stored, hipStream_t s);
 hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t s);
 hipError_t launch_all_stop(IrCtrl* const* ctrls, int n, int32_t* out, hipStream_t s);
+
+// One instance of a batch, as the batched refinement kernels see it: the
+// user's K, B and X (set before each run), the instance's workspace arrays
+// and refinement controls.
+struct BatchIrDev {
+  const double2* K;
+  const double2* B;
+  double2* X;
+  int64_t ld;
+  void* W;         // the factor-precision solve vector (complex128 for a complex128 batch)
+  double2* X64;
+  double2* R64;
+  double2* P64;
+  double* rmax;    // 3 x 128 doubles: rmax, xmax, bmax
+  double* xmax;
+  double* bmax;
+  IrCtrl* ctrl;
+  UserView uv;
+  const RTaskDev* rt;
+  int32_t nrt, nrhs;
+  double tol;
+  int32_t max_iter, pad;
+};
+constexpr int kBatchUserMax = 32;  // instances whose user pointers one launch sets
+struct BatchUserArgs {
+  const void* K[kBatchUserMax];
+  const void* B[kBatchUserMax];
+  void* X[kBatchUserMax];
+  int64_t ld[kBatchUserMax];
+  int32_t base, count;
+};
+hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const void* const* B, void* const* X,
+                             const int64_t* ld, hipStream_t s);
+hipError_t launch_batch_begin(BatchIrDev* tab, int n, int prec, int64_t maxtot, hipStream_t s);
+hipError_t launch_batch_cvt_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
+hipError_t launch_batch_check(BatchIrDev* tab, int n, int prec, int maxnrt, int maxnrhs, int64_t maxtot,
+                              int final_step, hipStream_t s);
+hipError_t launch_batch_cvt_down(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
+hipError_t launch_batch_axpy_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
+hipError_t launch_batch_perm_out(BatchIrDev* tab, int n, int prec, int64_t maxtot, hipStream_t s);
 hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, const void* A, int64_t lda,
                              const void* d, const void* B, int64_t ldb, void* C, int64_t ldc, double alpha,
                              double beta, hipStream_t s);

@@ -96,7 +96,8 @@ def batch(args):
     _log(f"batch: {len(insts)} instances, N = {[i.N for i in insts][:8]}...")
     # tile edge from the tuner (timed on one instance of the largest grid)
     probe = max(insts, key=lambda i: i.N)
-    tuned = tune.tune(probe, d3m.C64_IR, nrhs=16, reps=2)
+    tuned = {"config": dict(tune.DEFAULT), "timings": None} if getattr(args, "no_tune", False) else \
+        tune.tune(probe, d3m.C64_IR, nrhs=16, reps=2)
     cfg = tuned["config"]
     _log(f"tuned tile {tuned}")
     fs, Ks, Bs, Xs, flops = [], [], [], [], 0.0
