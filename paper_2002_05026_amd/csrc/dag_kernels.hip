@@ -180,6 +180,17 @@ __device__ __noinline__ void task_trsm(const Ctx<T>& cx_, const Task& t_) {
   gemm_store<T>(acc, t.m, t.n, o, cx.lds);
 }
 
+// Whether a complex64 Schur update of an m x n tile is formed as its
+// transpose, C^T -= (L_sI D_I) L_rI^T.  The engine gives each wave 16 rows
+// (two waves per SIMD, so more than 4 row blocks cost two) and issues the
+// products of the accumulator's column blocks, so a tile with fewer row
+// than column blocks issues fewer products transposed.  The same products
+// are summed in the same order; only which side carries D differs.
+__device__ __forceinline__ bool xupd_swap(int m, int n) {
+  const int mb = (m + 15) >> 4, nb = (n + 15) >> 4;
+  return (nb > 4 ? 2 : 1) * mb < (mb > 4 ? 2 : 1) * nb;
+}
+
 // C -= sum over the task's sources of (L_rI D_I) L_sI^T on one tile pair
 // (TK_XUPD); t.pad0 > 1: the sources are xsrc[t.pad1 ...], else the task's
 // own operands
@@ -192,7 +203,7 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
   Acc<T, true> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
-  const Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1);
+  Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1);
   GePre<T> pre;
   pre.ok = false;
   auto src = [&](int q) {
@@ -206,11 +217,12 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
     // direct-load pipeline runs over the slabs of all of them; the target's
     // loads go out with the last slab
     D3M_LDS GeSrc<T>* tab = reinterpret_cast<D3M_LDS GeSrc<T>*>(cx.lds + ge_lds_bytes_dma<T>());
+    const bool sw = xupd_swap(t.m, t.n);
     if (!(PRESRC && t.pad0 > 1) && (int)threadIdx.x < nsrc) {
       const XSrc x = src(threadIdx.x);
       GeSrc<T> e;
-      e.a = cx.LD + x.a_off;
-      e.b = cx.L + x.b_off;
+      e.a = cx.LD + (sw ? x.b_off : x.a_off);
+      e.b = cx.L + (sw ? x.a_off : x.b_off);
       e.lda = e.ldb = x.lda;
       e.k = x.k;
       e.pad = 0;
@@ -223,7 +235,15 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
       ok = ok && ((((uintptr_t)e.a | (uintptr_t)e.b) & 15) == 0) && (((e.lda | e.ldb) & 1) == 0);
     }
     if (ok) {
-      ge_pipe<T, 8, true, true>(acc, t.m, t.n, nsrc, [&](int q) { return ge_src_lds(tab, q); }, cx.lds, &pre, &o);
+      if (sw) {
+        o = outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, (T)1);
+        ge_pipe<T, 8, true, true, false, true>(acc, t.n, t.m, nsrc, [&](int q) { return ge_src_lds(tab, q); },
+                                               cx.lds, &pre, &o);
+        gemm_store<T>(acc, t.n, t.m, o, nullptr, pre);
+        return;
+      }
+      ge_pipe<T, 8, true, true, false, true>(acc, t.m, t.n, nsrc, [&](int q) { return ge_src_lds(tab, q); }, cx.lds,
+                                             &pre, &o);
       done = true;
     }
   }
@@ -554,9 +574,10 @@ __global__ __launch_bounds__(kThreads) void k_dag(DagArgs a) {
           typedef typename Cplx<T>::type C;
           const InstView* iv = a.inst + nt->inst;
           const XSrc x = iv->xsrc[nt->pad1 + q];
+          const bool sw = xupd_swap(nt->m, nt->n);
           GeSrc<T> e;
-          e.a = reinterpret_cast<const C*>(iv->LD) + x.a_off;
-          e.b = reinterpret_cast<const C*>(iv->L) + x.b_off;
+          e.a = reinterpret_cast<const C*>(iv->LD) + (sw ? x.b_off : x.a_off);
+          e.b = reinterpret_cast<const C*>(iv->L) + (sw ? x.a_off : x.b_off);
           e.lda = e.ldb = x.lda;
           e.k = x.k;
           e.pad = 0;

@@ -470,7 +470,11 @@ __device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Ou
 // Starts and ends with a barrier.
 // W2: a two-block accumulator width too (n in 17..32), for callers whose n
 // is the right-hand-side count of a solve (the factor keeps three widths).
-template <typename T, int NBMAX, bool PRE, bool TR, bool W2 = false, typename SRC>
+// ALLW: one copy of the slab loop per column-block count (n rounded up to
+// 16, 1..8), so that a tile with a partial last column block issues the
+// products of its own width and not of the next of 1, 4 and 8: the Schur
+// updates, where most of the factor's products are, take it.
+template <typename T, int NBMAX, bool PRE, bool TR, bool W2 = false, bool ALLW = false, typename SRC>
 __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc, const SRC& src, lds_char* lds,
                                         GePre<T>* pre, const Out<T>* po) {
   constexpr int KD = GeDma<T>::KB, NB = GeDma<T>::NBUF, SL = 2 * KD * GE_LDP;
@@ -569,6 +573,19 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
       __syncthreads();
     }
   };
+  if constexpr (ALLW && NBMAX == 8) {
+    switch (nbj) {
+      case 1: run(std::integral_constant<int, 1>()); break;
+      case 2: run(std::integral_constant<int, 2>()); break;
+      case 3: run(std::integral_constant<int, 3>()); break;
+      case 4: run(std::integral_constant<int, 4>()); break;
+      case 5: run(std::integral_constant<int, 5>()); break;
+      case 6: run(std::integral_constant<int, 6>()); break;
+      case 7: run(std::integral_constant<int, 7>()); break;
+      default: run(std::integral_constant<int, 8>()); break;
+    }
+    return;
+  }
   if (NBMAX > 4 && nbj > 4) run(std::integral_constant<int, (NBMAX > 4 ? 8 : 1)>());
   else if (W2 && NBMAX > 1 && nbj == 2) run(std::integral_constant<int, (NBMAX > 1 ? 2 : 1)>());
   else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
