@@ -293,9 +293,21 @@ void d3m_batch_destroy(d3m_batch b);
 d3m_status d3m_factor_bind_static(d3m_plan plan, d3m_precision prec, int32_t nrhs_max, const d3m_options* opt,
                                   d3m_factor* out);
 
-/* Device tuning: time each candidate tile configuration of the GEMM task
- * body on the current device and return the fastest (id, measured GFLOP/s)
- * for the precision. */
+/* Engine measurement (the benchmarked GEMM weight of the paper's Sec. II
+ * scheduling, measured on this device): times the task-body GEMM on every
+ * workgroup of the device along each candidate load path, for the
+ * precision, and writes each candidate's aggregate GFLOP/s (8 flops per
+ * complex multiply-add) to gflops_out[0 .. *ncand - 1] (*ncand = 4):
+ *   0  update tile 128x128x512, the factor's path (direct global->LDS loads
+ *      for complex64, register slabs for complex128);
+ *   1  update tile through register slabs of half the depth;
+ *   2  solve tile 64x64x448 (right-hand-side block shared by all
+ *      workgroups), whole k per wave;
+ *   3  the solve tile with k split over two wave halves, the solve's path.
+ * *best_id is the faster of the update-tile candidates 0 and 1.
+ * dev_scratch: device memory of at least 256*3*128*512 complex elements of
+ * the precision (overwritten); D3M_ERR_WORKSPACE if bytes is smaller.
+ * Synchronizes the device. */
 d3m_status d3m_tune_gemm(d3m_precision prec, void* dev_scratch, size_t bytes, int32_t* best_id,
                          double* gflops_out /* [ncand] or NULL */, int32_t* ncand);
 

@@ -448,9 +448,11 @@ class Batch:
         return Xs
 
 
-def gemm_rate(precision: int = C128) -> float:
-    """Measured aggregate GFLOP/s of the task-body GEMM (256 workgroups, each
-    repeating 128x128x512 complex tile products)."""
+def gemm_candidates(precision: int = C128) -> dict:
+    """Measured aggregate GFLOP/s of the task-body GEMM along each candidate
+    load path (d3m_tune_gemm): {"rates": [update direct/register, update
+    half-depth register, solve whole-k, solve split-k], "best": index of the
+    faster update-tile candidate}."""
     import torch
     es = 16 if precision == C128 else 8
     nbytes = 256 * 3 * 128 * 512 * es
@@ -460,4 +462,10 @@ def gemm_rate(precision: int = C128) -> float:
     g = (ctypes.c_double * 8)()
     _check(lib().d3m_tune_gemm(int(precision), _ptr(buf), nbytes, ctypes.byref(best), g, ctypes.byref(nc)),
            "d3m_tune_gemm")
-    return float(g[0])
+    return {"rates": [float(g[i]) for i in range(nc.value)], "best": int(best.value)}
+
+
+def gemm_rate(precision: int = C128) -> float:
+    """Measured aggregate GFLOP/s of the factor's update-tile GEMM path
+    (256 workgroups, each repeating 128x128x512 complex tile products)."""
+    return gemm_candidates(precision)["rates"][0]

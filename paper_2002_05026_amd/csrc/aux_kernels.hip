@@ -602,43 +602,82 @@ hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, c
 }
 
 // ---------------------------------------------------------------- GEMM timing
-// Repeated 128x128x512 tile products on private buffers, one per workgroup:
-// used by the tuner to measure the task body's per-CU rate.
-template <typename T>
+// Candidate engine paths, timed on repeated products with one private
+// region of 3 * 128 * 512 elements per workgroup:
+//   0: an update tile, 128 x 128 x 512 (A, B private), the path the factor's
+//      updates take (direct loads for complex64, register slabs for
+//      complex128);
+//   1: the same product through register slabs of half the depth (complex64:
+//      register slabs instead of direct loads);
+//   2: a solve tile, 64 x 64 x 448 (A private, B shared by all workgroups,
+//      as the right-hand-side block of a source panel), whole k per wave;
+//   3: the solve tile with k split over the two halves of the workgroup.
+
+template <typename T, int V>
 __global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type* buf, int reps) {
   typedef typename Cplx<T>::type C;
   __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes_dma<T>()];
+  static_assert(ge_lds_bytes<T, GeKB<T>::KB>() <= ge_lds_bytes_dma<T>(), "register path LDS");
   C* base = buf + (int64_t)blockIdx.x * (3 * 128 * 512);
   Acc<T> acc;
   for (int r = 0; r < reps; ++r) {
     acc.zero();
     Opnd<T> A, B;
-    A.p = base;
-    A.ld = 128;
-    A.mode = OP_N;
-    A.i0 = 0;
-    B = A;
-    B.p = base + 128 * 512;
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
     Out<T> o;
-    o.dst = base + 2 * 128 * 512;
-    o.rs = 1;
-    o.cs = 128;
-    o.src = o.dst;
-    o.srs = 1;
-    o.scs = 128;
-    o.alpha = -1;
-    o.beta = 1;
     o.rowdiv = o.coldiv = nullptr;
     o.dst2 = nullptr;
-    gemm_store<T>(acc, 128, 128, o);
+    o.alpha = -1;
+    o.beta = 1;
+    A.mode = OP_N;
+    A.i0 = 0;
+    if constexpr (V <= 1) {
+      A.p = base;
+      A.ld = 128;
+      B = A;
+      B.p = base + 128 * 512;
+      if constexpr (V == 0) gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
+      else gemm_acc<T, 8, GeKB<T>::KB / 2, OP_N, false>(acc, 128, 128, 512, A, nullptr, B, (lds_char*)lds);
+      o.dst = base + 2 * 128 * 512;
+      o.rs = 1;
+      o.cs = 128;
+      o.src = o.dst;
+      o.srs = 1;
+      o.scs = 128;
+      gemm_store<T>(acc, 128, 128, o);
+    } else {
+      A.p = base;
+      A.ld = 64;
+      B = A;
+      B.p = buf + 64 * 512;  // inside workgroup 0's region, after its A
+      gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true, V == 3>(acc, 64, 64, 448, A, nullptr, B,
+                                                                         (lds_char*)lds);
+      o.dst = base + 2 * 128 * 512;
+      o.rs = 64;
+      o.cs = 1;
+      o.src = o.dst;
+      o.srs = 64;
+      o.scs = 1;
+      gemm_store<T>(acc, 64, 64, o);
+    }
   }
 }
 
 hipError_t launch_gemm_bench(int prec, void* buf, int reps, int variant, hipStream_t s) {
-  (void)variant;
-  if (prec == 0) hipLaunchKernelGGL(k_gemm_bench<double>, dim3(256), dim3(kThreads), 0, s, (double2*)buf, reps);
-  else hipLaunchKernelGGL(k_gemm_bench<float>, dim3(256), dim3(kThreads), 0, s, (float2*)buf, reps);
+  auto go = [&](auto tt, auto vv) {
+    typedef decltype(tt) T;
+    constexpr int V = decltype(vv)::value;
+    hipLaunchKernelGGL((k_gemm_bench<T, V>), dim3(256), dim3(kThreads), 0, s, (typename Cplx<T>::type*)buf, reps);
+  };
+  auto pick = [&](auto tt) {
+    switch (variant) {
+      case 0: go(tt, std::integral_constant<int, 0>()); break;
+      case 1: go(tt, std::integral_constant<int, 1>()); break;
+      case 2: go(tt, std::integral_constant<int, 2>()); break;
+      default: go(tt, std::integral_constant<int, 3>()); break;
+    }
+  };
+  if (prec == 0) pick(double());
+  else pick(float());
   return hipGetLastError();
 }
 

@@ -839,19 +839,23 @@ d3m_status d3m_tune_gemm(d3m_precision prec, void* dev_scratch, size_t bytes, in
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipMemset(dev_scratch, 0, need));
-  HIPCHK(launch_gemm_bench(p, dev_scratch, 2, 0, nullptr));
-  HIPCHK(hipEventRecord(e0, nullptr));
-  HIPCHK(launch_gemm_bench(p, dev_scratch, reps, 0, nullptr));
-  HIPCHK(hipEventRecord(e1, nullptr));
-  HIPCHK(hipEventSynchronize(e1));
-  float ms = 0;
-  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  double rate[kBenchCands];
+  for (int v = 0; v < kBenchCands; ++v) {
+    HIPCHK(launch_gemm_bench(p, dev_scratch, 2, v, nullptr));
+    HIPCHK(hipEventRecord(e0, nullptr));
+    HIPCHK(launch_gemm_bench(p, dev_scratch, reps, v, nullptr));
+    HIPCHK(hipEventRecord(e1, nullptr));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    const double per = v <= 1 ? 8.0 * 128 * 128 * 512 : 8.0 * 64 * 64 * 448;
+    rate[v] = 256.0 * reps * per / (ms * 1e-3) / 1e9;
+    if (gflops_out) gflops_out[v] = rate[v];
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  const double flops = 256.0 * reps * 8.0 * 128 * 128 * 512;
-  if (gflops_out) gflops_out[0] = flops / (ms * 1e-3) / 1e9;
-  *best_id = 0;
-  *ncand = 1;
+  *best_id = rate[1] > rate[0] ? 1 : 0;
+  *ncand = kBenchCands;
   return D3M_OK;
 }
 

@@ -203,7 +203,7 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
   Acc<T, true> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
-  Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1);
+  const Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1);
   GePre<T> pre;
   pre.ok = false;
   auto src = [&](int q) {
@@ -236,10 +236,12 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
     }
     if (ok) {
       if (sw) {
-        o = outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, (T)1);
+        // its own copy of the pipeline and the store: with the strides
+        // fixed at compile time in each, their addressing stays in registers
+        const Out<T> ot = outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, (T)1);
         ge_pipe<T, 8, true, true, false, true>(acc, t.n, t.m, nsrc, [&](int q) { return ge_src_lds(tab, q); },
-                                               cx.lds, &pre, &o);
-        gemm_store<T>(acc, t.n, t.m, o, nullptr, pre);
+                                               cx.lds, &pre, &ot);
+        gemm_store<T>(acc, t.n, t.m, ot, nullptr, pre);
         return;
       }
       ge_pipe<T, 8, true, true, false, true>(acc, t.m, t.n, nsrc, [&](int q) { return ge_src_lds(tab, q); }, cx.lds,
@@ -312,7 +314,7 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
   Acc<T> acc;
   acc.zero();
   if (cx.iv->pivot) {
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, t.k + t.pad0,
+    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true, true>(acc, t.m, nc, t.k + t.pad0,
                                                                opn<T>(cx.Gi + t.a_off, t.lda), nullptr,
                                                                opn<T>(cx.W + t.b_off * nr + j0, nr), cx.lds);
     Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
@@ -320,7 +322,7 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
     gemm_store<T>(acc, t.m, nc, o);
     return;
   }
-  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, t.k, opn<T>(cx.Li + t.a_off, t.lda),
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true, true>(acc, t.m, nc, t.k, opn<T>(cx.Li + t.a_off, t.lda),
                                                              nullptr, opn<T>(cx.W + t.b_off * nr + j0, nr),
                                                              cx.lds);
   Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)1, (T)0);
@@ -329,13 +331,12 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
   gemm_store<T>(acc, t.m, nc, o);
 }
 
-// forward update: b_r -= sum over the task's sources of (L_rI D_I) z_I
-// (t.pad0 > 1: the sources are xsrc[t.pad1 ...], else the task's own
-// operands); t.n = 1: the target is an extra accumulator written first
+// forward update: b_r -= (L_rI D_I) z_I; t.n = 1: the target is an extra
+// accumulator written first
 template <typename T>
 __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
-  if (nc <= kMvMaxCols && t.pad0 <= 1) {
+  if (nc <= kMvMaxCols) {
     Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, t.n ? (T)0 : (T)1);
     o.wt = true;
     solve_mv<T, false>(t.m, nc, t.k, cx.LD + t.a_off, t.lda, cx.Z + t.b_off * nr + j0, nr, o, cx.lds);
@@ -343,19 +344,16 @@ __device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
   }
   Acc<T> acc;
   acc.zero();
-  const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
-  for (int q = 0; q < nsrc; ++q) {
-    XSrc x{t.a_off, t.b_off, t.k, t.lda};
-    if (t.pad0 > 1) x = cx.iv->xsrc[t.pad1 + q];
-    gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true>(acc, t.m, nc, x.k, opn<T>(cx.LD + x.a_off, x.lda),
-                                                               nullptr, opn<T>(cx.Z + x.b_off * nr + j0, nr),
-                                                               cx.lds);
-  }
-  // two stores with a constant beta each, so neither has a per-element branch
-  Out<T> o0 = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)0), o1 = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, (T)1);
-  o0.wt = o1.wt = true;
-  if (t.n) gemm_store<T>(acc, t.m, nc, o0);
-  else gemm_store<T>(acc, t.m, nc, o1);
+  // one source (kMergeSolve): a loop over sources around the inlined
+  // pipeline would keep all of its state live across the back edge
+  static_assert(kMergeSolve == 1, "forward updates have one source");
+  gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true, true>(acc, t.m, nc, t.k, opn<T>(cx.LD + t.a_off, t.lda),
+                                                                     nullptr, opn<T>(cx.Z + t.b_off * nr + j0, nr),
+                                                                     cx.lds);
+  // the first update into an extra accumulator overwrites it (beta 0)
+  Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, t.n ? (T)0 : (T)1);
+  o.wt = true;
+  gemm_store<T>(acc, t.m, nc, o);
 }
 
 // b_r += the t.k extra accumulators of tile r (N rows apart) (TK_RED)
@@ -409,7 +407,7 @@ __device__ __noinline__ void task_bupd(const Ctx<T>& cx_, const Task& t_) {
   }
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(acc, t.m, nc, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T),
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true, true>(acc, t.m, nc, t.k, opn<T>(cx.L + t.a_off, t.lda, OP_T),
                                                               nullptr, opn<T>(cx.W + t.b_off * nr + j0, nr), cx.lds);
   Out<T> o = outp<T>(cx.Z + t.c_off * nr + j0, nr, 1, (T)-1, (T)1);
   o.wt = true;
@@ -434,7 +432,7 @@ __device__ __noinline__ void task_btile(const Ctx<T>& cx_, const Task& t_) {
   }
   Acc<T> acc;
   acc.zero();
-  gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true>(
+  gemm_acc<T, 8, GeKB<T>::KB, OP_T, false, false, false, true, true>(
       acc, t.m, nc, t.k + back, opn<T>(cx.Li + t.a_off - back, t.lda, OP_T), nullptr,
       opn<T>(cx.Z + (t.b_off - back) * nr + j0, nr), cx.lds);
   Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)1, (T)0);

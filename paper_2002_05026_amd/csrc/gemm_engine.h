@@ -222,9 +222,12 @@ template <typename T, int KB = GeKB<T>::KB> struct Slab {
   uint32_t amask, bmask;
 };
 
+// ks > 0: split k (see gemm_acc's SK): slab rows 64..127 of A and B hold
+// rows 0..63 of the columns ks later, and a half's columns end at ks
+// (first half) or k (second half).
 template <typename T, int KB, int AM>
 __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, const typename Cplx<T>::type* dA,
-                                         const Opnd<T>& B, int m, int n, int k, int p0) {
+                                         const Opnd<T>& B, int m, int n, int k, int p0, int ks = 0) {
   typedef typename Cplx<T>::type C;
   const int tid = threadIdx.x;
   constexpr int NE = Slab<T, KB>::NE, LOG = ge_log2(KB);
@@ -237,9 +240,15 @@ __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, cons
     int i, pp;
     if (amode == OP_T) { pp = e & (KB - 1); i = e >> LOG; }
     else { i = e & (GE_TM - 1); pp = e >> 7; }
-    const int p = p0 + pp;
-    const bool ok = (i < m) & (p < k);
-    const C* src = ok ? op_addr<AM>(A, i, p) : A.p;
+    int ia = i, p = p0 + pp, ke = k;
+    if (ks > 0) {
+      const int h = i >> 6;
+      ia = i & 63;
+      p += h * ks;
+      ke = h ? k : ks;
+    }
+    const bool ok = (ia < m) & (p < ke);
+    const C* src = ok ? op_addr<AM>(A, ia, p) : A.p;
     sl.a[q] = *gptr<T>(src);
     if (dA) sl.d[q] = *gptr<T>(dA + (ok ? p : 0));
     sl.amask |= (ok ? 1u : 0u) << q;
@@ -247,8 +256,14 @@ __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, cons
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = tid + GE_THREADS * q;
-    const int j = e & (GE_TN - 1), p = p0 + (e >> 7);
-    const bool ok = (j < n) & (p < k);
+    int j = e & (GE_TN - 1), p = p0 + (e >> 7), ke = k;
+    if (ks > 0) {
+      const int h = j >> 6;
+      j &= 63;
+      p += h * ks;
+      ke = h ? k : ks;
+    }
+    const bool ok = (j < n) & (p < ke);
     const C* src = ok ? B.p + j + (int64_t)p * B.ld : B.p;
     sl.b[q] = *gptr<T>(src);
     sl.bmask |= (ok ? 1u : 0u) << q;
@@ -458,6 +473,59 @@ template <typename T> struct Out;
 template <typename T>
 __device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Out<T>& o);
 
+// Split k: waves 4..7 formed partial sums over the second k range for the
+// same rows as waves 0..3 (column blocks 0..3); they pass them through LDS
+// to the first half, which adds them, and clear their own accumulators (so
+// that a caller may add further products).  Called right after a barrier
+// that ends the products (LDS free); ends with a barrier.
+template <typename T, bool TR>
+__device__ __forceinline__ void ge_sk_reduce(Acc<T, TR>& acc, lds_char* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if constexpr (sizeof(T) == 4) {
+    D3M_LDS v4f* buf = reinterpret_cast<D3M_LDS v4f*>(lds);
+    if (w >= 4) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        buf[((w - 4) * 12 + b) * 64 + lane] = acc.p1[b];
+        buf[((w - 4) * 12 + 4 + b) * 64 + lane] = acc.p2[b];
+        buf[((w - 4) * 12 + 8 + b) * 64 + lane] = acc.p3[b];
+      }
+    }
+    __syncthreads();
+    if (w < 4) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        acc.p1[b] += buf[(w * 12 + b) * 64 + lane];
+        acc.p2[b] += buf[(w * 12 + 4 + b) * 64 + lane];
+        acc.p3[b] += buf[(w * 12 + 8 + b) * 64 + lane];
+      }
+    } else {
+      acc.zero();
+    }
+  } else {
+    typedef typename V4<T>::type V;
+    D3M_LDS V* buf = reinterpret_cast<D3M_LDS V*>(lds);
+    if (w >= 4) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        buf[((w - 4) * 8 + b) * 64 + lane] = acc.re[b];
+        buf[((w - 4) * 8 + 4 + b) * 64 + lane] = acc.im[b];
+      }
+    }
+    __syncthreads();
+    if (w < 4) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        acc.re[b] += buf[(w * 8 + b) * 64 + lane];
+        acc.im[b] += buf[(w * 8 + 4 + b) * 64 + lane];
+      }
+    } else {
+      acc.zero();
+    }
+  }
+  __syncthreads();
+}
+
 // acc += sum_q A_q B_q^T over nsrc sources (src(q) gives them, wave-uniform),
 // all direct-loadable (ge_dma_ok), as one direct-load pipeline over the slabs
 // of all sources: a source boundary costs no refill.  Three LDS buffers:
@@ -474,7 +542,9 @@ __device__ __forceinline__ void ge_preload(GePre<T>& pre, int m, int n, const Ou
 // 16, 1..8), so that a tile with a partial last column block issues the
 // products of its own width and not of the next of 1, 4 and 8: the Schur
 // updates, where most of the factor's products are, take it.
-template <typename T, int NBMAX, bool PRE, bool TR, bool W2 = false, bool ALLW = false, typename SRC>
+// SK: split k for one source with m, n <= 64 (see gemm_acc).
+template <typename T, int NBMAX, bool PRE, bool TR, bool W2 = false, bool ALLW = false, bool SK = false,
+          typename SRC>
 __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc, const SRC& src, lds_char* lds,
                                         GePre<T>* pre, const Out<T>* po) {
   constexpr int KD = GeDma<T>::KB, NB = GeDma<T>::NBUF, SL = 2 * KD * GE_LDP;
@@ -482,7 +552,6 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool rowok = 16 * w < m;
   const int nbj = (n + 15) >> 4;
   wg_sync_global();
   int nsl = 0;
@@ -491,6 +560,14 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
     if (kq > 0) nsl += (kq + KD - 1) / KD;
   }
   if (m <= 0 || n <= 0 || nsl == 0) return;
+  // split k: the first ceil(nsl / 2) slabs go to waves 0..3 (LDS rows and
+  // columns 0..63), the rest to waves 4..7 (64..127), one step loading a
+  // slab of each half
+  const bool split = SK && !PRE && nsrc == 1 && m <= 64 && n <= 64 && nsl > 1;
+  const int ks = split ? (nsl + 1) / 2 * KD : 0;
+  if (split) nsl = (nsl + 1) / 2;
+  const int hw = split ? (w >> 2) : 0;
+  const bool rowok = (split ? 16 * (w & 3) : 16 * w) < m;
   // load and compute cursors: source, first column of the slab, operands
   int ql = 0, pl = 0, qc = 0, pc = 0;
   GeSrc<T> el = src(0), ec = el;
@@ -514,9 +591,9 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
       const int g = wq + 8 * q, op = g / KD, cq = g - op * KD;
       const typename Cplx<T>::type* xp = op ? el.b : el.a;
       const int64_t ld = op ? el.ldb : el.lda;
-      int r = 2 * lane;
+      int r = split ? 2 * (lane & 31) : 2 * lane;
       if (r >= (op ? n : m)) r = 0;
-      gp[q] = xp + r + (int64_t)cq * ld;
+      gp[q] = xp + r + (int64_t)(cq + (split && lane >= 32 ? ks : 0)) * ld;
       gstep[q] = (int64_t)KD * ld;
     }
   };
@@ -528,12 +605,14 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
     for (int q = 0; q < NW; ++q) {
       const int g = wq + 8 * q, op = g / KD, cq = g - op * KD;
       D3M_LDS cpx<T>* dst = bs + (op * KD + cq) * GE_LDP;
-      const void* a = (full || pl + cq < el.k) ? (const void*)gp[q] : (const void*)(ge_zero_bytes + 16 * lane);
+      // (split: the first half's slabs are all whole)
+      const bool okc = split ? (lane < 32 || ks + pl + cq < el.k) : (full || pl + cq < el.k);
+      const void* a = okc ? (const void*)gp[q] : (const void*)(ge_zero_bytes + 16 * lane);
       __builtin_amdgcn_global_load_lds(a, (D3M_LDS void*)dst, 16, 0, 0);
       gp[q] += gstep[q];
     }
     pl += KD;
-    if (pl >= el.k) {
+    if (pl >= (split ? ks : el.k)) {
       pl = 0;
       do { ++ql; if (ql < nsrc) el = src(ql); } while (ql < nsrc && el.k <= 0);
       if (ql < nsrc) src_start();
@@ -544,8 +623,13 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
     if (rowok) {
       const D3M_LDS cpx<T>* cur = buf0 + (s % NB) * SL;
       const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
-      const D3M_LDS cpx<T>* bp = cur + KD * GE_LDP + lk * GE_LDP + lr;
-      const int kend = __builtin_amdgcn_readfirstlane(ec.k - pc < KD ? ec.k - pc : KD);
+      const D3M_LDS cpx<T>* bp = cur + KD * GE_LDP + lk * GE_LDP + lr + 64 * hw;
+      int ke = ec.k - pc < KD ? ec.k - pc : KD;
+      if (split && hw) {
+        ke = ec.k - ks - pc;
+        ke = ke < 0 ? 0 : (ke > KD ? KD : ke);
+      }
+      const int kend = __builtin_amdgcn_readfirstlane(ke);
       ge_mma<decltype(nbjc)::value>(acc, ap, bp, kend);
     }
     pc += KD;
@@ -571,6 +655,9 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
       slab(nsl - 1, nbjc);
       ge_wait_vm<0>();
       __syncthreads();
+    }
+    if constexpr (SK) {
+      if (split) ge_sk_reduce<T, TR>(acc, lds);
     }
   };
   if constexpr (ALLW && NBMAX == 8) {
@@ -607,8 +694,14 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
 // overlaps them (pre->ok tells the store).  A flag rather than a null test:
 // a null test of a pointer to a local keeps the local out of registers.
 // W2: see ge_pipe.
+// SK: split k when m and n are at most 64 (the solve's tiles): such a tile
+// keeps only waves 0..3 (one per SIMD) busy and half of each slab's rows
+// and columns unused, so waves 4..7 take the second half of the k range in
+// those unused LDS rows and columns, and their partial sums are added at
+// the end (ge_sk_reduce): two waves per SIMD, and half as many slab steps,
+// each loading as many bytes as before.  The sum is formed in two halves.
 template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool PRE = false,
-          bool TR = false, bool W2 = false>
+          bool TR = false, bool W2 = false, bool SK = false>
 __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds,
                          GePre<T>* pre = nullptr, const Out<T>* po = nullptr) {
@@ -616,8 +709,14 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
   D3M_LDS cpx<T>* buf1 = buf0 + 2 * KB * GE_LDP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool rowok = 16 * w < m;
   const int nbj = (n + 15) >> 4;
+  // split k (SK): the first half's columns are [0, ks), a whole number of
+  // slabs; kl is the loop's extent
+  const bool split = SK && m <= 64 && n <= 64 && k > KB;
+  const int ks = split ? ((k + KB - 1) / KB + 1) / 2 * KB : 0;
+  const int kl = split ? ks : k;
+  const int hw = split ? (w >> 2) : 0;
+  const bool rowok = (split ? 16 * (w & 3) : 16 * w) < m;
   // one LDS slab of KBX columns into the accumulator; three widths only
   // (more variants make the allocator copy the accumulator); LDS columns
   // beyond n hold zeros or columns of B that only reach discarded outputs
@@ -628,8 +727,13 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     constexpr int KBX = decltype(kbx)::value, NBJ = decltype(nbjc)::value;
     if (!rowok) return;
     const D3M_LDS cpx<T>* ap = cur + lk * GE_LDP + 16 * w + lr;
-    const D3M_LDS cpx<T>* bp = cur + KBX * GE_LDP + lk * GE_LDP + lr;
-    const int kend = __builtin_amdgcn_readfirstlane(k - p0 < KBX ? k - p0 : KBX);
+    const D3M_LDS cpx<T>* bp = cur + KBX * GE_LDP + lk * GE_LDP + lr + 64 * hw;
+    int ke = k - p0 < KBX ? k - p0 : KBX;
+    if (split) {
+      ke = hw ? k - ks - p0 : ks - p0;
+      ke = ke < 0 ? 0 : (ke > KBX ? KBX : ke);
+    }
+    const int kend = __builtin_amdgcn_readfirstlane(ke);
     ge_mma<NBJ>(acc, ap, bp, kend);
   };
   if constexpr (DMA && AM == OP_N && sizeof(cpx<T>) == 8) {
@@ -639,7 +743,7 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
         e.a = A.p; e.b = B.p; e.lda = A.ld; e.ldb = B.ld; e.k = k; e.pad = 0;
         return e;
       };
-      ge_pipe<T, NBMAX, PRE, TR, W2>(acc, m, n, 1, one, lds, pre, po);
+      ge_pipe<T, NBMAX, PRE, TR, W2, false, SK>(acc, m, n, 1, one, lds, pre, po);
       return;
     }
   }
@@ -654,23 +758,23 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     // loaded into the register slab that held s+1 (sb for even s, sa for odd
     // s): each load has two slabs of products to arrive; one barrier per slab
     Slab<T, KB> sa, sb;
-    ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 0);
-    if (KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, KB);
+    ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 0, ks);
+    if (KB < kl) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, KB, ks);
     ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-    if (2 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 2 * KB);
+    if (2 * KB < kl) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 2 * KB, ks);
     __syncthreads();
-    for (int p0 = 0; p0 < k; p0 += 2 * KB) {
+    for (int p0 = 0; p0 < kl; p0 += 2 * KB) {
       mma(buf0, p0, kbc(), nbjc);
-      if (p0 + KB < k) {
+      if (p0 + KB < kl) {
         ge_stash<T, KB, AM>(sb, A.mode, scaled, buf1, buf1 + KB * GE_LDP);
-        if (p0 + 3 * KB < k) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, p0 + 3 * KB);
+        if (p0 + 3 * KB < kl) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, p0 + 3 * KB, ks);
       }
       __syncthreads();
-      if (p0 + KB >= k) break;
+      if (p0 + KB >= kl) break;
       mma(buf1, p0 + KB, kbc(), nbjc);
-      if (p0 + 2 * KB < k) {
+      if (p0 + 2 * KB < kl) {
         ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-        if (p0 + 4 * KB < k) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, p0 + 4 * KB);
+        if (p0 + 4 * KB < kl) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, p0 + 4 * KB, ks);
       }
       __syncthreads();
     }
@@ -679,18 +783,18 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     // s & 1; while slab s is multiplied, slab s+1 is written to the other
     // buffer and slab s+2 is loaded into registers; one barrier per slab
     Slab<T, KB> sl;
-    ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, 0);
+    ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, 0, ks);
     ge_stash<T, KB, AM>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-    if (KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, KB);
+    if (KB < kl) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, KB, ks);
     __syncthreads();
     int s = 0;
-    for (int p0 = 0; p0 < k; p0 += KB, ++s) {
+    for (int p0 = 0; p0 < kl; p0 += KB, ++s) {
       D3M_LDS cpx<T>* cur = (s & 1) ? buf1 : buf0;
       D3M_LDS cpx<T>* nxt = (s & 1) ? buf0 : buf1;
       mma(cur, p0, kbc(), nbjc);
-      if (p0 + KB < k) {
+      if (p0 + KB < kl) {
         ge_stash<T, KB, AM>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
-        if (p0 + 2 * KB < k) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, p0 + 2 * KB);
+        if (p0 + 2 * KB < kl) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, p0 + 2 * KB, ks);
       }
       __syncthreads();
     }
@@ -700,6 +804,9 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
   else if (W2 && NBMAX > 1 && nbj == 2) run(std::integral_constant<int, (NBMAX > 1 ? 2 : 1)>());
   else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
   else run(std::integral_constant<int, 1>());
+  if constexpr (SK) {
+    if (split) ge_sk_reduce<T, TR>(acc, lds);
+  }
 }
 
 template <typename T> __device__ __forceinline__ cpx<T> cpx_div(cpx<T> a, cpx<T> b) {

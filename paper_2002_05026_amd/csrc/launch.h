@@ -143,6 +143,7 @@ hipError_t launch_batch_perm_out(BatchIrDev* tab, int n, int prec, int64_t maxto
 hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, const void* A, int64_t lda,
                              const void* d, const void* B, int64_t ldb, void* C, int64_t ldc, double alpha,
                              double beta, hipStream_t s);
+constexpr int kBenchCands = 4;  // engine paths launch_gemm_bench times (see k_gemm_bench)
 hipError_t launch_gemm_bench(int prec, void* buf, int reps, int variant, hipStream_t s);
 
 }  // namespace d3m
