@@ -609,8 +609,10 @@ hipError_t launch_debug_gemm(int prec, int m, int n, int k, int amode, int i0, c
 //      complex128);
 //   1: the same product through register slabs of half the depth (complex64:
 //      register slabs instead of direct loads);
-//   2: a solve tile, 64 x 64 x 448 (A private, B shared by all workgroups,
-//      as the right-hand-side block of a source panel), whole k per wave;
+//   2: a solve tile, 64 x 64 x 448 (B shared by all workgroups, as the
+//      right-hand-side block of a source panel; A one of five private tiles
+//      in turn, together larger than the last-level cache, so that A
+//      streams from HBM as the factor does in a solve), whole k per wave;
 //   3: the solve tile with k split over the two halves of the workgroup.
 
 template <typename T, int V>
@@ -645,13 +647,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bench(typename Cplx<T>::type*
       o.scs = 128;
       gemm_store<T>(acc, 128, 128, o);
     } else {
-      A.p = base;
+      // region: A tiles [0, 5 * 64 * 448), C, then (workgroup 0's) B
+      constexpr int kA = 64 * 448;
+      A.p = base + (r % 5) * kA;
       A.ld = 64;
       B = A;
-      B.p = buf + 64 * 512;  // inside workgroup 0's region, after its A
+      B.p = buf + 5 * kA + 64 * 64;
       gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, false, true, V == 3>(acc, 64, 64, 448, A, nullptr, B,
                                                                          (lds_char*)lds);
-      o.dst = base + 2 * 128 * 512;
+      o.dst = base + 5 * kA;
       o.rs = 64;
       o.cs = 1;
       o.src = o.dst;

@@ -334,7 +334,9 @@ __device__ __noinline__ void task_ftile(const Ctx<T>& cx_, const Task& t_) {
 // forward update: b_r -= (L_rI D_I) z_I; t.n = 1: the target is an extra
 // accumulator written first
 template <typename T>
-__device__ __noinline__ void task_fupd(const Ctx<T>& cx, const Task& t) {
+__device__ __noinline__ void task_fupd(const Ctx<T>& cx_, const Task& t_) {
+  const Ctx<T> cx = uniform_ctx(cx_);
+  const Task t = uniform_task(t_);
   const int nr = cx.nrhs, nc = cx.ncols, j0 = cx.j0;
   if (nc <= kMvMaxCols) {
     Out<T> o = outp<T>(cx.W + t.c_off * nr + j0, nr, 1, (T)-1, t.n ? (T)0 : (T)1);
