@@ -180,7 +180,7 @@ __device__ __noinline__ void task_trsm(const Ctx<T>& cx_, const Task& t_) {
   gemm_store<T>(acc, t.m, t.n, o, cx.lds);
 }
 
-// Whether a complex64 Schur update of an m x n tile is formed as its
+// Whether a Schur update of an m x n tile is formed as its
 // transpose, C^T -= (L_sI D_I) L_rI^T.  The engine gives each wave 16 rows
 // (two waves per SIMD, so more than 4 row blocks cost two) and issues the
 // products of the accumulator's column blocks, so a tile with fewer row
@@ -249,12 +249,42 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
       done = true;
     }
   }
-  if (!done)
+  if constexpr (sizeof(T) == 8) {
+    // complex128: register slabs, one source at a time; one copy of the
+    // source loop per column-block count, so that a tile with a partial last
+    // column block issues the products of its own width, and the transpose
+    // formed where that issues fewer (as on the direct-load path)
+    const bool sw = xupd_swap(t.m, t.n);
+    const int mm = sw ? t.n : t.m, nn = sw ? t.m : t.n;
+    auto srcs = [&](auto wc) {
+      for (int q = 0; q < nsrc; ++q) {
+        const XSrc x = src(q);
+        gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, true, false, false, decltype(wc)::value>(
+            acc, mm, nn, x.k, opn<T>(cx.LD + (sw ? x.b_off : x.a_off), x.lda), nullptr,
+            opn<T>(cx.L + (sw ? x.a_off : x.b_off), x.lda), cx.lds);
+      }
+    };
+    switch ((nn + 15) >> 4) {
+      case 1: srcs(std::integral_constant<int, 1>()); break;
+      case 2: srcs(std::integral_constant<int, 2>()); break;
+      case 3: srcs(std::integral_constant<int, 3>()); break;
+      case 4: srcs(std::integral_constant<int, 4>()); break;
+      case 5: srcs(std::integral_constant<int, 5>()); break;
+      case 6: srcs(std::integral_constant<int, 6>()); break;
+      case 7: srcs(std::integral_constant<int, 7>()); break;
+      default: srcs(std::integral_constant<int, 8>()); break;
+    }
+    if (sw) {
+      gemm_store<T>(acc, t.n, t.m, outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, (T)1), nullptr, pre);
+      return;
+    }
+  } else if (!done) {
     for (int q = 0; q < nsrc; ++q) {
       const XSrc x = src(q);
       gemm_acc<T, 8, GeKB<T>::KB, OP_N, true>(acc, t.m, t.n, x.k, opn<T>(cx.LD + x.a_off, x.lda), nullptr,
                                           opn<T>(cx.L + x.b_off, x.lda), cx.lds);
     }
+  }
   gemm_store<T>(acc, t.m, t.n, o, nullptr, pre);
 }
 

@@ -694,6 +694,10 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
 // overlaps them (pre->ok tells the store).  A flag rather than a null test:
 // a null test of a pointer to a local keeps the local out of registers.
 // W2: see ge_pipe.
+// FIXW > 0: the accumulator width is exactly FIXW column blocks (the caller
+// picked it from n, 16 (FIXW - 1) < n <= 16 FIXW): a caller that loops over
+// several products into one accumulator switches on the width once, outside
+// its loop, so that each loop holds a single slab loop.
 // SK: split k when m and n are at most 64 (the solve's tiles): such a tile
 // keeps only waves 0..3 (one per SIMD) busy and half of each slab's rows
 // and columns unused, so waves 4..7 take the second half of the k range in
@@ -701,7 +705,7 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
 // the end (ge_sk_reduce): two waves per SIMD, and half as many slab steps,
 // each loading as many bytes as before.  The sum is formed in two halves.
 template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool PRE = false,
-          bool TR = false, bool W2 = false, bool SK = false>
+          bool TR = false, bool W2 = false, bool SK = false, int FIXW = 0>
 __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
                          const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds,
                          GePre<T>* pre = nullptr, const Out<T>* po = nullptr) {
@@ -800,7 +804,8 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     }
   }
   };
-  if (NBMAX > 4 && nbj > 4) run(std::integral_constant<int, (NBMAX > 4 ? 8 : 1)>());
+  if constexpr (FIXW > 0) run(std::integral_constant<int, FIXW>());
+  else if (NBMAX > 4 && nbj > 4) run(std::integral_constant<int, (NBMAX > 4 ? 8 : 1)>());
   else if (W2 && NBMAX > 1 && nbj == 2) run(std::integral_constant<int, (NBMAX > 1 ? 2 : 1)>());
   else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
   else run(std::integral_constant<int, 1>());
