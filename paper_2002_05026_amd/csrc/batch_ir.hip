@@ -10,6 +10,7 @@
 #include "d3m_internal.h"
 #include "gemm_engine.h"
 #include "ir_parts.h"
+#include "setup_parts.h"
 #include "launch.h"
 
 namespace d3m {
@@ -24,6 +25,33 @@ __global__ void k_batch_user(BatchIrDev* tab, BatchUserArgs u) {
   t.B = (const double2*)u.B[i];
   t.X = (double2*)u.X[i];
   t.ld = u.ld[i];
+}
+
+// grid (workgroups per instance, instances)
+__global__ void k_batch_prepare(const BatchIrDev* tab) {
+  const BatchIrDev& t = tab[blockIdx.y];
+  prepare_part(t.status, t.growth, t.npanel, t.ctrl, t.tol, t.max_iter, blockIdx.x * blockDim.x + threadIdx.x,
+               gridDim.x * blockDim.x);
+}
+
+// grid (32, blocks, instances)
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_scatter(const BatchIrDev* tab) {
+  const BatchIrDev& t = tab[blockIdx.z];
+  if ((int)blockIdx.y >= t.nkp + t.nfill) return;
+  scatter_part<T>(t.K, (typename Cplx<T>::type*)t.L, t.kp, t.nkp, t.fills, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+// grid (row tiles, instances)
+__global__ __launch_bounds__(512) void k_batch_knorm(const BatchIrDev* tab) {
+  const BatchIrDev& t = tab[blockIdx.y];
+  if ((int)blockIdx.x >= t.nrt) return;
+  knorm_part(t.K, t.uv, t.rt[blockIdx.x], t.ctrl);
+}
+
+__global__ void k_batch_flags(const BatchIrDev* tab, int n, const int32_t* src) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *tab[i].flag = *src;
 }
 
 // ir reset and zeroed column maxima (one block per instance)
@@ -120,6 +148,21 @@ hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const
     }
     hipLaunchKernelGGL(k_batch_user, dim3(1), dim3(64), 0, s, tab, u);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int maxnb, int maxnrt, int maxpanel, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_prepare, dim3(std::max(1, (maxpanel + 255) / 256), n), dim3(256), 0, s, tab);
+  if (maxnb > 0) {
+    if (prec == 0) hipLaunchKernelGGL(k_batch_scatter<double>, dim3(32, maxnb, n), dim3(256), 0, s, tab);
+    else hipLaunchKernelGGL(k_batch_scatter<float>, dim3(32, maxnb, n), dim3(256), 0, s, tab);
+  }
+  if (maxnrt > 0) hipLaunchKernelGGL(k_batch_knorm, dim3(maxnrt, n), dim3(512), 0, s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_flags(BatchIrDev* tab, int n, const int32_t* src, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_flags, dim3((n + 63) / 64), dim3(64), 0, s, tab, n, src);
   return hipGetLastError();
 }
 

@@ -896,6 +896,7 @@ struct d3m_batch_s {
   int prec = 0;
   int nworkers = 256;
   int maxnrt = 1, maxnrhs = 1;
+  int maxnb = 0, maxpanel = 1;  // largest scatter block count and panel count of an instance
   int64_t maxtot = 1;  // largest N * nrhs of an instance
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
@@ -986,6 +987,17 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
     t.nrhs = fi->nrhs_max;
     t.tol = fi->opt.tol;
     t.max_iter = fi->opt.max_iter;
+    t.L = fi->ws + fi->lay.L;
+    t.kp = fi->at<KPlaceDev>(fi->lay.kp);
+    t.fills = fi->at<KPlaceDev>(fi->lay.fills);
+    t.nkp = (int32_t)fi->tab.kp.size();
+    t.nfill = (int32_t)fi->tab.fills.size();
+    t.status = fi->at<int32_t>(fi->lay.status);
+    t.growth = fi->at<float>(fi->lay.growth);
+    t.flag = fi->at<int32_t>(fi->lay.flags) + 1;
+    t.npanel = fi->plan->p.nb;
+    b->maxnb = std::max(b->maxnb, (int)(t.nkp + t.nfill));
+    b->maxpanel = std::max(b->maxpanel, (int)t.npanel);
     b->maxnrt = std::max(b->maxnrt, (int)t.nrt);
     b->maxnrhs = std::max(b->maxnrhs, (int)t.nrhs);
     b->maxtot = std::max<int64_t>(b->maxtot, fi->plan->p.N * t.nrhs);
@@ -1017,23 +1029,16 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
     if (!K[i] || !B[i] || !X[i] || nrhs[i] != f->nrhs_max || ld[i] < f->plan->p.N) return D3M_ERR_ARG;
     if (stale(f)) return D3M_ERR_STATE;
   }
-  // scatter/convert and ||K|| per instance, then one persistent factor launch
-  for (int i = 0; i < n; ++i) {
-    d3m_factor_s* f = b->f[i];
-    const PlanImpl& p = f->plan->p;
-    HIPCHK(launch_prepare(f->at<int32_t>(f->lay.status), f->at<float>(f->lay.growth), p.nb, f->ctrl(), f->opt.tol,
-                          f->opt.max_iter, s));
-    HIPCHK(launch_scatter(K[i], f->ws + f->lay.L, f->at<KPlaceDev>(f->lay.kp), (int)f->tab.kp.size(),
-                          f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->prec, s));
-    HIPCHK(launch_knorm(K[i], f->uv(), f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), f->ctrl(), s));
-  }
-  d3m_status st = batch_dag(b, false, nullptr, s);
-  if (st) return st;
-  for (int i = 0; i < n; ++i)
-    HIPCHK(launch_copy_flag(b->at<int32_t>(b->lay.flags) + 1, b->f[i]->at<int32_t>(b->f[i]->lay.flags) + 1, s));
-  // the refinement bookkeeping of all instances: one launch per kind and step
+  // the user's pointers into the instance table, then state reset,
+  // scatter/convert and ||K|| of all instances (a launch each) and one
+  // persistent factor launch
   BatchIrDev* tab = b->at<BatchIrDev>(b->lay.bir);
   HIPCHK(launch_batch_user(tab, n, K, B, X, ld, s));
+  HIPCHK(launch_batch_setup(tab, n, b->prec, b->maxnb, b->maxnrt, b->maxpanel, s));
+  d3m_status st = batch_dag(b, false, nullptr, s);
+  if (st) return st;
+  HIPCHK(launch_batch_flags(tab, n, b->at<int32_t>(b->lay.flags) + 1, s));
+  // the refinement bookkeeping of all instances: one launch per kind and step
   HIPCHK(launch_batch_begin(tab, n, b->prec, b->maxtot, s));
   st = batch_dag(b, true, nullptr, s);
   if (st) return st;

@@ -98,7 +98,6 @@ hipError_t launch_axpy_up(const void* W32, void* X64, int64_t n, const int32_t* 
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 hipError_t launch_dk(const void* Lam, const void* X, int64_t ld, int nrhs, void* dK, const UserView& uv,
                      const DkTaskDev* dt, int ndt, int stored, hipStream_t s);
-hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t s);
 hipError_t launch_all_stop(IrCtrl* const* ctrls, int n, int32_t* out, hipStream_t s);
 
 // One instance of a batch, as the batched refinement kernels see it: the
@@ -121,7 +120,15 @@ struct BatchIrDev {
   const RTaskDev* rt;
   int32_t nrt, nrhs;
   double tol;
-  int32_t max_iter, pad;
+  // set-up of the factorization (state reset, scatter, ||K||)
+  void* L;                      // factor storage (precision of the batch)
+  const KPlaceDev* kp;
+  const KPlaceDev* fills;
+  int32_t nkp, nfill;
+  int32_t* status;
+  float* growth;
+  int32_t* flag;                // the instance's factor-status flag (copy of the batch's)
+  int32_t npanel, max_iter;
 };
 constexpr int kBatchUserMax = 32;  // instances whose user pointers one launch sets
 struct BatchUserArgs {
@@ -134,6 +141,11 @@ struct BatchUserArgs {
 hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const void* const* B, void* const* X,
                              const int64_t* ld, hipStream_t s);
 hipError_t launch_batch_begin(BatchIrDev* tab, int n, int prec, int64_t maxtot, hipStream_t s);
+// state reset, scatter/convert of K and ||K||_inf of every instance (user K
+// pointers set by launch_batch_user first): three launches
+hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int maxnb, int maxnrt, int maxpanel, hipStream_t s);
+// every instance's factor-status flag = *src
+hipError_t launch_batch_flags(BatchIrDev* tab, int n, const int32_t* src, hipStream_t s);
 hipError_t launch_batch_cvt_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
 hipError_t launch_batch_check(BatchIrDev* tab, int n, int prec, int maxnrt, int maxnrhs, int64_t maxtot,
                               int final_step, hipStream_t s);
