@@ -34,12 +34,19 @@ __global__ void k_batch_prepare(const BatchIrDev* tab) {
                gridDim.x * blockDim.x);
 }
 
-// grid (32, blocks, instances)
+// grid (32, all instances' blocks): block y belongs to the last instance
+// whose first block (sb0, ascending) is at most y
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_scatter(const BatchIrDev* tab) {
-  const BatchIrDev& t = tab[blockIdx.z];
-  if ((int)blockIdx.y >= t.nkp + t.nfill) return;
-  scatter_part<T>(t.K, (typename Cplx<T>::type*)t.L, t.kp, t.nkp, t.fills, blockIdx.y, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_batch_scatter(const BatchIrDev* tab, int n) {
+  const int y = blockIdx.y;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].sb0 <= y) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchIrDev& t = tab[lo];
+  scatter_part<T>(t.K, (typename Cplx<T>::type*)t.L, t.kp, t.nkp, t.fills, y - t.sb0, blockIdx.x, gridDim.x);
 }
 
 // grid (row tiles, instances)
@@ -151,11 +158,11 @@ hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const
   return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int maxnb, int maxnrt, int maxpanel, hipStream_t s) {
+hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int maxnrt, int maxpanel, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_prepare, dim3(std::max(1, (maxpanel + 255) / 256), n), dim3(256), 0, s, tab);
-  if (maxnb > 0) {
-    if (prec == 0) hipLaunchKernelGGL(k_batch_scatter<double>, dim3(32, maxnb, n), dim3(256), 0, s, tab);
-    else hipLaunchKernelGGL(k_batch_scatter<float>, dim3(32, maxnb, n), dim3(256), 0, s, tab);
+  if (totnb > 0) {
+    if (prec == 0) hipLaunchKernelGGL(k_batch_scatter<double>, dim3(32, totnb), dim3(256), 0, s, tab, n);
+    else hipLaunchKernelGGL(k_batch_scatter<float>, dim3(32, totnb), dim3(256), 0, s, tab, n);
   }
   if (maxnrt > 0) hipLaunchKernelGGL(k_batch_knorm, dim3(maxnrt, n), dim3(512), 0, s, tab);
   return hipGetLastError();

@@ -896,7 +896,7 @@ struct d3m_batch_s {
   int prec = 0;
   int nworkers = 256;
   int maxnrt = 1, maxnrhs = 1;
-  int maxnb = 0, maxpanel = 1;  // largest scatter block count and panel count of an instance
+  int totnb = 0, maxpanel = 1;  // scatter blocks of all instances, largest panel count of an instance
   int64_t maxtot = 1;  // largest N * nrhs of an instance
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
@@ -996,7 +996,8 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
     t.growth = fi->at<float>(fi->lay.growth);
     t.flag = fi->at<int32_t>(fi->lay.flags) + 1;
     t.npanel = fi->plan->p.nb;
-    b->maxnb = std::max(b->maxnb, (int)(t.nkp + t.nfill));
+    t.sb0 = b->totnb;
+    b->totnb += t.nkp + t.nfill;
     b->maxpanel = std::max(b->maxpanel, (int)t.npanel);
     b->maxnrt = std::max(b->maxnrt, (int)t.nrt);
     b->maxnrhs = std::max(b->maxnrhs, (int)t.nrhs);
@@ -1034,7 +1035,7 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
   // persistent factor launch
   BatchIrDev* tab = b->at<BatchIrDev>(b->lay.bir);
   HIPCHK(launch_batch_user(tab, n, K, B, X, ld, s));
-  HIPCHK(launch_batch_setup(tab, n, b->prec, b->maxnb, b->maxnrt, b->maxpanel, s));
+  HIPCHK(launch_batch_setup(tab, n, b->prec, b->totnb, b->maxnrt, b->maxpanel, s));
   d3m_status st = batch_dag(b, false, nullptr, s);
   if (st) return st;
   HIPCHK(launch_batch_flags(tab, n, b->at<int32_t>(b->lay.flags) + 1, s));

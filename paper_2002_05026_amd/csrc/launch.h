@@ -129,6 +129,7 @@ struct BatchIrDev {
   float* growth;
   int32_t* flag;                // the instance's factor-status flag (copy of the batch's)
   int32_t npanel, max_iter;
+  int32_t sb0, pad;             // the instance's first block in the batch's scatter grid
 };
 constexpr int kBatchUserMax = 32;  // instances whose user pointers one launch sets
 struct BatchUserArgs {
@@ -143,7 +144,7 @@ hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const
 hipError_t launch_batch_begin(BatchIrDev* tab, int n, int prec, int64_t maxtot, hipStream_t s);
 // state reset, scatter/convert of K and ||K||_inf of every instance (user K
 // pointers set by launch_batch_user first): three launches
-hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int maxnb, int maxnrt, int maxpanel, hipStream_t s);
+hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int maxnrt, int maxpanel, hipStream_t s);
 // every instance's factor-status flag = *src
 hipError_t launch_batch_flags(BatchIrDev* tab, int n, const int32_t* src, hipStream_t s);
 hipError_t launch_batch_cvt_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
