@@ -120,15 +120,21 @@ template <typename T> struct Out {
   bool wt = false;                          // store with device-scope atomic stores (write-through)
 };
 
-// One output element.  wt: as two relaxed device-scope atomic stores, which
-// write through to where every XCD sees them; a task whose stores are all of
-// that kind needs no L2 write-back before it releases its successors.
+// One output element.  wt: as relaxed device-scope atomic stores of 64
+// bits (one for complex64, two for complex128), which write through to
+// where every XCD sees them; a task whose stores are all of that kind needs
+// no L2 write-back before it releases its successors.
 template <typename T>
 __device__ __forceinline__ void st_out(D3M_GLB cpx<T>* p, const cpx<T>& v, bool wt) {
   if (wt) {
-    D3M_GLB T* q = (D3M_GLB T*)p;
-    __hip_atomic_store(q, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(q + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (sizeof(T) == 4) {
+      const uint64_t bits = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
+      __hip_atomic_store((D3M_GLB uint64_t*)p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      D3M_GLB uint64_t* q = (D3M_GLB uint64_t*)p;
+      __hip_atomic_store(q, (uint64_t)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(q + 1, (uint64_t)__double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   } else {
     *p = v;
   }

@@ -20,6 +20,7 @@
 """
 from __future__ import annotations
 
+import json
 import sys
 import time
 
@@ -50,8 +51,14 @@ def fp64(args):
     runs = {}
     for nrhs in (int(v) for v in str(getattr(args, "fp64_nrhs", "1,16")).split(",")):
         inst = gen.config_fp64(nrhs=nrhs)
-        tuned = {"config": dict(tune.DEFAULT)} if getattr(args, "no_tune", False) else \
-            tune.tune(inst, d3m.C128, nrhs=nrhs, reps=2, save=False)
+        if getattr(args, "knobs", None):
+            kn = json.loads(args.knobs)
+            kn = kn.get("c128", kn) if ("c64" in kn or "c128" in kn) else kn
+            tuned = {"config": dict(tune.DEFAULT, **kn)}
+        elif getattr(args, "no_tune", False):
+            tuned = {"config": dict(tune.DEFAULT)}
+        else:
+            tuned = tune.tune(inst, d3m.C128, nrhs=nrhs, reps=2, save=False)
         _log(f"fp64 nrhs={nrhs} tuned {tuned}")
         plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, **tuned["config"])
         flops = plan.info["flops_factor"]

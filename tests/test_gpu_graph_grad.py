@@ -198,3 +198,21 @@ def test_tuner_times_every_candidate_and_applies_the_best(tmp_path, monkeypatch)
     f.factorize(torch.from_numpy(inst.K).cuda())
     f.solve(torch.from_numpy(inst.B).cuda())
     assert f.status()["status"] == 0
+
+
+@pytest.mark.parametrize("prec_name", ["C64_IR", "C128"])
+def test_engine_candidates_are_timed_and_the_paths_taken_hold_up(prec_name):
+    # d3m_tune_gemm times four engine paths on every workgroup of the device:
+    # update tile (direct loads or register slabs, and register slabs of half
+    # the depth) and solve tile (whole k or k split over the two wave halves)
+    d3m = _d3m()
+    prec = getattr(d3m, prec_name)
+    c = d3m.gemm_candidates(prec)
+    print(f"[case] engine candidates {prec_name} {c}", flush=True)
+    r = c["rates"]
+    assert len(r) == 4 and all(v > 0 for v in r)
+    assert c["best"] == (1 if r[1] > r[0] else 0)
+    # the paths the task bodies take: candidate 0 for updates, 3 for solve
+    # tiles; each within 10% of the best of its group (a regression guard)
+    assert r[0] >= 0.9 * max(r[0], r[1])
+    assert r[3] >= 0.9 * max(r[2], r[3])
