@@ -39,6 +39,9 @@ struct XSrc {
 // plan's merge option picks the count up to this bound.
 constexpr int kMergeSrc = 16;
 constexpr int kMergeSolve = 1;
+// Forward solve updates from source panels at least this wide are cut into
+// two tasks over column halves of the panel.
+constexpr int kSolveKSplitMin = 256;
 
 // One task, in ticket order.  Offsets are in complex elements, relative to
 // the instance's base pointers (panel storage L, solve vector W).

@@ -846,26 +846,35 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
           const Panel& PJ = p.panels[B.J];
           for (int r = st0[B.J]; r < st0[B.J + 1]; ++r) {
             const int r0 = stl[r].first, sz = stl[r].second;
-            GState::PendF& pf = S.pendf[r];
-            if (pf.src.empty()) {
-              Task u{};
-              u.kind = TK_FUPD | (g << 8);
-              u.panel = I;
-              u.m = sz;
-              u.k = P.n;
-              u.lda = P.H;
-              u.aux = r;
-              u.a_off = P.off + B.prow + r0;                  // rows of (L D)_rI in LD
-              u.b_off = P.prow0;                              // rows of z_I in Z
-              u.c_off = PJ.prow0 + r0;
-              pf.t = u;
-              pf.ac.push_back({0, true});  // the target, set when the slot is known
+            // the update from a wide panel of the last eighth of the order
+            // (the dense top of the tree, whose panels form a chain) is cut
+            // into column halves, two tasks into two accumulators: each link
+            // of the chain waits for half the product
+            const int nh = (P.n >= kSolveKSplitMin && 8 * I >= 7 * nb) ? 2 : 1;
+            const int kh = (P.n / 2) & ~1;  // even: the halves' operand columns stay 16-byte aligned
+            for (int h = 0; h < nh; ++h) {
+              const int k0 = h == 0 ? 0 : kh, k1 = (nh == 1 || h == 1) ? P.n : kh;
+              GState::PendF& pf = S.pendf[r];
+              if (pf.src.empty()) {
+                Task u{};
+                u.kind = TK_FUPD | (g << 8);
+                u.panel = I;
+                u.m = sz;
+                u.k = k1 - k0;
+                u.lda = P.H;
+                u.aux = r;
+                u.a_off = P.off + B.prow + r0 + (int64_t)k0 * P.H;  // rows of (L D)_rI in LD, columns k0..
+                u.b_off = P.prow0 + k0;                             // rows k0.. of z_I in Z
+                u.c_off = PJ.prow0 + r0;
+                pf.t = u;
+                pf.ac.push_back({0, true});  // the target, set when the slot is known
+              }
+              pf.pr.insert(pf.pr.end(), S.ftile[I].begin(), S.ftile[I].end());
+              for (int c = st0[I]; c < st0[I + 1]; ++c) pf.ac.push_back({kZKey | gk | c, false});
+              pf.src.push_back({P.off + B.prow + r0 + (int64_t)k0 * P.H, P.prow0 + k0, k1 - k0, P.H});
+              pf.w += tile_work(sz, wn, k1 - k0) / 5.5e5 + (pf.src.size() > 1 ? 3.0 : 0.0);
+              if ((int)pf.src.size() >= kMergeSolve) emit_fupd(r);
             }
-            pf.pr.insert(pf.pr.end(), S.ftile[I].begin(), S.ftile[I].end());
-            for (int c = st0[I]; c < st0[I + 1]; ++c) pf.ac.push_back({kZKey | gk | c, false});
-            pf.src.push_back({P.off + B.prow + r0, P.prow0, P.n, P.H});
-            pf.w += tile_work(sz, wn, P.n) / 5.5e5 + (pf.src.size() > 1 ? 3.0 : 0.0);
-            if ((int)pf.src.size() >= kMergeSolve) emit_fupd(r);
           }
         }
       }
