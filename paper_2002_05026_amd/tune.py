@@ -9,6 +9,11 @@ GPU task DAGs are chosen by timing the library itself on the device:
 * solve_tile  rows of a solve task                                  -> solve DAG time
 * rhs_groups  column groups of the right-hand sides (grouped DAG)   -> solve DAG time
 
+A batch (tune_batch) is tuned as a batch: every knob by the time of the
+whole merged run (factor, solve and refinement of all instances), since the
+grain that is best for one instance alone (little parallelism) is not the
+best for many merged into one launch.
+
 Coordinate descent in that order: each knob's candidates are timed with the
 best values found so far for the others (factor knobs by the time of
 d3m_factorize, solve knobs by the time of d3m_solve for the caller's number
@@ -125,3 +130,44 @@ def tune(instance, precision: int, nrhs: Optional[int] = None, reps: int = 2, sa
             json.dump(data, fh, indent=1, sort_keys=True)
         os.replace(tmp, path)
     return res
+
+
+def _time_batch(instances, Ks, Bs, precision: int, cfg: dict, reps: int) -> float:
+    """ms of one d3m_batch_run (all instances, this configuration), mean over
+    reps, after one untimed run."""
+    import torch
+
+    import paper_2002_05026_amd as d3m
+    nrhs = int(Bs[0].shape[0])
+    fs = [d3m.Factor(d3m.Plan(i.sizes, i.pairs, grid=i.grid, **cfg), precision, nrhs_max=nrhs) for i in instances]
+    b = d3m.Batch(fs)
+    Xs = [torch.empty_like(B) for B in Bs]
+    b.run(Ks, Bs, Xs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.run(Ks, Bs, Xs)
+    e1.record()
+    torch.cuda.synchronize()
+    bad = [st for st in (f.status() for f in fs) if st["status"] != 0]
+    if bad:
+        raise RuntimeError(f"tuning run failed: {bad[0]}")
+    del b, fs, Xs
+    torch.cuda.empty_cache()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_batch(instances, Ks, Bs, precision: int, reps: int = 2, knobs=KNOBS) -> dict:
+    """Coordinate descent over the knobs, each candidate timed as a whole
+    batch run of `instances` (device K and B given); returns {'config': best,
+    'timings': {knob: {value: ms}}} (not cached: a batch is its own case)."""
+    cfg = dict(DEFAULT)
+    timings = {}
+    for name, cands in knobs:
+        times = {}
+        for v in cands:
+            times[int(v)] = _time_batch(instances, Ks, Bs, precision, dict(cfg, **{name: v}), reps)
+        cfg[name] = min(times, key=times.get)
+        timings[name] = times
+    return {"config": cfg, "timings": timings}
