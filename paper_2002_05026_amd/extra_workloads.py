@@ -105,8 +105,14 @@ def batch(args):
     Bs = [torch.from_numpy(inst.B).cuda() for inst in insts]
     # plan knobs tuned on the batch itself (each candidate timed as a whole
     # merged run), outside the timed region
-    tuned = {"config": dict(tune.DEFAULT), "timings": None} if getattr(args, "no_tune", False) else \
-        tune.tune_batch(insts, Ks, Bs, d3m.C64_IR, reps=1)
+    if getattr(args, "knobs", None):
+        kn = json.loads(args.knobs)
+        kn = kn.get("c64", kn) if ("c64" in kn or "c128" in kn) else kn
+        tuned = {"config": dict(tune.DEFAULT, **kn), "timings": None}
+    elif getattr(args, "no_tune", False):
+        tuned = {"config": dict(tune.DEFAULT), "timings": None}
+    else:
+        tuned = tune.tune_batch(insts, Ks, Bs, d3m.C64_IR, reps=1)
     cfg = tuned["config"]
     _log(f"tuned tile {tuned}")
     fs, Xs, flops = [], [], 0.0
