@@ -228,10 +228,10 @@ template <typename T, int KB = GeKB<T>::KB> struct Slab {
   uint32_t amask, bmask;
 };
 
-// ks > 0: split k (see gemm_acc's SK): slab rows 64..127 of A and B hold
-// rows 0..63 of the columns ks later, and a half's columns end at ks
-// (first half) or k (second half).
-template <typename T, int KB, int AM>
+// SPL: split k (see gemm_acc's SK): slab rows 64..127 of A and B hold rows
+// 0..63 of the columns ks later, and a half's columns end at ks (first
+// half) or k (second half).
+template <typename T, int KB, int AM, bool SPL = false>
 __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, const typename Cplx<T>::type* dA,
                                          const Opnd<T>& B, int m, int n, int k, int p0, int ks = 0) {
   typedef typename Cplx<T>::type C;
@@ -247,7 +247,7 @@ __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, cons
     if (amode == OP_T) { pp = e & (KB - 1); i = e >> LOG; }
     else { i = e & (GE_TM - 1); pp = e >> 7; }
     int ia = i, p = p0 + pp, ke = k;
-    if (ks > 0) {
+    if constexpr (SPL) {
       const int h = i >> 6;
       ia = i & 63;
       p += h * ks;
@@ -263,7 +263,7 @@ __device__ __forceinline__ void ge_fetch(Slab<T, KB>& sl, const Opnd<T>& A, cons
   for (int q = 0; q < NE; ++q) {
     const int e = tid + GE_THREADS * q;
     int j = e & (GE_TN - 1), p = p0 + (e >> 7), ke = k;
-    if (ks > 0) {
+    if constexpr (SPL) {
       const int h = j >> 6;
       j &= 63;
       p += h * ks;
@@ -548,9 +548,10 @@ __device__ __forceinline__ void ge_sk_reduce(Acc<T, TR>& acc, lds_char* lds) {
 // 16, 1..8), so that a tile with a partial last column block issues the
 // products of its own width and not of the next of 1, 4 and 8: the Schur
 // updates, where most of the factor's products are, take it.
-// SK: split k for one source with m, n <= 64 (see gemm_acc).
+// SK: split k; the caller has one source with m, n <= 64 and k above one
+// slab (see gemm_acc).  FIXW > 0: the accumulator width, fixed by the caller.
 template <typename T, int NBMAX, bool PRE, bool TR, bool W2 = false, bool ALLW = false, bool SK = false,
-          typename SRC>
+          int FIXW = 0, typename SRC>
 __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc, const SRC& src, lds_char* lds,
                                         GePre<T>* pre, const Out<T>* po) {
   constexpr int KD = GeDma<T>::KB, NB = GeDma<T>::NBUF, SL = 2 * KD * GE_LDP;
@@ -569,7 +570,8 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
   // split k: the first ceil(nsl / 2) slabs go to waves 0..3 (LDS rows and
   // columns 0..63), the rest to waves 4..7 (64..127), one step loading a
   // slab of each half
-  const bool split = SK && !PRE && nsrc == 1 && m <= 64 && n <= 64 && nsl > 1;
+  static_assert(!(SK && PRE), "split k does not preload the store");
+  constexpr bool split = SK;
   const int ks = split ? (nsl + 1) / 2 * KD : 0;
   if (split) nsl = (nsl + 1) / 2;
   const int hw = split ? (w >> 2) : 0;
@@ -662,10 +664,12 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
       ge_wait_vm<0>();
       __syncthreads();
     }
-    if constexpr (SK) {
-      if (split) ge_sk_reduce<T, TR>(acc, lds);
-    }
+    if constexpr (SK) ge_sk_reduce<T, TR>(acc, lds);
   };
+  if constexpr (FIXW > 0) {
+    run(std::integral_constant<int, FIXW>());
+    return;
+  }
   if constexpr (ALLW && NBMAX == 8) {
     switch (nbj) {
       case 1: run(std::integral_constant<int, 1>()); break;
@@ -710,19 +714,21 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
 // those unused LDS rows and columns, and their partial sums are added at
 // the end (ge_sk_reduce): two waves per SIMD, and half as many slab steps,
 // each loading as many bytes as before.  The sum is formed in two halves.
-template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool PRE = false,
-          bool TR = false, bool W2 = false, bool SK = false, int FIXW = 0>
-__device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
-                         const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds,
-                         GePre<T>* pre = nullptr, const Out<T>* po = nullptr) {
+// The body of gemm_acc; SPL: split k, chosen by gemm_acc (m, n <= 64 and k
+// above one slab), fixed at compile time so that each form is its own code
+// (with the choice left to run time inside, measured 30% slower).
+template <typename T, int NBMAX, int KB, int AM, bool DMA, bool PRE, bool TR, bool W2, bool SPL, int FIXW>
+__device__ __forceinline__ void gemm_acc_body(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
+                                              const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds,
+                                              GePre<T>* pre, const Out<T>* po) {
   D3M_LDS cpx<T>* buf0 = reinterpret_cast<D3M_LDS cpx<T>*>(lds);
   D3M_LDS cpx<T>* buf1 = buf0 + 2 * KB * GE_LDP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int nbj = (n + 15) >> 4;
-  // split k (SK): the first half's columns are [0, ks), a whole number of
+  // split k (SPL): the first half's columns are [0, ks), a whole number of
   // slabs; kl is the loop's extent
-  const bool split = SK && m <= 64 && n <= 64 && k > KB;
+  constexpr bool split = SPL;
   const int ks = split ? ((k + KB - 1) / KB + 1) / 2 * KB : 0;
   const int kl = split ? ks : k;
   const int hw = split ? (w >> 2) : 0;
@@ -753,7 +759,7 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
         e.a = A.p; e.b = B.p; e.lda = A.ld; e.ldb = B.ld; e.k = k; e.pad = 0;
         return e;
       };
-      ge_pipe<T, NBMAX, PRE, TR, W2, false, SK>(acc, m, n, 1, one, lds, pre, po);
+      ge_pipe<T, NBMAX, PRE, TR, W2, false, SPL, FIXW>(acc, m, n, 1, one, lds, pre, po);
       return;
     }
   }
@@ -768,23 +774,23 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     // loaded into the register slab that held s+1 (sb for even s, sa for odd
     // s): each load has two slabs of products to arrive; one barrier per slab
     Slab<T, KB> sa, sb;
-    ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 0, ks);
-    if (KB < kl) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, KB, ks);
+    ge_fetch<T, KB, AM, SPL>(sa, A, dA, B, m, n, k, 0, ks);
+    if (KB < kl) ge_fetch<T, KB, AM, SPL>(sb, A, dA, B, m, n, k, KB, ks);
     ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-    if (2 * KB < kl) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, 2 * KB, ks);
+    if (2 * KB < kl) ge_fetch<T, KB, AM, SPL>(sa, A, dA, B, m, n, k, 2 * KB, ks);
     __syncthreads();
     for (int p0 = 0; p0 < kl; p0 += 2 * KB) {
       mma(buf0, p0, kbc(), nbjc);
       if (p0 + KB < kl) {
         ge_stash<T, KB, AM>(sb, A.mode, scaled, buf1, buf1 + KB * GE_LDP);
-        if (p0 + 3 * KB < kl) ge_fetch<T, KB, AM>(sb, A, dA, B, m, n, k, p0 + 3 * KB, ks);
+        if (p0 + 3 * KB < kl) ge_fetch<T, KB, AM, SPL>(sb, A, dA, B, m, n, k, p0 + 3 * KB, ks);
       }
       __syncthreads();
       if (p0 + KB >= kl) break;
       mma(buf1, p0 + KB, kbc(), nbjc);
       if (p0 + 2 * KB < kl) {
         ge_stash<T, KB, AM>(sa, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-        if (p0 + 4 * KB < kl) ge_fetch<T, KB, AM>(sa, A, dA, B, m, n, k, p0 + 4 * KB, ks);
+        if (p0 + 4 * KB < kl) ge_fetch<T, KB, AM, SPL>(sa, A, dA, B, m, n, k, p0 + 4 * KB, ks);
       }
       __syncthreads();
     }
@@ -793,9 +799,9 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
     // s & 1; while slab s is multiplied, slab s+1 is written to the other
     // buffer and slab s+2 is loaded into registers; one barrier per slab
     Slab<T, KB> sl;
-    ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, 0, ks);
+    ge_fetch<T, KB, AM, SPL>(sl, A, dA, B, m, n, k, 0, ks);
     ge_stash<T, KB, AM>(sl, A.mode, scaled, buf0, buf0 + KB * GE_LDP);
-    if (KB < kl) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, KB, ks);
+    if (KB < kl) ge_fetch<T, KB, AM, SPL>(sl, A, dA, B, m, n, k, KB, ks);
     __syncthreads();
     int s = 0;
     for (int p0 = 0; p0 < kl; p0 += KB, ++s) {
@@ -804,7 +810,7 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
       mma(cur, p0, kbc(), nbjc);
       if (p0 + KB < kl) {
         ge_stash<T, KB, AM>(sl, A.mode, scaled, nxt, nxt + KB * GE_LDP);
-        if (p0 + 2 * KB < kl) ge_fetch<T, KB, AM>(sl, A, dA, B, m, n, k, p0 + 2 * KB, ks);
+        if (p0 + 2 * KB < kl) ge_fetch<T, KB, AM, SPL>(sl, A, dA, B, m, n, k, p0 + 2 * KB, ks);
       }
       __syncthreads();
     }
@@ -815,9 +821,29 @@ __device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, c
   else if (W2 && NBMAX > 1 && nbj == 2) run(std::integral_constant<int, (NBMAX > 1 ? 2 : 1)>());
   else if (NBMAX > 1 && nbj > 1) run(std::integral_constant<int, (NBMAX > 1 ? 4 : 1)>());
   else run(std::integral_constant<int, 1>());
-  if constexpr (SK) {
-    if (split) ge_sk_reduce<T, TR>(acc, lds);
+  if constexpr (SPL) ge_sk_reduce<T, TR>(acc, lds);
+}
+
+template <typename T, int NBMAX = 8, int KB = GeKB<T>::KB, int AM = -1, bool DMA = false, bool PRE = false,
+          bool TR = false, bool W2 = false, bool SK = false, int FIXW = 0>
+__device__ __forceinline__ void gemm_acc(Acc<T, TR>& acc, int m, int n, int k, const Opnd<T>& A,
+                         const typename Cplx<T>::type* dA, const Opnd<T>& B, lds_char* lds,
+                         GePre<T>* pre = nullptr, const Out<T>* po = nullptr) {
+  if constexpr (SK && !PRE && FIXW == 0) {
+    static_assert(GeDma<T>::KB == KB || sizeof(T) == 8, "one split threshold for both load paths");
+    if (m <= 64 && n <= 64 && k > KB) {
+      // each accumulator width its own copy too (n <= 64: 4, 2 with W2, 1)
+      const int nbj = (n + 15) >> 4;
+      if (NBMAX >= 4 && (nbj > 2 || (nbj == 2 && !W2)))
+        gemm_acc_body<T, 4, KB, AM, DMA, PRE, TR, W2, true, (NBMAX >= 4 ? 4 : 1)>(acc, m, n, k, A, dA, B, lds, pre, po);
+      else if (W2 && NBMAX >= 2 && nbj == 2)
+        gemm_acc_body<T, 2, KB, AM, DMA, PRE, TR, W2, true, (NBMAX >= 2 ? 2 : 1)>(acc, m, n, k, A, dA, B, lds, pre, po);
+      else
+        gemm_acc_body<T, 1, KB, AM, DMA, PRE, TR, W2, true, 1>(acc, m, n, k, A, dA, B, lds, pre, po);
+      return;
+    }
   }
+  gemm_acc_body<T, NBMAX, KB, AM, DMA, PRE, TR, W2, false, FIXW>(acc, m, n, k, A, dA, B, lds, pre, po);
 }
 
 template <typename T> __device__ __forceinline__ cpx<T> cpx_div(cpx<T> a, cpx<T> b) {
