@@ -809,7 +809,7 @@ d3m_status d3m_factor_tasks(d3m_factor f, int32_t solve, int32_t* kinds, int32_t
 void d3m_factor_destroy(d3m_factor f) {
   if (!f) return;
   for (int w = 0; w < 2; ++w)
-    for (auto& e : f->ev[w]) hipEventDestroy(e);
+    for (auto& e : f->ev[w]) (void)hipEventDestroy(e);
   delete f;
 }
 
@@ -852,8 +852,8 @@ d3m_status d3m_tune_gemm(d3m_precision prec, void* dev_scratch, size_t bytes, in
     rate[v] = 256.0 * reps * per / (ms * 1e-3) / 1e9;
     if (gflops_out) gflops_out[v] = rate[v];
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *best_id = rate[1] > rate[0] ? 1 : 0;
   *ncand = kBenchCands;
   return D3M_OK;
