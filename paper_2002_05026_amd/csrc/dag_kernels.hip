@@ -256,23 +256,37 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
     // formed where that issues fewer (as on the direct-load path)
     const bool sw = xupd_swap(t.m, t.n);
     const int mm = sw ? t.n : t.m, nn = sw ? t.m : t.n;
-    auto srcs = [&](auto wc) {
+    // A tile of at most 64 x 64 (64-row tiles) splits each source's k over
+    // the two wave halves (both waves of each SIMD busy), chosen here, once,
+    // outside the source loop.
+    auto srcs = [&](auto wc, auto spl) {
       for (int q = 0; q < nsrc; ++q) {
         const XSrc x = src(q);
-        gemm_acc<T, 8, GeKB<T>::KB, OP_N, true, false, true, false, false, decltype(wc)::value>(
+        gemm_acc_body<T, 8, GeKB<T>::KB, OP_N, true, false, true, false, decltype(spl)::value, decltype(wc)::value>(
             acc, mm, nn, x.k, opn<T>(cx.LD + (sw ? x.b_off : x.a_off), x.lda), nullptr,
-            opn<T>(cx.L + (sw ? x.a_off : x.b_off), x.lda), cx.lds);
+            opn<T>(cx.L + (sw ? x.a_off : x.b_off), x.lda), cx.lds, nullptr, nullptr);
       }
     };
-    switch ((nn + 15) >> 4) {
-      case 1: srcs(std::integral_constant<int, 1>()); break;
-      case 2: srcs(std::integral_constant<int, 2>()); break;
-      case 3: srcs(std::integral_constant<int, 3>()); break;
-      case 4: srcs(std::integral_constant<int, 4>()); break;
-      case 5: srcs(std::integral_constant<int, 5>()); break;
-      case 6: srcs(std::integral_constant<int, 6>()); break;
-      case 7: srcs(std::integral_constant<int, 7>()); break;
-      default: srcs(std::integral_constant<int, 8>()); break;
+    using spl_t = std::integral_constant<bool, true>;
+    using spl_f = std::integral_constant<bool, false>;
+    if (mm <= 64 && nn <= 64) {
+      switch ((nn + 15) >> 4) {
+        case 1: srcs(std::integral_constant<int, 1>(), spl_t()); break;
+        case 2: srcs(std::integral_constant<int, 2>(), spl_t()); break;
+        case 3: srcs(std::integral_constant<int, 3>(), spl_t()); break;
+        default: srcs(std::integral_constant<int, 4>(), spl_t()); break;
+      }
+    } else {
+      switch ((nn + 15) >> 4) {
+        case 1: srcs(std::integral_constant<int, 1>(), spl_f()); break;
+        case 2: srcs(std::integral_constant<int, 2>(), spl_f()); break;
+        case 3: srcs(std::integral_constant<int, 3>(), spl_f()); break;
+        case 4: srcs(std::integral_constant<int, 4>(), spl_f()); break;
+        case 5: srcs(std::integral_constant<int, 5>(), spl_f()); break;
+        case 6: srcs(std::integral_constant<int, 6>(), spl_f()); break;
+        case 7: srcs(std::integral_constant<int, 7>(), spl_f()); break;
+        default: srcs(std::integral_constant<int, 8>(), spl_f()); break;
+      }
     }
     if (sw) {
       gemm_store<T>(acc, t.n, t.m, outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, (T)1), nullptr, pre);

@@ -727,9 +727,11 @@ __device__ __forceinline__ void gemm_acc_body(Acc<T, TR>& acc, int m, int n, int
   const int lr = lane & 15, lk = lane >> 4;
   const int nbj = (n + 15) >> 4;
   // split k (SPL): the first half's columns are [0, ks), a whole number of
-  // slabs; kl is the loop's extent
+  // slabs (or all of k when k fits one slab: the second half is then empty);
+  // kl is the loop's extent.  The direct-load path needs k above one slab
+  // (its first half's lanes take every column as valid): gemm_acc checks.
   constexpr bool split = SPL;
-  const int ks = split ? ((k + KB - 1) / KB + 1) / 2 * KB : 0;
+  const int ks = split ? min(((k + KB - 1) / KB + 1) / 2 * KB, k) : 0;
   const int kl = split ? ks : k;
   const int hw = split ? (w >> 2) : 0;
   const bool rowok = (split ? 16 * (w & 3) : 16 * w) < m;
