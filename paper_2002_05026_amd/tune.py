@@ -15,7 +15,8 @@ grain that is best for one instance alone (little parallelism) is not the
 best for many merged into one launch.
 
 Coordinate descent in that order: each knob's candidates are timed with the
-best values found so far for the others (factor knobs by the time of
+best values found so far for the others, and a candidate replaces the
+current value only when more than 0.5% faster (factor knobs by the time of
 d3m_factorize, solve knobs by the time of d3m_solve for the caller's number
 of right-hand sides, HIP events on the stream), and the fastest is kept.  Results are cached as JSON keyed
 by GPU architecture, precision, interface-size bucket and right-hand-side
@@ -102,6 +103,19 @@ def _time(instance, precision: int, nrhs: int, cfg: dict, reps: int) -> tuple:
     return tf / reps, ts / reps
 
 
+# A candidate replaces the current value only when it is faster by more than
+# this fraction: two timings closer than that are run-to-run noise, and a
+# noise-level switch would make the chosen configuration change between runs.
+MARGIN = 0.005
+
+
+def _pick(times: dict, current: int) -> int:
+    best = min(times, key=times.get)
+    if current in times and times[best] > (1.0 - MARGIN) * times[current]:
+        return current
+    return best
+
+
 def tune(instance, precision: int, nrhs: Optional[int] = None, reps: int = 2, save: bool = True,
          knobs=KNOBS) -> dict:
     """Coordinate descent over the knobs on `instance`; returns (and caches)
@@ -116,7 +130,7 @@ def tune(instance, precision: int, nrhs: Optional[int] = None, reps: int = 2, sa
             trial = dict(cfg, **{name: v})
             fac, sol = _time(instance, precision, nrhs, trial, reps)
             times[int(v)] = fac if name in FACTOR_KNOBS else sol
-        cfg[name] = min(times, key=times.get)
+        cfg[name] = _pick(times, cfg[name])
         timings[name] = times
     mean_n = float(instance.sizes.mean())
     res = {"config": cfg, "timings": timings, "key": key(precision, mean_n, nrhs)}
@@ -168,6 +182,6 @@ def tune_batch(instances, Ks, Bs, precision: int, reps: int = 2, knobs=KNOBS) ->
         times = {}
         for v in cands:
             times[int(v)] = _time_batch(instances, Ks, Bs, precision, dict(cfg, **{name: v}), reps)
-        cfg[name] = min(times, key=times.get)
+        cfg[name] = _pick(times, cfg[name])
         timings[name] = times
     return {"config": cfg, "timings": timings}

@@ -180,7 +180,8 @@ def test_batch_instance_equals_single_run_bitwise():
 
 def test_tuner_times_every_candidate_and_applies_the_best(tmp_path, monkeypatch):
     # coordinate descent over the four knobs, three timed candidates each;
-    # the cached choice is the fastest of each knob's timings
+    # the cached choice is the fastest of each knob's timings (up to the
+    # tuner's noise margin)
     d3m = _d3m()
     from paper_2002_05026_amd import tune
     monkeypatch.setenv("D3M_TUNE_CACHE", str(tmp_path / "tune.json"))
@@ -190,7 +191,8 @@ def test_tuner_times_every_candidate_and_applies_the_best(tmp_path, monkeypatch)
     for name, cands in tune.KNOBS:
         t = res["timings"][name]
         assert sorted(t) == sorted(cands) and all(v > 0 for v in t.values())
-        assert res["config"][name] == min(t, key=t.get)
+        # the fastest, or a value within the tuner's noise margin of it
+        assert t[res["config"][name]] * (1 - tune.MARGIN) <= min(t.values())
     assert tune.lookup(d3m.C64_IR, float(inst.sizes.mean()), 32) == res["config"]
     # the tuned plan solves
     plan = d3m.Plan(inst.sizes, inst.pairs, grid=inst.grid, **res["config"])
