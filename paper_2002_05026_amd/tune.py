@@ -111,7 +111,7 @@ MARGIN = 0.005
 
 def _pick(times: dict, current: int) -> int:
     best = min(times, key=times.get)
-    if current in times and times[best] > (1.0 - MARGIN) * times[current]:
+    if current in times and times[best] >= (1.0 - MARGIN) * times[current]:
         return current
     return best
 
