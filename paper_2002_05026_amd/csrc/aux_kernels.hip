@@ -167,6 +167,15 @@ __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const d
   residual_tile(K, X, P, uv, rt[blockIdx.x], nrhs, blockIdx.y, blockIdx.z, (lds_char*)lds);
 }
 
+// The same for at most kResDirectRhs right-hand sides, K read straight into
+// the matrix-core operands (no LDS, so two workgroups per CU).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_residual_direct(const double2* K, const double2* X, double2* P,
+                                                         UserView uv, const RTaskDev* rt, int nrhs,
+                                                         const int32_t* skip) {
+  if (skip && *skip) return;
+  residual_tile_direct(K, X, P, uv, rt[blockIdx.x], nrhs, blockIdx.z);
+}
+
 // R = B - sum_z P_z (internal rows, RHS fastest; B in user layout) and the
 // column maxima of |R| into colmax.
 __global__ void k_residual_fin(const double2* B, int64_t ld, const double2* P, double2* R, double* colmax,
@@ -181,8 +190,12 @@ hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void*
                            const int32_t* skip, hipStream_t s) {
   if (nrhs > 128) return hipErrorInvalidValue;
   const int ny = (nrhs + kResCols - 1) / kResCols;
-  hipLaunchKernelGGL(k_residual, dim3(nrt, ny, kResSplit), dim3(kThreads), 0, s, (const double2*)K,
-                     (const double2*)X64, (double2*)P, uv, rt, nrhs, skip);
+  if (nrhs <= kResDirectRhs)
+    hipLaunchKernelGGL(k_residual_direct, dim3(nrt, 1, kResSplit), dim3(kThreads), 0, s, (const double2*)K,
+                       (const double2*)X64, (double2*)P, uv, rt, nrhs, skip);
+  else
+    hipLaunchKernelGGL(k_residual, dim3(nrt, ny, kResSplit), dim3(kThreads), 0, s, (const double2*)K,
+                       (const double2*)X64, (double2*)P, uv, rt, nrhs, skip);
   const int64_t tot = uv.N * nrhs;
   const int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_residual_fin, dim3(blocks), dim3(256), 0, s, (const double2*)B, ld, (const double2*)P,

@@ -90,11 +90,22 @@ __global__ void k_batch_cvt_up(const BatchIrDev* tab) {
 __global__ __launch_bounds__(kThreads) void k_batch_residual(const BatchIrDev* tab, int ny, int prec) {
   __shared__ __attribute__((aligned(16))) char lds[ge_lds_bytes<double, kResKB>()];
   const BatchIrDev& t = tab[blockIdx.z];
-  if (t.ctrl->stop) return;
+  if (t.ctrl->stop || t.nrhs <= kResDirectRhs) return;  // those take k_batch_residual_direct
   const int by = blockIdx.y % ny, bz = blockIdx.y / ny;
   if ((int)blockIdx.x >= t.nrt || kResCols * by >= t.nrhs) return;
   const double2* X = prec == 0 ? (const double2*)t.W : t.X64;
   residual_tile(t.K, X, t.P64, t.uv, t.rt[blockIdx.x], t.nrhs, by, bz, (lds_char*)lds);
+}
+
+// grid (row tiles, kResSplit, instances); instances of at most kResDirectRhs
+// right-hand sides, as in the single-factor residual
+__global__ __launch_bounds__(kThreads) void k_batch_residual_direct(const BatchIrDev* tab, int prec) {
+  const BatchIrDev& t = tab[blockIdx.z];
+  if (t.ctrl->stop || t.nrhs > kResDirectRhs || (int)blockIdx.x >= t.nrt) return;
+  const double2* X = prec == 0 ? (const double2*)t.W : t.X64;
+  const UserView uv = t.uv;
+  const RTaskDev rt = t.rt[blockIdx.x];
+  residual_tile_direct(t.K, X, t.P64, uv, rt, t.nrhs, blockIdx.y);
 }
 
 __global__ void k_batch_residual_fin(const BatchIrDev* tab) {
@@ -188,11 +199,14 @@ hipError_t launch_batch_cvt_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_batch_check(BatchIrDev* tab, int n, int prec, int maxnrt, int maxnrhs, int64_t maxtot,
-                              int final_step, hipStream_t s) {
+hipError_t launch_batch_check(BatchIrDev* tab, int n, int prec, int maxnrt, int minnrhs, int maxnrhs,
+                              int64_t maxtot, int final_step, hipStream_t s) {
   if (maxnrhs > 128) return hipErrorInvalidValue;
   const int ny = (maxnrhs + kResCols - 1) / kResCols;
-  hipLaunchKernelGGL(k_batch_residual, dim3(maxnrt, ny * kResSplit, n), dim3(kThreads), 0, s, tab, ny, prec);
+  if (minnrhs <= kResDirectRhs)
+    hipLaunchKernelGGL(k_batch_residual_direct, dim3(maxnrt, kResSplit, n), dim3(kThreads), 0, s, tab, prec);
+  if (maxnrhs > kResDirectRhs)
+    hipLaunchKernelGGL(k_batch_residual, dim3(maxnrt, ny * kResSplit, n), dim3(kThreads), 0, s, tab, ny, prec);
   hipLaunchKernelGGL(k_batch_residual_fin, dim3(blocks_for(maxtot, 4096), n), dim3(256), 0, s, tab);
   hipLaunchKernelGGL(k_batch_colmax_x, dim3(blocks_for(maxtot, 2048), n), dim3(256), 0, s, tab, prec);
   hipLaunchKernelGGL(k_batch_ir_check, dim3(n), dim3(64), 0, s, tab, final_step);

@@ -895,7 +895,7 @@ struct d3m_batch_s {
   char* ws = nullptr;
   int prec = 0;
   int nworkers = 256;
-  int maxnrt = 1, maxnrhs = 1;
+  int maxnrt = 1, maxnrhs = 1, minnrhs = 1 << 30;
   int totnb = 0, maxpanel = 1;  // scatter blocks of all instances, largest panel count of an instance
   int64_t maxtot = 1;  // largest N * nrhs of an instance
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
@@ -1001,6 +1001,7 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
     b->maxpanel = std::max(b->maxpanel, (int)t.npanel);
     b->maxnrt = std::max(b->maxnrt, (int)t.nrt);
     b->maxnrhs = std::max(b->maxnrhs, (int)t.nrhs);
+    b->minnrhs = std::min(b->minnrhs, (int)t.nrhs);
     b->maxtot = std::max<int64_t>(b->maxtot, fi->plan->p.N * t.nrhs);
   }
   auto up = [&](size_t off, const void* src, size_t n) {
@@ -1047,7 +1048,7 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
   const int max_iter = b->f[0]->opt.max_iter;
   if (b->prec == 1) HIPCHK(launch_batch_cvt_up(tab, n, b->maxtot, s));
   for (int it = 0; it <= (b->prec == 1 ? max_iter : 0); ++it) {
-    HIPCHK(launch_batch_check(tab, n, b->prec, b->maxnrt, b->maxnrhs, b->maxtot,
+    HIPCHK(launch_batch_check(tab, n, b->prec, b->maxnrt, b->minnrhs, b->maxnrhs, b->maxtot,
                               b->prec == 0 ? 2 : (it == max_iter ? 1 : 0), s));
     if (b->prec == 1 && it < max_iter) HIPCHK(launch_batch_cvt_down(tab, n, b->maxtot, s));
     if (b->prec == 0 || it == max_iter) break;

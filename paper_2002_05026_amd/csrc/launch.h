@@ -148,8 +148,8 @@ hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int m
 // every instance's factor-status flag = *src
 hipError_t launch_batch_flags(BatchIrDev* tab, int n, const int32_t* src, hipStream_t s);
 hipError_t launch_batch_cvt_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
-hipError_t launch_batch_check(BatchIrDev* tab, int n, int prec, int maxnrt, int maxnrhs, int64_t maxtot,
-                              int final_step, hipStream_t s);
+hipError_t launch_batch_check(BatchIrDev* tab, int n, int prec, int maxnrt, int minnrhs, int maxnrhs,
+                              int64_t maxtot, int final_step, hipStream_t s);
 hipError_t launch_batch_cvt_down(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
 hipError_t launch_batch_axpy_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);
 hipError_t launch_batch_perm_out(BatchIrDev* tab, int n, int prec, int64_t maxtot, hipStream_t s);
