@@ -30,19 +30,19 @@ hipError_t launch_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ct
 // ---------------------------------------------------------------- scatter
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter(const double2* K, typename Cplx<T>::type* L, const KPlaceDev* kp,
-                                                 int nkp, const KPlaceDev* fills, int nfill) {
-  scatter_part<T>(K, L, kp, nkp, fills, blockIdx.y, blockIdx.x, gridDim.x);
+                                                 int nkp, const KPlaceDev* fills, double* part) {
+  scatter_part<T>(K, L, kp, nkp, fills, part, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_scatter(const void* K, void* L, const KPlaceDev* kp, int nkp, const KPlaceDev* fills,
-                          int nfill, int prec, hipStream_t s) {
+                          int nfill, double* part, int prec, hipStream_t s) {
   int nb = nkp + nfill;
   if (nb == 0) return hipSuccess;
   dim3 grid(32, nb);
   if (prec == 0)
-    hipLaunchKernelGGL(k_scatter<double>, grid, dim3(256), 0, s, (const double2*)K, (double2*)L, kp, nkp, fills, nfill);
+    hipLaunchKernelGGL(k_scatter<double>, grid, dim3(256), 0, s, (const double2*)K, (double2*)L, kp, nkp, fills, part);
   else
-    hipLaunchKernelGGL(k_scatter<float>, grid, dim3(256), 0, s, (const double2*)K, (float2*)L, kp, nkp, fills, nfill);
+    hipLaunchKernelGGL(k_scatter<float>, grid, dim3(256), 0, s, (const double2*)K, (float2*)L, kp, nkp, fills, part);
   return hipGetLastError();
 }
 
@@ -203,12 +203,11 @@ hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void*
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(512) void k_knorm(const double2* K, UserView uv, const RTaskDev* rt, IrCtrl* ctrl) {
-  knorm_part(K, uv, rt[blockIdx.x], ctrl);
-}
+__global__ __launch_bounds__(256) void k_knorm(KnormDev kn, IrCtrl* ctrl) { knorm_part(kn, ctrl, blockIdx.x); }
 
-hipError_t launch_knorm(const void* K, const UserView& uv, const RTaskDev* rt, int nrt, IrCtrl* ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_knorm, dim3(nrt), dim3(512), 0, s, (const double2*)K, uv, rt, ctrl);
+hipError_t launch_knorm(const KnormDev& kn, IrCtrl* ctrl, hipStream_t s) {
+  if (kn.ngroups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_knorm, dim3((kn.ngroups + 7) / 8), dim3(256), 0, s, kn, ctrl);
   return hipGetLastError();
 }
 

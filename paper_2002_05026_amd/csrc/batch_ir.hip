@@ -46,14 +46,14 @@ __global__ __launch_bounds__(256) void k_batch_scatter(const BatchIrDev* tab, in
     else hi = mid - 1;
   }
   const BatchIrDev& t = tab[lo];
-  scatter_part<T>(t.K, (typename Cplx<T>::type*)t.L, t.kp, t.nkp, t.fills, y - t.sb0, blockIdx.x, gridDim.x);
+  scatter_part<T>(t.K, (typename Cplx<T>::type*)t.L, t.kp, t.nkp, t.fills, t.part, y - t.sb0, blockIdx.x, gridDim.x);
 }
 
-// grid (row tiles, instances)
-__global__ __launch_bounds__(512) void k_batch_knorm(const BatchIrDev* tab) {
+// grid (groups of eight 32-row groups, instances)
+__global__ __launch_bounds__(256) void k_batch_knorm(const BatchIrDev* tab) {
   const BatchIrDev& t = tab[blockIdx.y];
-  if ((int)blockIdx.x >= t.nrt) return;
-  knorm_part(t.K, t.uv, t.rt[blockIdx.x], t.ctrl);
+  if (8 * (int)blockIdx.x >= t.kn.ngroups) return;
+  knorm_part(t.kn, t.ctrl, blockIdx.x);
 }
 
 __global__ void k_batch_flags(const BatchIrDev* tab, int n, const int32_t* src) {
@@ -169,13 +169,13 @@ hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const
   return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int maxnrt, int maxpanel, hipStream_t s) {
+hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int maxkng, int maxpanel, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_prepare, dim3(std::max(1, (maxpanel + 255) / 256), n), dim3(256), 0, s, tab);
   if (totnb > 0) {
-    if (prec == 0) hipLaunchKernelGGL(k_batch_scatter<double>, dim3(32, totnb), dim3(256), 0, s, tab, n);
-    else hipLaunchKernelGGL(k_batch_scatter<float>, dim3(32, totnb), dim3(256), 0, s, tab, n);
+    if (prec == 0) hipLaunchKernelGGL(k_batch_scatter<double>, dim3(4, totnb), dim3(256), 0, s, tab, n);
+    else hipLaunchKernelGGL(k_batch_scatter<float>, dim3(4, totnb), dim3(256), 0, s, tab, n);
   }
-  if (maxnrt > 0) hipLaunchKernelGGL(k_batch_knorm, dim3(maxnrt, n), dim3(512), 0, s, tab);
+  if (maxkng > 0) hipLaunchKernelGGL(k_batch_knorm, dim3((maxkng + 7) / 8, n), dim3(256), 0, s, tab);
   return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ struct Layout {
   size_t L, LD, D, Linv, Ginv, Doff, ipiv, W, Z, X64, R64, P64, norms, ctrl, status, growth, counters, flags;
     size_t ftasks, fsucc, fcnt, stasks, ssucc, scnt, s2tasks, s2succ, s2cnt, sgtasks, sgsucc, sgcnt;
   size_t panels, pblocks, tiles, xsrc, iv;
-  size_t kp, fills, rt, rptr, rblk, rsplit, nI, row0, prow0, perm, dkt, kg;
+  size_t kp, fills, rt, rptr, rblk, rsplit, nI, row0, prow0, perm, dkt, kg, kpart, knptr, knent;
   size_t total;
 };
 
@@ -45,12 +45,39 @@ struct Tables {
   std::vector<int32_t> perm;
   std::vector<DkTaskDev> dkt;
   std::vector<KPlaceDev> kg;  // reduced matrix out of panel storage (partial elimination)
+  // ||K||_inf from the scatter's tile sums: per 32-row group of each
+  // interface, the tile-sum vectors to add (KnormDev); kpart doubles of them
+  std::vector<int32_t> kn_ptr;
+  std::vector<int64_t> kn_ent;
+  int64_t kpart = 0;
 };
 
 void make_tables(const PlanImpl& p, Tables& t) {
-  for (auto& k : p.kplace) t.kp.push_back({k.src, k.dst, k.rows, k.cols, k.ld_dst, k.trans});
-  for (auto& f : p.fills) t.fills.push_back({0, f.dst, f.rows, f.cols, f.ld_dst, 0});
-  for (auto& k : p.kgather) t.kg.push_back({k.src, k.dst, k.rows, k.cols, k.ld_dst, k.trans});
+  // K placements with their tile-sum vectors (64 doubles per 32x32 tile),
+  // and for every 32-row group of every interface the vectors that hold its
+  // rows: row sums of the tiles whose rows are the group's, column sums of
+  // the tiles whose columns are (placement order, then tile order)
+  std::vector<int32_t> gbase(p.nb + 1, 0);
+  for (int i = 0; i < p.nb; ++i) gbase[i + 1] = gbase[i] + (p.n[i] + 31) / 32;
+  std::vector<std::vector<int64_t>> grp(gbase[p.nb]);
+  for (auto& k : p.kplace) {
+    const int tr = (k.rows + 31) / 32, tc = (k.cols + 31) / 32;
+    t.kp.push_back({k.src, k.dst, k.rows, k.cols, k.ld_dst, k.trans, t.kpart, k.ri == k.ci && !k.trans, 0});
+    for (int c = 0; c < tc; ++c)
+      for (int r = 0; r < tr; ++r) {
+        const int64_t v = t.kpart + (int64_t)(r + (int64_t)tr * c) * 64;
+        grp[gbase[k.ri] + r].push_back(v);
+        grp[gbase[k.ci] + c].push_back(v + 32);
+      }
+    t.kpart += (int64_t)tr * tc * 64;
+  }
+  t.kn_ptr.assign(1, 0);
+  for (auto& g : grp) {
+    t.kn_ent.insert(t.kn_ent.end(), g.begin(), g.end());
+    t.kn_ptr.push_back((int32_t)t.kn_ent.size());
+  }
+  for (auto& f : p.fills) t.fills.push_back({0, f.dst, f.rows, f.cols, f.ld_dst, 0, -1, 0, 0});
+  for (auto& k : p.kgather) t.kg.push_back({k.src, k.dst, k.rows, k.cols, k.ld_dst, k.trans, -1, 0, 0});
   t.nI = p.n;
   t.row0.assign(p.nb + 1, 0);
   for (int i = 0; i < p.nb; ++i) t.row0[i + 1] = t.row0[i] + p.n[i];
@@ -159,6 +186,9 @@ Layout make_layout(const PlanImpl& p, const Tables& t, int prec, int nrhs_max) {
   l.perm = take(t.perm.size() * sizeof(int32_t));
   l.dkt = take(t.dkt.size() * sizeof(DkTaskDev));
   l.kg = take(t.kg.size() * sizeof(KPlaceDev));
+  l.kpart = take(t.kpart * sizeof(double));
+  l.knptr = take(t.kn_ptr.size() * sizeof(int32_t));
+  l.knent = take(t.kn_ent.size() * sizeof(int64_t));
   l.total = o;
   return l;
 }
@@ -210,6 +240,15 @@ struct d3m_factor_s {
     u.perm = at<int32_t>(lay.perm);
     u.N = plan->p.N;
     return u;
+  }
+  KnormDev kn() const {
+    KnormDev k;
+    k.part = at<double>(lay.kpart);
+    k.ptr = at<int32_t>(lay.knptr);
+    k.ent = at<int64_t>(lay.knent);
+    k.ngroups = (int32_t)tab.kn_ptr.size() - 1;
+    k.pad = 0;
+    return k;
   }
   IrCtrl* ctrl() const { return at<IrCtrl>(lay.ctrl); }
   int32_t* stop() const { return &ctrl()->stop; }
@@ -487,7 +526,9 @@ d3m_status d3m::bind_factor(d3m_plan plan, d3m_precision prec, void* dev_ws, siz
             up(f->lay.row0, f->tab.row0.data(), f->tab.row0.size() * 8) &&
             up(f->lay.prow0, f->tab.prow0.data(), f->tab.prow0.size() * 8) &&
             up(f->lay.perm, f->tab.perm.data(), f->tab.perm.size() * 4) &&
-            up(f->lay.dkt, f->tab.dkt.data(), f->tab.dkt.size() * sizeof(DkTaskDev));
+            up(f->lay.dkt, f->tab.dkt.data(), f->tab.dkt.size() * sizeof(DkTaskDev)) &&
+            up(f->lay.knptr, f->tab.kn_ptr.data(), f->tab.kn_ptr.size() * 4) &&
+            up(f->lay.knent, f->tab.kn_ent.data(), f->tab.kn_ent.size() * 8);
   if (f->opt.timing) {
     for (int w = 0; w < 2; ++w) {
       f->ev[w].resize(2 * d3m_factor_s::kRing);
@@ -522,10 +563,11 @@ d3m_status d3m_factorize(d3m_factor f, const void* dev_K, d3m_stream stream) {
   HIPCHK(launch_prepare(f->at<int32_t>(f->lay.status), f->at<float>(f->lay.growth), p.nb, f->ctrl(), f->opt.tol,
                         f->opt.max_iter, s));
   HIPCHK(launch_scatter(dev_K, f->ws + f->lay.L, f->at<KPlaceDev>(f->lay.kp), (int)f->tab.kp.size(),
-                        f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->prec, s));
+                        f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->at<double>(f->lay.kpart),
+                        f->prec, s));
+  HIPCHK(launch_knorm(f->kn(), f->ctrl(), s));
   d3m_status st = run_dag(f, 0, f->nrhs_max, nullptr, s);
   if (st != D3M_OK) return st;
-  HIPCHK(launch_knorm(dev_K, f->uv(), f->at<RTaskDev>(f->lay.rt), (int)f->tab.rt.size(), f->ctrl(), s));
   f->last = s;
   f->factored = true;
   return D3M_OK;
@@ -621,7 +663,8 @@ d3m_status d3m_reduce(d3m_factor f, const void* dev_A, const void* dev_F, int64_
   HIPCHK(launch_prepare(f->at<int32_t>(f->lay.status), f->at<float>(f->lay.growth), p.nb, f->ctrl(), f->opt.tol,
                         f->opt.max_iter, s));
   HIPCHK(launch_scatter(dev_A, f->ws + f->lay.L, f->at<KPlaceDev>(f->lay.kp), (int)f->tab.kp.size(),
-                        f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->prec, s));
+                        f->at<KPlaceDev>(f->lay.fills), (int)f->tab.fills.size(), f->at<double>(f->lay.kpart),
+                        f->prec, s));
   d3m_status st = run_dag(f, 0, f->nrhs_max, nullptr, s);
   if (st != D3M_OK) return st;
   if (dev_Kred) {
@@ -895,7 +938,7 @@ struct d3m_batch_s {
   char* ws = nullptr;
   int prec = 0;
   int nworkers = 256;
-  int maxnrt = 1, maxnrhs = 1, minnrhs = 1 << 30;
+  int maxnrt = 1, maxnrhs = 1, minnrhs = 1 << 30, maxkng = 0;
   int totnb = 0, maxpanel = 1;  // scatter blocks of all instances, largest panel count of an instance
   int64_t maxtot = 1;  // largest N * nrhs of an instance
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
@@ -990,6 +1033,8 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
     t.L = fi->ws + fi->lay.L;
     t.kp = fi->at<KPlaceDev>(fi->lay.kp);
     t.fills = fi->at<KPlaceDev>(fi->lay.fills);
+    t.part = fi->at<double>(fi->lay.kpart);
+    t.kn = fi->kn();
     t.nkp = (int32_t)fi->tab.kp.size();
     t.nfill = (int32_t)fi->tab.fills.size();
     t.status = fi->at<int32_t>(fi->lay.status);
@@ -1000,6 +1045,7 @@ d3m_status d3m_batch_create(int32_t ninst, const d3m_factor* f, void* dev_ws, si
     b->totnb += t.nkp + t.nfill;
     b->maxpanel = std::max(b->maxpanel, (int)t.npanel);
     b->maxnrt = std::max(b->maxnrt, (int)t.nrt);
+    b->maxkng = std::max(b->maxkng, (int)t.kn.ngroups);
     b->maxnrhs = std::max(b->maxnrhs, (int)t.nrhs);
     b->minnrhs = std::min(b->minnrhs, (int)t.nrhs);
     b->maxtot = std::max<int64_t>(b->maxtot, fi->plan->p.N * t.nrhs);
@@ -1036,7 +1082,7 @@ d3m_status d3m_batch_run(d3m_batch b, const void* const* K, const void* const* B
   // persistent factor launch
   BatchIrDev* tab = b->at<BatchIrDev>(b->lay.bir);
   HIPCHK(launch_batch_user(tab, n, K, B, X, ld, s));
-  HIPCHK(launch_batch_setup(tab, n, b->prec, b->totnb, b->maxnrt, b->maxpanel, s));
+  HIPCHK(launch_batch_setup(tab, n, b->prec, b->totnb, b->maxkng, b->maxpanel, s));
   d3m_status st = batch_dag(b, false, nullptr, s);
   if (st) return st;
   HIPCHK(launch_batch_flags(tab, n, b->at<int32_t>(b->lay.flags) + 1, s));

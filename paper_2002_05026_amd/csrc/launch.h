@@ -8,9 +8,26 @@
 namespace d3m {
 
 // K block placement into panel storage (src/dst offsets in complex elements).
+// part: where the scatter writes the |k| sums of the placement's 32x32 tiles
+// (tile t = tr + 32-row-tiles * tc: 32 row sums, then 32 column sums, in the
+// destination's coordinates; doubles); diag: a diagonal block, of which only
+// the lower triangle counts (its diagonal in the row sums).  Fills and
+// gathers leave part unused.
 struct KPlaceDev {
   int64_t src, dst;
   int32_t rows, cols, ld_dst, trans;  // trans: dst(r,c) = src[c + r*cols]
+  int64_t part;
+  int32_t diag, pad;
+};
+
+// ||K||_inf from the scatter's tile sums: for every 32-row group of every
+// interface, the partial vectors to add, ent[ptr[g]..ptr[g+1]) (offsets into
+// part, in a fixed order), row l of the group at part[ent + l].
+struct KnormDev {
+  const double* part;
+  const int32_t* ptr;
+  const int64_t* ent;
+  int32_t ngroups, pad;
 };
 
 // Block-row entry for the residual and the norm of K.
@@ -67,9 +84,12 @@ hipError_t launch_reset(int32_t* counters, const int32_t* init, int n, int32_t* 
 
 hipError_t launch_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ctrl, double tol, int max_iter,
                           hipStream_t s);
+// K into panel storage in the factor's precision, fill blocks zeroed, and the
+// |k| sums of every placed tile into part (for launch_knorm)
 hipError_t launch_scatter(const void* K, void* L, const KPlaceDev* kp, int nkp, const KPlaceDev* fills,
-                          int nfill, int prec, hipStream_t s);
-hipError_t launch_knorm(const void* K, const UserView& uv, const RTaskDev* rt, int nrt, IrCtrl* ctrl, hipStream_t s);
+                          int nfill, double* part, int prec, hipStream_t s);
+// ctrl->knorm = max over rows of the sums of the scatter's tile sums
+hipError_t launch_knorm(const KnormDev& kn, IrCtrl* ctrl, hipStream_t s);
 hipError_t launch_perm_in(const void* B, int64_t ld, void* W, int prec, const UserView& uv, int nrhs,
                           const int32_t* skip, hipStream_t s);
 hipError_t launch_perm_out(const void* W, void* X, int64_t ld, const UserView& uv, int nrhs, hipStream_t s);
@@ -125,6 +145,8 @@ struct BatchIrDev {
   const KPlaceDev* kp;
   const KPlaceDev* fills;
   int32_t nkp, nfill;
+  double* part;                 // the scatter's tile sums
+  KnormDev kn;
   int32_t* status;
   float* growth;
   int32_t* flag;                // the instance's factor-status flag (copy of the batch's)
@@ -144,7 +166,7 @@ hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const
 hipError_t launch_batch_begin(BatchIrDev* tab, int n, int prec, int64_t maxtot, hipStream_t s);
 // state reset, scatter/convert of K and ||K||_inf of every instance (user K
 // pointers set by launch_batch_user first): three launches
-hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int maxnrt, int maxpanel, hipStream_t s);
+hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int maxkng, int maxpanel, hipStream_t s);
 // every instance's factor-status flag = *src
 hipError_t launch_batch_flags(BatchIrDev* tab, int n, const int32_t* src, hipStream_t s);
 hipError_t launch_batch_cvt_up(BatchIrDev* tab, int n, int64_t maxtot, hipStream_t s);

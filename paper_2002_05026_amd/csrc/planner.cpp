@@ -431,7 +431,7 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   for (int i = 0; i < nb; ++i) {
     int I = p.pos[i];
     const Panel& P = p.panels[I];
-    p.kplace.push_back({p.koff[i], P.off, P.n, P.n, P.H, 0});
+    p.kplace.push_back({p.koff[i], P.off, P.n, P.n, P.H, 0, i, i});
   }
   std::set<std::pair<int, int>> orig;  // (row panel J, col panel I), J > I
   for (size_t k = 0; k < p.pairs.size(); ++k) {
@@ -439,11 +439,11 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
     int pa = p.pos[a], pb = p.pos[b];
     if (pa > pb) {  // block (a, b) lives in panel b at rows of a: copy as is
       const Panel& P = p.panels[pb];
-      p.kplace.push_back({p.koff[nb + k], P.off + prow_in[pb][pa], p.n[a], p.n[b], P.H, 0});
+      p.kplace.push_back({p.koff[nb + k], P.off + prow_in[pb][pa], p.n[a], p.n[b], P.H, 0, a, b});
       orig.insert({pa, pb});
     } else {        // block (b, a) = K_ab^T lives in panel a at rows of b
       const Panel& P = p.panels[pa];
-      p.kplace.push_back({p.koff[nb + k], P.off + prow_in[pa][pb], p.n[b], p.n[a], P.H, 1});
+      p.kplace.push_back({p.koff[nb + k], P.off + prow_in[pa][pb], p.n[b], p.n[a], P.H, 1, b, a});
       orig.insert({pb, pa});
     }
   }

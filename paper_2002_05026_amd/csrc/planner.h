@@ -48,7 +48,8 @@ struct PlanImpl {
   std::vector<Tile> tiles;
   int64_t L_elems = 0, Linv_elems = 0;
   // K block placement into panels (for the scatter kernel), one per K block
-  struct KPlace { int64_t src, dst; int32_t rows, cols, ld_dst, trans; };
+  // ri, ci: user ids of the interfaces of the destination's rows and columns
+  struct KPlace { int64_t src, dst; int32_t rows, cols, ld_dst, trans, ri = 0, ci = 0; };
   std::vector<KPlace> kplace;                 // K blocks -> panel storage
   struct FillPlace { int64_t dst; int32_t rows, cols, ld_dst; };
   std::vector<FillPlace> fills;               // blocks of L that start at zero

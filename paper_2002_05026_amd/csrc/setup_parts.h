@@ -38,10 +38,14 @@ __device__ __forceinline__ void prepare_part(int32_t* status, float* growth, int
 // Scatter/convert of one block of K into the factor storage: b indexes the
 // K placements first, then the fill blocks (zeroed); 32x32 tiles of a K
 // block (the elements of a fill block) are spread over the bx-th of gx
-// workgroups (256 threads).  Transposed blocks go through LDS.
+// workgroups (256 threads).  Transposed blocks go through LDS.  Every tile
+// also leaves its |k| row and column sums in part (the input of ||K||_inf,
+// so that K is read once for both): the tile goes through LDS and is added
+// up there.
 template <typename T>
 __device__ __forceinline__ void scatter_part(const double2* K, typename Cplx<T>::type* L, const KPlaceDev* kp,
-                                             int nkp, const KPlaceDev* fills, int b, int bx, int gx) {
+                                             int nkp, const KPlaceDev* fills, double* part, int b, int bx,
+                                             int gx) {
   typedef typename Cplx<T>::type C;
   __shared__ double2 tileb[32][33];
   const bool fill = b >= nkp;
@@ -61,6 +65,27 @@ __device__ __forceinline__ void scatter_part(const double2* K, typename Cplx<T>:
   }
   const int tr = (P.rows + 31) / 32, tc = (P.cols + 31) / 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  // |k| sums of the tile in tileb (destination coordinates): threads 0..127
+  // add rows, 128..255 columns, four lanes per row (column) over 8 entries
+  // each, combined as (s0 + s1) + (s2 + s3); a diagonal block counts its
+  // lower triangle, the diagonal in the row sums only
+  auto tile_sums = [&](int t, int r0, int c0) {
+    const int k = (threadIdx.x & 127) >> 2, sub = threadIdx.x & 3;
+    const bool col = threadIdx.x >= 128;
+    double sm = 0;
+#pragma unroll 4
+    for (int j = 8 * sub; j < 8 * sub + 8; ++j) {
+      const int rr = col ? j : k, cc = col ? k : j;
+      const int r = r0 + rr, c = c0 + cc;
+      bool in = r < P.rows && c < P.cols;
+      if (P.diag) in = in && (col ? r > c : r >= c);
+      const double2 v = tileb[rr][cc];
+      sm += in ? sqrt(v.x * v.x + v.y * v.y) : 0.0;
+    }
+    sm += __shfl_xor(sm, 1, 64);
+    sm += __shfl_xor(sm, 2, 64);
+    if (sub == 0) part[P.part + (int64_t)t * 64 + (col ? 32 : 0) + k] = sm;
+  };
   for (int t = bx; t < tr * tc; t += gx) {
     const int r0 = (t % tr) * 32, c0 = (t / tr) * 32;
     if (sizeof(C) == 8 && !P.trans) {
@@ -89,6 +114,11 @@ __device__ __forceinline__ void scatter_part(const double2* K, typename Cplx<T>:
           *reinterpret_cast<float4*>(L + P.dst + r + (int64_t)c * P.ld_dst) = o;
         }
       }
+      __syncthreads();  // the previous tile's sums are done with tileb
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tileb[2 * tp + (q & 1)][cc + 16 * (q >> 1)] = v[q];
+      __syncthreads();
+      tile_sums(t, r0, c0);
     } else if (!P.trans) {
       // the four loads of a thread go out together (unconditional, from a
       // valid address outside the block), then the stores
@@ -109,6 +139,11 @@ __device__ __forceinline__ void scatter_part(const double2* K, typename Cplx<T>:
           L[P.dst + r + (int64_t)c * P.ld_dst] = o;
         }
       }
+      __syncthreads();  // the previous tile's sums are done with tileb
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tileb[tx][ty + 8 * q] = v[q];
+      __syncthreads();
+      tile_sums(t, r0, c0);
     } else {
       // dst(r, c) = src[c + r * cols]: read src rows c contiguous
       __syncthreads();
@@ -155,84 +190,28 @@ __device__ __forceinline__ void scatter_part(const double2* K, typename Cplx<T>:
           }
         }
       }
+      tile_sums(t, r0, c0);  // the in-range entries of tileb are the tile
     }
   }
 }
 
-// ||K||_inf: row sums of |k_ij| of the symmetric K, then the maximum.  One
-// workgroup per row tile.  Every access runs along the stored blocks' unit
-// stride: blocks read by columns (K_IJ, and the lower part of the diagonal
-// block) with lanes over rows, blocks read by rows (K_JI^T, and the upper
-// part of the diagonal block from its lower triangle) with lanes over
-// columns.  Partial sums are combined in a fixed order (deterministic).
-// (workgroup of 512 threads, row tile t)
-__device__ __forceinline__ void knorm_part(const double2* K, const UserView& uv, const RTaskDev t, IrCtrl* ctrl) {
-  const int I = t.I, nI = uv.n[I];
-  __shared__ double part[5][kTileMax];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // s += |K[base + p * stride]| for p = p0, p0 + step, .. < pend, in that
-  // order; eight loads go out together (from a valid address past pend)
-  // and the terms past pend add zero, so the loads stay unconditional
-  auto sum = [&](double& s, int64_t base, int64_t stride, int p0, int pend, int step) {
-    constexpr int U = 8;
-    for (int q = p0; q < pend; q += U * step) {
-      double2 v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int p = q + u * step;
-        v[u] = K[base + (int64_t)(p < pend ? p : p0) * stride];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double a = sqrt(v[u].x * v[u].x + v[u].y * v[u].y);
-        s += (q + u * step < pend) ? a : 0.0;
-      }
-    }
-  };
-  // lanes over rows: thread (row i, group g) sums the columns p = g mod 4
-  {
-    const int i = tid & (kTileMax - 1), g = tid >> 7;
-    double s = 0;
-    if (i < t.sz) {
-      const int gi = t.r0 + i;
-      for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
-        const RBlkDev b = uv.rblk[e];
-        if (b.mode == 2) continue;
-        const int pend = b.mode == 0 ? gi + 1 : uv.n[b.J];
-        sum(s, b.koff + gi, nI, g, pend, 4);
-      }
-    }
-    part[g][i] = s;
-  }
-  // lanes over columns: wave w sums rows w, w + 8, ... of the row-read blocks
-  for (int i = w; i < t.sz; i += 8) {
-    const int gi = t.r0 + i;
-    double s = 0;
-    for (int e = uv.rptr[I]; e < uv.rptr[I + 1]; ++e) {
-      const RBlkDev b = uv.rblk[e];
-      if (b.mode == 1) continue;
-      if (b.mode == 2) {
-        const int nJ = uv.n[b.J];
-        sum(s, b.koff + (int64_t)gi * nJ, 1, lane, nJ, 64);
-      } else {
-        sum(s, b.koff + (int64_t)gi * nI, 1, gi + 1 + lane, nI, 64);  // (gi, p) above the diagonal = (p, gi)
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) part[4][i] = s;
-  }
-  __syncthreads();
-  __shared__ double rmax[8];
+// ||K||_inf: the row sums of |k_ij| of the symmetric K are the sums of the
+// scatter's tile sums over each row's tiles (in the order of kn.ent, so the
+// result does not depend on timing), and the norm is their maximum.  Eight
+// 32-row groups per workgroup of 256 threads, starting at group 8 bx.
+__device__ __forceinline__ void knorm_part(const KnormDev& kn, IrCtrl* ctrl, int bx) {
+  const int g = 8 * bx + (threadIdx.x >> 5), l = threadIdx.x & 31;
   double m = 0;
-  if (tid < t.sz) m = (((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid])) + part[4][tid]);
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
-  if (lane == 0) rmax[w] = m;
-  __syncthreads();
-  if (tid == 0) {
-    double r = 0;
-    for (int q = 0; q < 8; ++q) r = fmax(r, rmax[q]);
-    atomic_max_pos(&ctrl->knorm, r);
+  if (g < kn.ngroups) {
+#pragma unroll 8
+    for (int e = kn.ptr[g]; e < kn.ptr[g + 1]; ++e) m += kn.part[kn.ent[e] + l];
   }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  __shared__ double rmax[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) rmax[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomic_max_pos(&ctrl->knorm, fmax(fmax(rmax[0], rmax[1]), fmax(rmax[2], rmax[3])));
 }
 
 }  // namespace d3m
