@@ -167,13 +167,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(const double2* K, const d
   residual_tile(K, X, P, uv, rt[blockIdx.x], nrhs, blockIdx.y, blockIdx.z, (lds_char*)lds);
 }
 
-// The same for at most kResDirectRhs right-hand sides, K read straight into
-// the matrix-core operands (no LDS, so two workgroups per CU).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_residual_direct(const double2* K, const double2* X, double2* P,
+// The same with K read straight into the matrix-core operands (no LDS):
+// NBJ 16-column blocks of right-hand sides, U k-steps of loads in flight
+template <int NBJ, int U>
+__global__ __launch_bounds__(kThreads) void k_residual_direct(const double2* K, const double2* X, double2* P,
                                                          UserView uv, const RTaskDev* rt, int nrhs,
                                                          const int32_t* skip) {
   if (skip && *skip) return;
-  residual_tile_direct(K, X, P, uv, rt[blockIdx.x], nrhs, blockIdx.z);
+  residual_tile_direct<NBJ, U>(K, X, P, uv, rt[blockIdx.x], nrhs, blockIdx.z);
 }
 
 // R = B - sum_z P_z (internal rows, RHS fastest; B in user layout) and the
@@ -190,9 +191,11 @@ hipError_t launch_residual(const void* K, const void* B, int64_t ld, const void*
                            const int32_t* skip, hipStream_t s) {
   if (nrhs > 128) return hipErrorInvalidValue;
   const int ny = (nrhs + kResCols - 1) / kResCols;
+  // (four blocks of right-hand sides in the direct form measured within 3%
+  // of the LDS form, where the matrix cores rather than latency bound it)
   if (nrhs <= kResDirectRhs)
-    hipLaunchKernelGGL(k_residual_direct, dim3(nrt, 1, kResSplit), dim3(kThreads), 0, s, (const double2*)K,
-                       (const double2*)X64, (double2*)P, uv, rt, nrhs, skip);
+    hipLaunchKernelGGL((k_residual_direct<1, kResDirU>), dim3(nrt, 1, kResSplit), dim3(kThreads), 0, s,
+                       (const double2*)K, (const double2*)X64, (double2*)P, uv, rt, nrhs, skip);
   else
     hipLaunchKernelGGL(k_residual, dim3(nrt, ny, kResSplit), dim3(kThreads), 0, s, (const double2*)K,
                        (const double2*)X64, (double2*)P, uv, rt, nrhs, skip);

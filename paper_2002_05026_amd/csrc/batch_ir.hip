@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_residual_direct(const BatchI
   const double2* X = prec == 0 ? (const double2*)t.W : t.X64;
   const UserView uv = t.uv;
   const RTaskDev rt = t.rt[blockIdx.x];
-  residual_tile_direct(t.K, X, t.P64, uv, rt, t.nrhs, blockIdx.y);
+  residual_tile_direct<1, kResDirU>(t.K, X, t.P64, uv, rt, t.nrhs, blockIdx.y);
 }
 
 __global__ void k_batch_residual_fin(const BatchIrDev* tab) {

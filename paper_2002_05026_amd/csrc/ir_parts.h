@@ -73,23 +73,24 @@ __device__ __forceinline__ void residual_tile(const double2* K, const double2* X
   }
 }
 
-// The same partial products for at most kResDirectRhs right-hand sides, with
-// K streamed from global memory straight into the MFMA operands (no LDS).
-// With one 16-column block of right-hand sides the product does about as
-// many FP64 flops per byte of K as the matrix cores do per byte of HBM, and
-// the LDS-staged form above, one slab of K in flight per workgroup, is then
-// held by load latency instead (measured 2.7 TB/s).  Here each wave owns 16
-// rows of the tile and keeps the loads of the next kResDirU k-steps (4
-// columns each) in flight while it multiplies the current ones; without LDS
-// two workgroups share a CU.  The k index of a lane's operands is
-// 4 s + lk in both A and B, as in the LDS form; columns beyond the block
-// read a clamped address and enter as zeros of A, rows beyond the tile and
+// The same partial products with K streamed from global memory straight into
+// the MFMA operands (no LDS), for at most 16 NBJ right-hand sides.  With one
+// 16-column block of right-hand sides the product does about as many FP64
+// flops per byte of K as the matrix cores do per byte of HBM, and the
+// LDS-staged form above, one slab of K in flight per workgroup, is then held
+// by load latency instead.  Here each wave owns 16 rows of the tile and keeps
+// the loads of the next U k-steps (4 columns each) in flight while it
+// multiplies the current ones.  The k index of a lane's operands is 4 s + lk
+// in both A and B, as in the LDS form; columns beyond the block read a
+// clamped address and enter as zeros of A, rows beyond the tile and
 // right-hand sides beyond nrhs read clamped addresses and are not stored.
+// the direct form is taken for at most kResDirectRhs right-hand sides (one
+// block), with kResDirU k-steps of loads in flight
 constexpr int kResDirectRhs = 16;
 constexpr int kResDirU = 3;
+template <int NBJ, int U>
 __device__ __forceinline__ void residual_tile_direct(const double2* K, const double2* X, double2* P,
                                                      const UserView& uv, const RTaskDev t, int nrhs, int bz) {
-  constexpr int U = kResDirU;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int I = t.I;
@@ -99,14 +100,21 @@ __device__ __forceinline__ void residual_tile_direct(const double2* K, const dou
   if (16 * w >= t.sz) return;  // no barrier in this body
   const int ri = 16 * w + lr;
   const int gi = t.r0 + (ri < t.sz ? ri : t.sz - 1);  // this lane's A row inside interface I
-  const int jc = lr < nrhs ? lr : 0;                  // this lane's B column
-  v4d cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+  int jc[NBJ];                                        // this lane's B columns
+#pragma unroll
+  for (int bj = 0; bj < NBJ; ++bj) jc[bj] = 16 * bj + lr < nrhs ? 16 * bj + lr : 0;
+  v4d cre[NBJ], cim[NBJ];
+#pragma unroll
+  for (int bj = 0; bj < NBJ; ++bj) {
+    cre[bj] = v4d{0, 0, 0, 0};
+    cim[bj] = v4d{0, 0, 0, 0};
+  }
   for (int e = e0; e < e1; ++e) {
     const RBlkDev b = uv.rblk[e];
     const int nJ = uv.n[b.J];
     if (nJ <= 0) continue;
     const D3M_GLB cpx<double>* kb = gptr<double>(K + b.koff);
-    const D3M_GLB cpx<double>* xb = gptr<double>(X + uv.prow0[b.J] * nrhs + jc);
+    const D3M_GLB cpx<double>* xb = gptr<double>(X + uv.prow0[b.J] * nrhs);
     const int ng = (nJ + 4 * U - 1) / (4 * U);  // groups of U k-steps
     // one copy of the loop per operand mode: 1 K_IJ (column-major, rows of
     // I contiguous), 2 K_JI^T, 0 the diagonal block from its lower triangle
@@ -117,28 +125,33 @@ __device__ __forceinline__ void residual_tile_direct(const double2* K, const dou
         if constexpr (MODE == 2) return (int64_t)gi * nJ + p;
         return gi >= p ? gi + (int64_t)p * nI : p + (int64_t)gi * nI;
       };
-      auto fetch = [&](cpx<double>* a, cpx<double>* x, int g) {
+      auto fetch = [&](cpx<double>* a, cpx<double>(*x)[NBJ], int g) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int p = 4 * (g * U + u) + lk;
           const int pc = p < nJ ? p : nJ - 1;
           a[u] = kb[aoff(pc)];
-          x[u] = xb[(int64_t)pc * nrhs];
+#pragma unroll
+          for (int bj = 0; bj < NBJ; ++bj) x[u][bj] = xb[(int64_t)pc * nrhs + jc[bj]];
         }
       };
-      auto mma = [&](const cpx<double>* a, const cpx<double>* x, int g) {
+      auto mma = [&](const cpx<double>* a, const cpx<double>(*x)[NBJ], int g) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (4 * (g * U + u) >= nJ) break;  // uniform
           const bool ok = 4 * (g * U + u) + lk < nJ;
           const double ar = ok ? a[u].x : 0.0, ai = ok ? a[u].y : 0.0;
-          cre = mfma16(ar, x[u].x, cre);
-          cre = mfma16(-ai, x[u].y, cre);
-          cim = mfma16(ar, x[u].y, cim);
-          cim = mfma16(ai, x[u].x, cim);
+#pragma unroll
+          for (int bj = 0; bj < NBJ; ++bj) {
+            cre[bj] = mfma16(ar, x[u][bj].x, cre[bj]);
+            cre[bj] = mfma16(-ai, x[u][bj].y, cre[bj]);
+            cim[bj] = mfma16(ar, x[u][bj].y, cim[bj]);
+            cim[bj] = mfma16(ai, x[u][bj].x, cim[bj]);
+          }
         }
       };
-      cpx<double> a0[U], x0[U], a1[U], x1[U];
+      cpx<double> a0[U], a1[U];
+      cpx<double> x0[U][NBJ], x1[U][NBJ];
       fetch(a0, x0, 0);
       for (int g = 0; g < ng; g += 2) {
         if (g + 1 < ng) fetch(a1, x1, g + 1);
@@ -152,15 +165,18 @@ __device__ __forceinline__ void residual_tile_direct(const double2* K, const dou
     else if (b.mode == 2) blk(std::integral_constant<int, 2>());
     else blk(std::integral_constant<int, 0>());
   }
-  if (lr < nrhs) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 16 * w + acc_row<double>(lk, v);
-      if (i < t.sz) {
-        double2 r;
-        r.x = cre[v];
-        r.y = cim[v];
-        dst[(int64_t)i * nrhs + lr] = r;
+  for (int bj = 0; bj < NBJ; ++bj) {
+    if (16 * bj + lr < nrhs) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + acc_row<double>(lk, v);
+        if (i < t.sz) {
+          double2 r;
+          r.x = cre[bj][v];
+          r.y = cim[bj][v];
+          dst[(int64_t)i * nrhs + 16 * bj + lr] = r;
+        }
       }
     }
   }
