@@ -172,8 +172,8 @@ hipError_t launch_batch_user(BatchIrDev* tab, int n, const void* const* K, const
 hipError_t launch_batch_setup(BatchIrDev* tab, int n, int prec, int totnb, int maxkng, int maxpanel, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_prepare, dim3(std::max(1, (maxpanel + 255) / 256), n), dim3(256), 0, s, tab);
   if (totnb > 0) {
-    if (prec == 0) hipLaunchKernelGGL(k_batch_scatter<double>, dim3(4, totnb), dim3(256), 0, s, tab, n);
-    else hipLaunchKernelGGL(k_batch_scatter<float>, dim3(4, totnb), dim3(256), 0, s, tab, n);
+    if (prec == 0) hipLaunchKernelGGL(k_batch_scatter<double>, dim3(32, totnb), dim3(256), 0, s, tab, n);
+    else hipLaunchKernelGGL(k_batch_scatter<float>, dim3(32, totnb), dim3(256), 0, s, tab, n);
   }
   if (maxkng > 0) hipLaunchKernelGGL(k_batch_knorm, dim3((maxkng + 7) / 8, n), dim3(256), 0, s, tab);
   return hipGetLastError();
