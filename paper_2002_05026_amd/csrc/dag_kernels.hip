@@ -203,7 +203,10 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
   Acc<T, true> acc;
   acc.zero();
   const int nsrc = t.pad0 > 1 ? t.pad0 : 1;
-  const Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, (T)1);
+  // aux bit 1: the first update of a tile of a fill block, which holds no K
+  // entries and is not zeroed beforehand: store the product, add nothing
+  const T beta = (t.aux & 2) ? (T)0 : (T)1;
+  const Out<T> o = outp<T>(cx.L + t.c_off, 1, t.ldc, (T)-1, beta);
   GePre<T> pre;
   pre.ok = false;
   auto src = [&](int q) {
@@ -238,7 +241,7 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
       if (sw) {
         // its own copy of the pipeline and the store: with the strides
         // fixed at compile time in each, their addressing stays in registers
-        const Out<T> ot = outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, (T)1);
+        const Out<T> ot = outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, beta);
         ge_pipe<T, 8, true, true, false, true>(acc, t.n, t.m, nsrc, [&](int q) { return ge_src_lds(tab, q); },
                                                cx.lds, &pre, &ot);
         gemm_store<T>(acc, t.n, t.m, ot, nullptr, pre);
@@ -289,7 +292,7 @@ __device__ __noinline__ void task_xupd(const Ctx<T>& cx_, const Task& t_) {
       }
     }
     if (sw) {
-      gemm_store<T>(acc, t.n, t.m, outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, (T)1), nullptr, pre);
+      gemm_store<T>(acc, t.n, t.m, outp<T>(cx.L + t.c_off, t.ldc, 1, (T)-1, beta), nullptr, pre);
       return;
     }
   } else if (!done) {

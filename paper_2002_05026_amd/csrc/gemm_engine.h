@@ -659,7 +659,7 @@ __device__ __forceinline__ void ge_pipe(Acc<T, TR>& acc, int m, int n, int nsrc,
       __syncthreads();
     }
     if constexpr (PRE) {
-      ge_preload<T>(*pre, m, n, *po);
+      if (po->src) ge_preload<T>(*pre, m, n, *po);
       slab(nsl - 1, nbjc);
       ge_wait_vm<0>();
       __syncthreads();

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <functional>
 #include <queue>
+#include <map>
 #include <set>
 #include <unordered_map>
 
@@ -447,11 +448,13 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
       orig.insert({pb, pa});
     }
   }
+  std::vector<std::pair<int, int>> fill_of;  // (row panel J, col panel I) of each fill block
   for (int I = 0; I < nb; ++I)
     for (int J : p.S[I])
       if (!orig.count({J, I})) {
         const Panel& P = p.panels[I];
         p.fills.push_back({P.off + prow_in[I][J], p.n[p.order[J]], P.n, P.H});
+        fill_of.push_back({J, I});
       }
 
   // ---- residual block rows (user numbering)
@@ -471,6 +474,9 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   GenDag g;
   std::vector<std::vector<Access>> facc;
   std::unordered_map<int64_t, int> lastw;  // storage tile -> last writer
+  // tiles of each fill block whose first writer stores its product (no K
+  // entries there to add it to), keyed by (row panel, col panel)
+  std::map<std::pair<int, int>, int> fill_first;
   auto lw = [&](int64_t k) { auto it = lastw.find(k); return it == lastw.end() ? -1 : it->second; };
   const int64_t kDKey = 1LL << 61;
   auto inv_key = [](int64_t a, int64_t b) { return (1LL << 59) | (a << 20) | b; };
@@ -663,6 +669,10 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
               PendUpd pu;
               pu.t = t;
               pu.pr = {lw(tk)};
+              if (pu.pr[0] < 0 && u != v && !orig.count({BJ.J, BK.J})) {
+                pu.t.aux |= 2;  // the tile's first update, in a fill block: store, not add
+                ++fill_first[{BJ.J, BK.J}];
+              }
               pu.ac = {{tk, true}};
               pu.w = 22.0;
               it = pend.emplace(tk, std::move(pu)).first;
@@ -689,6 +699,21 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
   }
   finalize(g, p.nworkers, sched, p.fdag);
   if (g.t.size() <= 40000) p.facc = std::move(facc);
+  // a fill block every tile of which is first written by an update that
+  // stores its product needs no zeroing; only its padding row (after an odd
+  // last row, read with it as a row pair) does, zeroed with the row before
+  // it as one aligned pair (that row's value is stored by its update later)
+  {
+    std::vector<PlanImpl::FillPlace> keep;
+    for (size_t f = 0; f < p.fills.size(); ++f) {
+      const auto& F = p.fills[f];
+      const auto it = fill_first.find(fill_of[f]);
+      const int ntile = p.panels[fill_of[f].first].nt * p.panels[fill_of[f].second].nt;
+      if (it == fill_first.end() || it->second < ntile) keep.push_back(F);
+      else if (F.rows & 1) keep.push_back({F.dst + F.rows - 1, 2, F.cols, F.ld_dst});
+    }
+    p.fills = std::move(keep);
+  }
 
   // ---- solve DAG: forward (elimination order), then backward (reverse).
   // W holds b (then x), Z holds z = D^-1 L^-1 b (then t); the diagonal
