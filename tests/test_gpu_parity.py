@@ -382,3 +382,28 @@ def test_fp64_fallback_recovers_a_pivot_fp32_cannot_carry():
     assert err["fallback"] <= 1e-6, err   # FP64 elimination of exact entries, stored in complex64
     assert err["plain"] >= 0.5, err       # FP32 elimination: the pivot is wrong in its leading digit
     assert 10 * st["pivot"]["eta_hist"][0] <= min(st["fallback"]["eta_hist"][0], st["plain"]["eta_hist"][0]), st
+
+
+@pytest.mark.parametrize("precision,tile", [(0, 16), (0, 0), (1, 32)])
+def test_refactorize_with_a_new_K_matches_oracle(precision, tile):
+    """A factor used again on a second K of the same structure: the fill-in
+    blocks of L (not in K, stored by the first update of each of their tiles,
+    not zeroed) must not keep anything of the first factorization."""
+    d3m = _d3m()
+    a = gen.make_instance((3, 3, 2), 40, gen.COEF_PLAIN, 2, 7)
+    b = gen.make_instance((3, 3, 2), 40, gen.COEF_PLAIN, 2, 8)
+    assert np.array_equal(a.sizes, b.sizes) and np.array_equal(a.pairs, b.pairs)
+    print(f"[case] refactorize N={a.N} prec={precision} tile={tile}", flush=True)
+    plan = d3m.Plan(a.sizes, a.pairs, grid=a.grid, tile=tile)
+    assert plan.info["fill_blocks"] > 0
+    f = d3m.Factor(plan, precision, nrhs_max=2)
+    f.factorize(torch.from_numpy(a.K).cuda())
+    f.factorize(torch.from_numpy(b.K).cuda())
+    X = f.solve(torch.from_numpy(np.ascontiguousarray(b.B)).cuda()).cpu().numpy()
+    st = f.status()
+    assert st["status"] == 0, st
+    order = oracle.nd_order(b.grid)
+    _, Xo = _oracle_solution(b, order, b.B)
+    eta = oracle.backward_error(b.sizes, b.pairs, b.K, X, b.B)
+    assert eta.max() <= (1e-12 if precision == 0 else 1e-10)
+    assert _fwd_err(X, Xo) <= (1e-10 if precision == 0 else 1e-8)
