@@ -42,6 +42,9 @@ constexpr int kMergeSolve = 1;
 // Forward solve updates from source panels at least this wide are cut into
 // two tasks over column halves of the panel.
 constexpr int kSolveKSplitMin = 256;
+// Plans of at least this many interfaces stop merging update sources in the
+// last eighth of the elimination order (the chain of the tree's top panels).
+constexpr int kChainMin = 64;
 
 // One task, in ticket order.  Offsets are in complex elements, relative to
 // the instance's base pointers (panel storage L, solve vector W).

@@ -665,6 +665,17 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
             t.c_off = PK.off + rowJinK + TR.r0 + (int64_t)TS.r0 * PK.H;
             int64_t tk = key3(BK.J, PJ.tile0 + r, s2);
             auto it = pend.find(tk);
+            // in the last eighth of the order (the dense top of the tree,
+            // whose panels form a chain) a source is not merged behind
+            // earlier ones: their product runs while this panel is still
+            // being factored, and the target waits for this panel's only.
+            // Plans of fewer than kChainMin interfaces keep merging: their
+            // chains are short, and in a batch other instances fill the time
+            if (it != pend.end() && nb >= kChainMin && 8 * I >= 7 * nb) {
+              emit_upd(tk, it->second);
+              pend.erase(it);
+              it = pend.end();
+            }
             if (it == pend.end()) {
               PendUpd pu;
               pu.t = t;

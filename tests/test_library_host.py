@@ -44,7 +44,9 @@ def test_analysis_matches_oracle_and_closed_forms(g, n):
 
 
 @pytest.mark.parametrize("g,lo,hi,tile", [((2, 2, 1), 48, 48, 16), ((2, 2, 2), 20, 70, 16), ((3, 3, 2), 5, 60, 16),
-                                          ((4, 4, 2), 20, 90, 32), ((3, 3, 2), 100, 300, 64)])
+                                          ((4, 4, 2), 20, 90, 32), ((3, 3, 2), 100, 300, 64),
+                                          # 144 interfaces: the top of the tree takes unmerged updates
+                                          ((4, 4, 4), 5, 20, 16)])
 def test_task_dags_are_race_free(g, lo, hi, tile):
     inst = gen.make_instance(g, (lo, hi), gen.COEF_PLAIN, 1, 9)
     for sched in (0, 1):
