@@ -43,7 +43,7 @@ constexpr int kMergeSolve = 1;
 // two tasks over column halves of the panel.
 constexpr int kSolveKSplitMin = 256;
 // Plans of at least this many interfaces stop merging update sources in the
-// last eighth of the elimination order (the chain of the tree's top panels).
+// last sixteenth of the elimination order (the chain of the tree's top panels).
 constexpr int kChainMin = 64;
 
 // One task, in ticket order.  Offsets are in complex elements, relative to

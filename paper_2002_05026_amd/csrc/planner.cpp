@@ -665,13 +665,15 @@ std::string build_plan(PlanImpl& p, int nb, const int32_t* sizes, int64_t npair,
             t.c_off = PK.off + rowJinK + TR.r0 + (int64_t)TS.r0 * PK.H;
             int64_t tk = key3(BK.J, PJ.tile0 + r, s2);
             auto it = pend.find(tk);
-            // in the last eighth of the order (the dense top of the tree,
+            // in the last sixteenth of the order (the dense top of the tree,
             // whose panels form a chain) a source is not merged behind
             // earlier ones: their product runs while this panel is still
-            // being factored, and the target waits for this panel's only.
-            // Plans of fewer than kChainMin interfaces keep merging: their
-            // chains are short, and in a batch other instances fill the time
-            if (it != pend.end() && nb >= kChainMin && 8 * I >= 7 * nb) {
+            // being factored, and the target waits for this panel's only
+            // (measured: the last eighth, quarter or half do less well, the
+            // last 24th or 32nd about as well).  Plans of fewer than
+            // kChainMin interfaces keep merging: their chains are short, and
+            // in a batch other instances fill the time
+            if (it != pend.end() && nb >= kChainMin && 16 * I >= 15 * nb) {
               emit_upd(tk, it->second);
               pend.erase(it);
               it = pend.end();
