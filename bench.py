@@ -30,8 +30,8 @@ PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
 # rocprofv3 --pmc runs (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after the plain-copy
 # calibration) recorded in profiles/k_dag_factor_c64_precision_4x4x4.md, valid
 # only for the kernel and planner sources they were taken with.
-TRAFFIC_BYTES = 223.51e9
-TRAFFIC_SRC_HASH = "7d2e65b2456b1b12"
+TRAFFIC_BYTES = 224.17e9
+TRAFFIC_SRC_HASH = "7253c2f3bbc4ebd2"
 KERNEL_SOURCES = tuple("paper_2002_05026_amd/csrc/" + f for f in (
     "dag_kernels.hip", "gemm_engine.h", "tile_ldlt.h", "tile_bk.h", "solve_mv.h", "launch.h", "d3m_internal.h",
     "planner.cpp"))
