@@ -31,7 +31,7 @@ PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
 # calibration) recorded in profiles/k_dag_factor_c64_precision_4x4x4.md, valid
 # only for the kernel and planner sources they were taken with.
 TRAFFIC_BYTES = 224.17e9
-TRAFFIC_SRC_HASH = "7253c2f3bbc4ebd2"
+TRAFFIC_SRC_HASH = "40f35fbe27a62e7d"
 KERNEL_SOURCES = tuple("paper_2002_05026_amd/csrc/" + f for f in (
     "dag_kernels.hip", "gemm_engine.h", "tile_ldlt.h", "tile_bk.h", "solve_mv.h", "launch.h", "d3m_internal.h",
     "planner.cpp"))

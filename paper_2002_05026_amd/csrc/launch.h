@@ -84,7 +84,8 @@ hipError_t launch_reset(int32_t* counters, const int32_t* init, int n, int32_t* 
 
 hipError_t launch_prepare(int32_t* status, float* growth, int npanel, IrCtrl* ctrl, double tol, int max_iter,
                           hipStream_t s);
-// K into panel storage in the factor's precision, fill blocks zeroed, and the
+// K into panel storage in the factor's precision, the listed zero blocks
+// (fill blocks no update stores into, padding row pairs) zeroed, and the
 // |k| sums of every placed tile into part (for launch_knorm)
 hipError_t launch_scatter(const void* K, void* L, const KPlaceDev* kp, int nkp, const KPlaceDev* fills,
                           int nfill, double* part, int prec, hipStream_t s);

@@ -52,7 +52,10 @@ struct PlanImpl {
   struct KPlace { int64_t src, dst; int32_t rows, cols, ld_dst, trans, ri = 0, ci = 0; };
   std::vector<KPlace> kplace;                 // K blocks -> panel storage
   struct FillPlace { int64_t dst; int32_t rows, cols, ld_dst; };
-  std::vector<FillPlace> fills;               // blocks of L that start at zero
+  // regions of L the scatter zeroes: fill blocks whose tiles are not all
+  // first written by an update that stores its product, and the padding
+  // row pairs of the others
+  std::vector<FillPlace> fills;
   // residual row blocks: for each interface (user id), the K blocks of its block row
   struct RBlk { int64_t koff; int32_t J; int32_t mode; };  // mode 0 diag(sym), 1 K_IJ, 2 K_JI^T
   std::vector<std::vector<RBlk>> rrow;

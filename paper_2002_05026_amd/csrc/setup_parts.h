@@ -36,7 +36,8 @@ __device__ __forceinline__ void prepare_part(int32_t* status, float* growth, int
 }
 
 // Scatter/convert of one block of K into the factor storage: b indexes the
-// K placements first, then the fill blocks (zeroed); 32x32 tiles of a K
+// K placements first, then the blocks to zero (fill blocks that no update
+// stores into, and the padding row pairs of the others); 32x32 tiles of a K
 // block (the elements of a fill block) are spread over the bx-th of gx
 // workgroups (256 threads).  Transposed blocks go through LDS.  Every tile
 // also leaves its |k| row and column sums in part (the input of ||K||_inf,
